@@ -1,0 +1,238 @@
+"""ctypes front end of the FP64 CPU oracle (gsoracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.  It shares no code
+with the HIP library; inputs are the float32 arrays of the seeded generators.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gsoracle.cpp")
+LIB = os.path.join(HERE, "libgsoracle.so")
+
+GROUPS = ("opacity", "sh_dc", "sh_rest", "mean", "log_scale", "quat")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP contraction off, OpenMP)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-fopenmp", "-ffp-contract=off", "-std=c++17",
+                               "-shared", "-fPIC", "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i64, i32, u32, dbl, flt = ctypes.c_int64, ctypes.c_int, ctypes.c_uint32, ctypes.c_double, ctypes.c_float
+        params = [P, P, P, P, P, i64, i32]
+        L.or_sh_basis.argtypes = [i32, P, P, P]
+        L.or_project.argtypes = params + [P, i32, P, P, P, P]
+        L.or_tile_lists.argtypes = params + [P, i32, i32, i32, P, i64, P]
+        L.or_tile_lists.restype = i64
+        L.or_render.argtypes = params + [P, i32, P, i32, i32, P, P, P, P]
+        L.or_render_alternatives.argtypes = params + [P, i32, P, P, i32, P, P]
+        L.or_backward.argtypes = params + [P, i32, P, P, i32, i32, dbl, P, P, P, P, P]
+        L.or_adam.argtypes = [P, P, P, P, i64, flt, flt, flt, flt, i32, P, P, P]
+        L.or_delta.argtypes = [P, P, P, i64, u32, flt, P]
+        L.or_delta.restype = i64
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _scene_args(scene):
+    arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in
+            (scene.mean, scene.log_scale, scene.quat, scene.opacity_logit, scene.sh)]
+    return arrs, [_p(a) for a in arrs] + [ctypes.c_int64(scene.n), ctypes.c_int(scene.sh_degree)]
+
+
+def n_params(sh_degree: int) -> int:
+    return 11 + 3 * (sh_degree + 1) ** 2
+
+
+def sh_basis(deg: int, d):
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    nk = (deg + 1) ** 2
+    Y = np.zeros(16)
+    dY = np.zeros(48)
+    lib().or_sh_basis(deg, _p(d), _p(Y), _p(dY))
+    return Y[:nk], dY[:nk * 3].reshape(nk, 3)
+
+
+@dataclass
+class Projection:
+    visible: np.ndarray   # [V, N] bool
+    zbits: np.ndarray     # [V, N] uint32
+    rec: np.ndarray       # [V, N, 16] u,w,A,B,C,a,b,c,o,r,g,b,pre_r,pre_g,pre_b,z
+    rect: np.ndarray      # [V, N, 4] px0,py0,px1,py1
+
+
+def project(scene, cams) -> Projection:
+    cams = np.ascontiguousarray(cams)
+    V, N = len(cams), scene.n
+    vis = np.zeros(V * N, np.uint8)
+    zb = np.zeros(V * N, np.uint32)
+    rec = np.zeros(V * N * 16, np.float64)
+    rect = np.zeros(V * N * 4, np.int32)
+    keep, args = _scene_args(scene)
+    lib().or_project(*args, _p(cams), V, _p(vis), _p(zb), _p(rec), _p(rect))
+    return Projection(vis.reshape(V, N).astype(bool), zb.reshape(V, N), rec.reshape(V, N, 16), rect.reshape(V, N, 4))
+
+
+def tile_layout(cams, tile_w: int, tile_h: int):
+    tiles = [((int(c["width"]) + tile_w - 1) // tile_w) * ((int(c["height"]) + tile_h - 1) // tile_h) for c in cams]
+    base = np.concatenate([[0], np.cumsum(tiles)]).astype(np.int64)
+    return base
+
+
+def tile_lists(scene, cams, tile_w: int, tile_h: int | None = None):
+    """(values [K] uint32 = v*N+i, ranges [tiles, 2] uint32)."""
+    tile_h = tile_h or tile_w
+    cams = np.ascontiguousarray(cams)
+    base = tile_layout(cams, tile_w, tile_h)
+    ranges = np.zeros(int(base[-1]) * 2, np.uint32)
+    keep, args = _scene_args(scene)
+    K = lib().or_tile_lists(*args, _p(cams), len(cams), tile_w, tile_h, None, 0, _p(ranges))
+    vals = np.zeros(max(K, 1), np.uint32)
+    K = lib().or_tile_lists(*args, _p(cams), len(cams), tile_w, tile_h, _p(vals), K, _p(ranges))
+    return vals[:K], ranges.reshape(-1, 2)
+
+
+def pixel_offsets(cams):
+    hw = [int(c["width"]) * int(c["height"]) for c in cams]
+    return np.concatenate([[0], np.cumsum(hw)]).astype(np.int64)
+
+
+@dataclass
+class Render:
+    image: np.ndarray     # [3*P] planar per view (views packed)
+    T: np.ndarray         # [P]
+    n_contrib: np.ndarray # [P]
+    flags: np.ndarray     # [P] near-threshold decisions met
+
+    def view_image(self, cams, v):
+        off = pixel_offsets(cams)
+        H, W = int(cams[v]["height"]), int(cams[v]["width"])
+        return self.image[3 * off[v]: 3 * off[v + 1]].reshape(3, H, W)
+
+
+def render(scene, cams, bg=(0.0, 0.0, 0.0), rows=None) -> Render:
+    cams = np.ascontiguousarray(cams)
+    P = int(pixel_offsets(cams)[-1])
+    img = np.zeros(3 * P)
+    T = np.ones(P)
+    nc = np.zeros(P, np.int32)
+    fl = np.zeros(P, np.int32)
+    bgv = np.asarray(bg, np.float64)
+    r0, r1 = (0, 0) if rows is None else rows
+    keep, args = _scene_args(scene)
+    lib().or_render(*args, _p(cams), len(cams), _p(bgv), r0, r1, _p(img), _p(T), _p(nc), _p(fl))
+    return Render(img, T, nc, fl)
+
+
+def render_alternatives(scene, cams, view: int, pix_xy, bg=(0.0, 0.0, 0.0)):
+    """For each (x, y): array [k, 5] of (r, g, b, T, n) over the outcomes of
+    the pixel's near-threshold decisions (row 0 is the primary outcome)."""
+    cams = np.ascontiguousarray(cams)
+    pix = np.ascontiguousarray(np.asarray(pix_xy, np.int32).reshape(-1, 2))
+    out = np.zeros(len(pix) * 16 * 5)
+    cnt = np.zeros(len(pix), np.int32)
+    bgv = np.asarray(bg, np.float64)
+    keep, args = _scene_args(scene)
+    lib().or_render_alternatives(*args, _p(cams), view, _p(bgv), _p(pix), len(pix), _p(out), _p(cnt))
+    out = out.reshape(len(pix), 16, 5)
+    return [out[q, :cnt[q]] for q in range(len(pix))]
+
+
+@dataclass
+class Backward:
+    grad: np.ndarray      # [nparam, N]
+    scale: np.ndarray     # [nparam, N]  |J|^T sum |2D terms|
+    slack: np.ndarray     # [nparam, N]  branch / sign-ambiguity allowance
+    loss: float
+    image: np.ndarray     # primary image [3*P]
+
+    def split(self, arr, sh_degree):
+        """Split an [nparam, N] array into the parameter tensors."""
+        return {"mean": arr[0:3], "log_scale": arr[3:6], "quat": arr[6:10],
+                "opacity_logit": arr[10], "sh": arr[11:]}
+
+
+def backward(scene, cams, upstream, mode: int, loss_mode: int = 0, bg=(0.0, 0.0, 0.0),
+             kink: float = 2e-5) -> Backward:
+    """mode 0: `upstream` is dL/dimage; mode 1: L1 against target `upstream`
+    (loss_mode 0 = sum over pixels, 1 = mean per view, summed over views)."""
+    cams = np.ascontiguousarray(cams)
+    npar = n_params(scene.sh_degree)
+    N = scene.n
+    P = int(pixel_offsets(cams)[-1])
+    up = np.ascontiguousarray(upstream, dtype=np.float32).reshape(-1)
+    assert up.shape[0] == 3 * P
+    g = np.zeros(npar * N)
+    s = np.zeros(npar * N)
+    k = np.zeros(npar * N)
+    loss = np.zeros(1)
+    img = np.zeros(3 * P)
+    bgv = np.asarray(bg, np.float64)
+    keep, args = _scene_args(scene)
+    lib().or_backward(*args, _p(cams), len(cams), _p(bgv), _p(up), mode, loss_mode, float(kink),
+                      _p(g), _p(s), _p(k), _p(loss), _p(img))
+    return Backward(g.reshape(npar, N), s.reshape(npar, N), k.reshape(npar, N), float(loss[0]), img)
+
+
+def adam(theta, g, m, v, lr, beta1, beta2, eps, step):
+    """One Adam step on float32 arrays; returns FP64 (theta, m, v)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float32).reshape(-1) for a in (theta, g, m, v)]
+    n = arrs[0].shape[0]
+    to, mo, vo = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().or_adam(*[_p(a) for a in arrs], n, float(lr), float(beta1), float(beta2), float(eps), int(step),
+                  _p(to), _p(mo), _p(vo))
+    shp = np.shape(theta)
+    return to.reshape(shp), mo.reshape(shp), vo.reshape(shp)
+
+
+def group_arrays(scene):
+    """The six streamed attribute groups as ([width][N] float32 views)."""
+    n = scene.n
+    sh = scene.sh
+    return [scene.opacity_logit.reshape(1, n), sh[0:3], sh[3:], scene.mean, scene.log_scale, scene.quat]
+
+
+def delta_capacity_words(n: int, sh_degree: int, mask: int = 0x3F) -> int:
+    widths = [1, 3, 3 * ((sh_degree + 1) ** 2 - 1), 3, 3, 4]
+    return 6 + sum(n * (1 + w) for g, w in enumerate(widths) if (mask >> g) & 1)
+
+
+def delta(cur_scene, base_scene, mask: int = 0x3F, tau: float = 1e-3):
+    """Delta extraction; updates `base_scene` in place; returns the words."""
+    n = cur_scene.n
+    cur = [np.ascontiguousarray(a) for a in group_arrays(cur_scene)]
+    base = group_arrays(base_scene)
+    for b in base:
+        assert b.flags["C_CONTIGUOUS"] or b.size == 0
+    widths = np.array([a.shape[0] for a in cur], np.int32)
+    cp = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in cur])
+    bp = (ctypes.c_void_p * 6)(*[b.ctypes.data for b in base])
+    out = np.zeros(delta_capacity_words(n, cur_scene.sh_degree, mask), np.uint32)
+    w = lib().or_delta(cp, bp, _p(widths), n, mask, float(np.float32(tau)), _p(out))
+    return out[:w]
