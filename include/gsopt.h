@@ -1,0 +1,269 @@
+/*
+ * gsopt: MI355X (gfx950) library for the online 3D Gaussian Splatting
+ * optimize step and its streaming deltas.
+ *
+ * The method (Sec. 3.1, overview): the server repeatedly renders the current
+ * Gaussian model from reference viewpoints, optionally grouped as
+ * mini-batches, compares the result with the captured ground-truth images
+ * under the configured loss, and updates the trainable parameters (means,
+ * scales, quaternions, opacities, spherical-harmonic coefficients) with the
+ * configured learning rates.  The optimized parameters are those of prior
+ * 3DGS work (Sec. 3.2.3), i.e. EWA projection of each Gaussian and
+ * front-to-back alpha compositing of depth-sorted splats per tile.  Changed
+ * attributes are streamed as per-tensor deltas relative to the previously
+ * transmitted state (Sec. 3.5).
+ *
+ * Conventions shared by every call
+ *  - Every pointer named dev_* or inside gs_params is DEVICE memory owned by
+ *    the caller; the library never allocates, frees or retains caller
+ *    memory.  host_* pointers are host memory read during the call only.
+ *  - Parameters are planar FP32 ("SoA"): mean[3][n], log_scale[3][n],
+ *    quat[4][n] as (w,x,y,z), opacity_logit[n], sh[(D+1)^2*3][n] where row
+ *    (k*3 + channel) holds SH coefficient k of that colour channel.
+ *  - Every call enqueues asynchronously on the given stream and returns
+ *    after host-side validation; it never synchronises the device unless
+ *    its description says so.  A context is not thread-safe: use one per
+ *    stream.
+ *  - Errors: GS_ERR_INVALID for bad arguments (nothing is enqueued),
+ *    GS_ERR_HIP for a HIP launch/runtime failure, GS_ERR_CAPACITY when a
+ *    previous step reported key overflow and the plan was not enlarged,
+ *    GS_ERR_STALE for a graph launch whose bound arguments changed,
+ *    GS_ERR_UNSUPPORTED for an option outside the built kernels.
+ *    gs_last_error() returns a message for the last failing call.
+ */
+#ifndef GSOPT_H
+#define GSOPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GS_OK = 0,
+  GS_ERR_INVALID = -1,
+  GS_ERR_CAPACITY = -2,
+  GS_ERR_HIP = -3,
+  GS_ERR_UNSUPPORTED = -4,
+  GS_ERR_STALE = -5
+} gs_status;
+
+typedef struct gs_context* gs_ctx;
+
+/* Gaussian model tensors (device pointers, layout above). sh_degree 0..3. */
+typedef struct {
+  float* mean;
+  float* log_scale;
+  float* quat;
+  float* opacity_logit;
+  float* sh;
+  int32_t n;
+  int32_t sh_degree;
+} gs_params;
+
+/* Pinhole reference camera, OpenCV axes (x right, y down, z forward).
+ * A world point p maps to camera space x = R p + t (R row-major) and to
+ * pixel (fx x0/x2 + cx, fy x1/x2 + cy); pixel (i, j) samples at
+ * (i + 0.5, j + 0.5).  campos is the camera centre (for view-dependent
+ * colour).  84 bytes, 4-byte aligned. */
+typedef struct {
+  float R[9];
+  float t[3];
+  float campos[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} gs_camera;
+
+/* Rendering options fixed at plan time.
+ *  tile_w, tile_h : tile size in pixels, one of 8x8, 16x8, 16x16, 32x16, 32x32
+ *  batch_depth    : splat records staged in LDS per batch: 32, 64, 128 or 256
+ *  bg             : background colour added with the final transmittance
+ *  loss_mode      : L1 reduction, 0 = sum over pixels and channels,
+ *                   1 = mean per view (1/(3HW)), summed over views */
+typedef struct {
+  int32_t tile_w, tile_h;
+  int32_t batch_depth;
+  int32_t reserved0;
+  float bg[3];
+  int32_t loss_mode;
+} gs_render_opts;
+
+/* Adam hyper-parameters (torch.optim.Adam semantics, no weight decay).
+ * lr per parameter group: 0 mean, 1 log_scale, 2 quat, 3 opacity_logit,
+ * 4 SH DC (rows 0..2 of sh), 5 SH higher bands (rows 3..). */
+typedef struct {
+  float lr[6];
+  float beta1, beta2, eps;
+} gs_adam_hparams;
+
+/* Counters of the last step, read by gs_read_counters. */
+typedef struct {
+  int64_t visible;       /* visible (view, Gaussian) pairs */
+  int64_t keys;          /* (tile, Gaussian) keys needed */
+  int64_t key_capacity;  /* keys the plan can hold */
+  uint32_t overflow;     /* 1 if keys > key_capacity (outputs then invalid) */
+  uint32_t reserved;
+} gs_counters;
+
+/* ---- context ------------------------------------------------------------ */
+gs_status gs_create(int32_t hip_device, gs_ctx* out);
+gs_status gs_destroy(gs_ctx ctx);
+/* Message of the last failing call on ctx (valid until the next call). */
+const char* gs_last_error(gs_ctx ctx);
+
+/* Fixes the frame layout for n Gaussians and n_views cameras: per-view
+ * pixel and tile offsets (views concatenated in order, tiles row-major per
+ * view), kernel variants, and the workspace size for up to key_capacity
+ * (tile, Gaussian) keys.  Host-side only (a small library-owned device table
+ * of view sizes is uploaded synchronously).  *workspace_bytes receives the
+ * size of the caller-allocated workspace that every later call takes. */
+gs_status gs_plan(gs_ctx ctx, int32_t n, int32_t sh_degree, int32_t n_views,
+                  const gs_camera* host_cams, const gs_render_opts* opts,
+                  int64_t key_capacity, size_t* workspace_bytes);
+
+/* Layout of the current plan: pixel_offsets[n_views+1] (pixel index of each
+ * view's first pixel; images are planar CHW per view at 3*pixel_offsets[v])
+ * and tile_offsets[n_views+1].  Either pointer may be NULL. */
+gs_status gs_frame_layout(gs_ctx ctx, int64_t* pixel_offsets, int32_t* tile_offsets);
+
+/* Stage "project/cull" (Sec. 3.1 render of the model; lineage EWA projection)
+ * for views [view_begin, view_begin + view_count): per (view, Gaussian) the
+ * FP32 depth key, the near/non-finite/off-screen cull, the screen-space
+ * conic, the projected mean (as a float pair), opacity, SH colour and the
+ * tile rectangle of the 3-sigma box.  dev_cams holds all planned views. */
+gs_status gs_project(gs_ctx ctx, const gs_params* params, const gs_camera* dev_cams,
+                     int32_t view_begin, int32_t view_count, void* dev_workspace, hipStream_t stream);
+
+/* Stage "tile keys + sort + ranges": one key per (tile, visible Gaussian),
+ * ordered by (tile, FP32 depth bits, Gaussian index) with a radix sort, then
+ * [start, end) per tile.  Key count is data dependent: kernels are driven by
+ * device-side counts and set the overflow flag instead of writing past the
+ * plan's capacity. */
+gs_status gs_build_tile_lists(gs_ctx ctx, int32_t view_begin, int32_t view_count,
+                              void* dev_workspace, hipStream_t stream);
+
+/* Stage "composite": per pixel, front-to-back alpha compositing of its tile's
+ * list with the 3-sigma ellipse test, alpha = min(0.99, o e^P), skip below
+ * 1/255, stop once transmittance would fall below 1e-4.  Writes images
+ * (planar CHW per view at 3*pixel_offsets[v]), final transmittance and
+ * contributor count per pixel (at pixel_offsets[v]); keeps the last list
+ * position internally for the backward pass. */
+gs_status gs_composite(gs_ctx ctx, int32_t view_begin, int32_t view_count, void* dev_workspace,
+                       float* dev_images, float* dev_T_final, uint32_t* dev_n_contrib,
+                       hipStream_t stream);
+
+/* Stage "backward": walks each pixel's list back to front from its last
+ * composited entry, recomputing alphas and transmittance, accumulates the
+ * per-(view, Gaussian) screen-space gradient, then applies the projection
+ * chain rule and sums over the views of the call into grads.
+ *  mode 0: dev_upstream is dL/dimage (image layout);
+ *  mode 1: dev_upstream is the target image; L1 loss with the plan's
+ *          loss_mode; *dev_loss (device FP32) receives the loss of these views.
+ *  accumulate 0 writes grads, 1 adds to them.  dev_loss may be NULL in mode 0. */
+gs_status gs_backward(gs_ctx ctx, const gs_params* params, const gs_camera* dev_cams,
+                      int32_t view_begin, int32_t view_count, void* dev_workspace,
+                      const float* dev_images, const float* dev_T_final, const float* dev_upstream,
+                      int32_t mode, const gs_params* grads, int32_t accumulate, float* dev_loss,
+                      hipStream_t stream);
+
+/* Fused Adam over all parameter tensors (configured learning rates,
+ * Sec. 3.1).  *dev_step holds the number of steps taken so far; the update
+ * uses t = *dev_step + 1 and a following kernel stores t. */
+gs_status gs_adam_step(gs_ctx ctx, const gs_params* params, const gs_params* grads,
+                       const gs_params* m, const gs_params* v, int32_t* dev_step,
+                       const gs_adam_hparams* hp, hipStream_t stream);
+
+/* Changed-Gaussian delta (Sec. 3.5: per-attribute tensor deltas relative to
+ * the previously transmitted state, Gaussian-ID ordering).  Groups, in this
+ * order and bit position of group_mask: 0 opacity (1 value), 1 SH DC (3),
+ * 2 SH higher bands (3((D+1)^2-1)), 3 mean (3), 4 log_scale (3), 5 quat (4).
+ * Row i of a masked group is emitted when some element has
+ * fl32(|cur - base|) > fl32(rel_tau * |base|).  dev_out (uint32 words):
+ * [6 counts], then per group in order: count indices ascending, followed by
+ * count*width FP32 values row-major.  Emitted baseline rows are overwritten
+ * with the current values.  out_cap_words must be at least
+ * 6 + sum over masked groups of n*(1+width); otherwise GS_ERR_INVALID.
+ * Uses the plan's workspace (n must equal the planned n). */
+gs_status gs_delta_extract(gs_ctx ctx, const gs_params* cur, const gs_params* baseline,
+                           uint32_t group_mask, float rel_tau, uint32_t* dev_out,
+                           int64_t out_cap_words, void* dev_workspace, hipStream_t stream);
+
+/* Snapshot bookkeeping (Sec. 3.5): baseline := cur for every tensor and
+ * *dev_epoch += 1. */
+gs_status gs_delta_reset_baseline(gs_ctx ctx, const gs_params* cur, const gs_params* baseline,
+                                  uint32_t* dev_epoch, hipStream_t stream);
+
+/* Internal arrays of the current plan, for tests and tools (read-only use).
+ * Per (view, Gaussian) pair, indexed v*n + i:
+ *   GS_SEG_DEPTH   u32 FP32 depth-key bits (valid where COUNT > 0)
+ *   GS_SEG_COUNT   u32 tiles touched, 0 when culled
+ *   GS_SEG_RECT    4 x u16 tile rectangle (tx0, ty0, tx1, ty1), inclusive
+ *   GS_SEG_RECORD  12 x f32 splat record (u_hi, w_hi, u_lo, w_lo, a, r, s, o,
+ *                  red, green, blue, 0) with conic
+ *                  P = -1/2 (a (dx + r dy)^2 + s dy^2)
+ *   GS_SEG_GRAD2D  12 x f32, first 9 = dL/d(u, w, a, b, c, o, red, green, blue)
+ *                  where (a, b, c) is the conic [[a, b], [b, c]]
+ * Per key / tile / pixel:
+ *   GS_SEG_SORTED_VALUES  u32 v*n + i in (tile, depth, index) order for the
+ *                         tile lists last built over [view_begin, +view_count)
+ *   GS_SEG_RANGES         u32 pairs [start, end) per global tile
+ *   GS_SEG_LAST           u32 one past the last composited list position per pixel
+ * *offset and *bytes are byte offsets/sizes inside the workspace. */
+typedef enum {
+  GS_SEG_DEPTH = 0,
+  GS_SEG_COUNT = 1,
+  GS_SEG_RECT = 2,
+  GS_SEG_RECORD = 3,
+  GS_SEG_GRAD2D = 4,
+  GS_SEG_SORTED_VALUES = 5,
+  GS_SEG_RANGES = 6,
+  GS_SEG_LAST = 7
+} gs_segment;
+gs_status gs_workspace_segment(gs_ctx ctx, int32_t which, int32_t view_begin, int32_t view_count,
+                               size_t* offset, size_t* bytes);
+
+/* Synchronous: waits for `stream` and reads the counters of the last step. */
+gs_status gs_read_counters(gs_ctx ctx, const void* dev_workspace, hipStream_t stream, gs_counters* out);
+
+/* ---- whole optimize step ------------------------------------------------ */
+typedef struct {
+  gs_params params, grads, adam_m, adam_v;  /* same n and sh_degree */
+  const gs_camera* dev_cams;                /* all planned views */
+  const float* dev_target;                  /* target images, image layout */
+  float* dev_images;
+  float* dev_T_final;
+  uint32_t* dev_n_contrib;
+  float* dev_loss;                          /* 1 float */
+  int32_t* dev_step;                        /* Adam step counter */
+  void* dev_workspace;
+  gs_adam_hparams hp;
+  int32_t plain;        /* 0: batched (every stage covers all views in one launch);
+                           1: plain (the same kernels one view per launch) */
+  int32_t do_delta;     /* 1: run gs_delta_extract after Adam */
+  gs_params baseline;   /* delta baselines (if do_delta) */
+  uint32_t group_mask;
+  float rel_tau;
+  uint32_t* dev_delta_out;
+  int64_t delta_cap_words;
+} gs_step_args;
+
+/* Enqueues one optimize step: project, tile lists, composite, L1 backward
+ * (gradients summed over all views, Sec. 3.1 mini-batch), Adam, optional
+ * delta extraction. */
+gs_status gs_step(gs_ctx ctx, const gs_step_args* args, hipStream_t stream);
+
+/* Captures gs_step(args) (batched or plain) into a HIP graph owned by ctx.
+ * The stream must be a non-default stream. */
+gs_status gs_step_capture(gs_ctx ctx, const gs_step_args* args, hipStream_t stream);
+
+/* Replays the captured graph.  Returns GS_ERR_STALE without launching if any
+ * field of *args differs from the captured arguments or the plan changed. */
+gs_status gs_step_launch(gs_ctx ctx, const gs_step_args* args, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSOPT_H */

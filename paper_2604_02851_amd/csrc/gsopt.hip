@@ -1,0 +1,479 @@
+// Host side of the gsopt C ABI: validation, plan and workspace layout, stage
+// sequencing (batched and plain), graph capture and replay.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace gs;
+
+struct gs_context {
+  int device = 0;
+  std::string err;
+  Plan plan;
+  uint64_t plan_gen = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  gs_step_args captured{};
+  uint64_t graph_gen = 0;
+};
+
+namespace {
+
+gs_status fail(gs_ctx c, gs_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+gs_status fail(gs_ctx c, gs_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+gs_status hip_check(gs_ctx c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GS_OK;
+  return fail(c, GS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define GS_HIP(c, expr)                                   \
+  do {                                                    \
+    gs_status _s = hip_check((c), (expr), #expr);         \
+    if (_s != GS_OK) return _s;                           \
+  } while (0)
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool tile_ok(int w, int h) {
+  return (w == 8 && h == 8) || (w == 16 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 16) ||
+         (w == 32 && h == 32);
+}
+
+WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, int64_t cap) {
+  WsLayout L{};
+  const int64_t vn = n * nviews;
+  L.vn = vn;
+  L.cap = cap;
+  const int64_t maxsort = vn > cap ? vn : cap;
+  L.hist_blocks = cdiv(maxsort, kSortChunk);
+  L.dblocks = (int32_t)cdiv(n, 256);
+  int64_t maxscan = maxsort;
+  if (256 * L.hist_blocks > maxscan) maxscan = 256 * L.hist_blocks;
+  if (6ll * L.dblocks > maxscan) maxscan = 6ll * L.dblocks;
+  L.partial_len = cdiv(maxscan, kSortChunk) + 2;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = al(o + (bytes ? bytes : 1)); return at; };
+  L.counters = take(sizeof(Counters));
+  L.depth = take(4 * vn);
+  L.count = take(4 * vn);
+  L.rect = take(8 * vn);
+  L.rec = take(sizeof(float) * kRecFloats * vn);
+  L.g2 = take(sizeof(float) * kG2Stride * vn);
+  L.vis_a = take(4 * vn);
+  L.vis_b = take(4 * vn);
+  L.vkey_a = take(4 * vn);
+  L.vkey_b = take(4 * vn);
+  L.koff = take(4 * (vn + 1));
+  L.keys_a = take(4 * cap);
+  L.keys_b = take(4 * cap);
+  L.vals_a = take(4 * cap);
+  L.vals_b = take(4 * cap);
+  L.hist = take(4 * (256 * L.hist_blocks + 1));
+  L.partial = take(4 * L.partial_len);
+  L.ranges = take(8 * tiles);
+  L.last = take(4 * pixels);
+  L.dflags = take(n);
+  L.dcount = take(4 * (6ll * L.dblocks + 1));
+  L.dbase = take(4 * 16);
+  L.total = o;
+  return L;
+}
+
+gs_status check_params(gs_ctx c, const gs_params* p, const char* what) {
+  if (!p) return fail(c, GS_ERR_INVALID, "%s: null gs_params", what);
+  if (p->n != c->plan.n || p->sh_degree != c->plan.sh_degree)
+    return fail(c, GS_ERR_INVALID, "%s: n=%d sh_degree=%d differ from the plan (n=%d, sh_degree=%d)", what, p->n,
+                p->sh_degree, c->plan.n, c->plan.sh_degree);
+  if (p->n > 0 && (!p->mean || !p->log_scale || !p->quat || !p->opacity_logit || !p->sh))
+    return fail(c, GS_ERR_INVALID, "%s: null tensor pointer", what);
+  return GS_OK;
+}
+
+gs_status check_range(gs_ctx c, int v0, int nv, const void* ws, const char* what) {
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "%s: no plan (call gs_plan first)", what);
+  if (v0 < 0 || nv < 1 || v0 + nv > c->plan.n_views)
+    return fail(c, GS_ERR_INVALID, "%s: view range [%d, %d) outside [0, %d)", what, v0, v0 + nv, c->plan.n_views);
+  if (!ws) return fail(c, GS_ERR_INVALID, "%s: null workspace", what);
+  return GS_OK;
+}
+
+bool same_params(const gs_params& a, const gs_params& b) {
+  return a.mean == b.mean && a.log_scale == b.log_scale && a.quat == b.quat && a.opacity_logit == b.opacity_logit &&
+         a.sh == b.sh && a.n == b.n && a.sh_degree == b.sh_degree;
+}
+
+bool same_args(const gs_step_args& a, const gs_step_args& b) {
+  bool same = same_params(a.params, b.params) && same_params(a.grads, b.grads) && same_params(a.adam_m, b.adam_m) &&
+              same_params(a.adam_v, b.adam_v) && a.dev_cams == b.dev_cams && a.dev_target == b.dev_target &&
+              a.dev_images == b.dev_images && a.dev_T_final == b.dev_T_final && a.dev_n_contrib == b.dev_n_contrib &&
+              a.dev_loss == b.dev_loss && a.dev_step == b.dev_step && a.dev_workspace == b.dev_workspace &&
+              std::memcmp(&a.hp, &b.hp, sizeof(a.hp)) == 0 && a.plain == b.plain && a.do_delta == b.do_delta;
+  if (same && a.do_delta)
+    same = same_params(a.baseline, b.baseline) && a.group_mask == b.group_mask && a.rel_tau == b.rel_tau &&
+           a.dev_delta_out == b.dev_delta_out && a.delta_cap_words == b.delta_cap_words;
+  return same;
+}
+
+ParamPtrs ptrs(const gs_params* p) {
+  return ParamPtrs{p->mean, p->log_scale, p->quat, p->opacity_logit, p->sh, p->n, p->sh_degree};
+}
+
+}  // namespace
+
+extern "C" {
+
+gs_status gs_create(int32_t hip_device, gs_ctx* out) {
+  if (!out) return GS_ERR_INVALID;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count) return GS_ERR_INVALID;
+  if (hipSetDevice(hip_device) != hipSuccess) return GS_ERR_HIP;
+  gs_ctx c = new gs_context();
+  c->device = hip_device;
+  *out = c;
+  return GS_OK;
+}
+
+gs_status gs_destroy(gs_ctx c) {
+  if (!c) return GS_ERR_INVALID;
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->plan.d_views) (void)hipFree(c->plan.d_views);
+  if (c->plan.d_tile_view) (void)hipFree(c->plan.d_tile_view);
+  delete c;
+  return GS_OK;
+}
+
+const char* gs_last_error(gs_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+gs_status gs_plan(gs_ctx c, int32_t n, int32_t sh_degree, int32_t n_views, const gs_camera* cams,
+                  const gs_render_opts* opts, int64_t key_capacity, size_t* ws_bytes) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (n < 0) return fail(c, GS_ERR_INVALID, "gs_plan: n=%d < 0", n);
+  if (sh_degree < 0 || sh_degree > 3) return fail(c, GS_ERR_INVALID, "gs_plan: sh_degree=%d not in 0..3", sh_degree);
+  if (n_views < 1 || n_views > kMaxViews)
+    return fail(c, GS_ERR_INVALID, "gs_plan: n_views=%d not in 1..%d", n_views, kMaxViews);
+  if (!cams || !opts || !ws_bytes) return fail(c, GS_ERR_INVALID, "gs_plan: null argument");
+  if (!tile_ok(opts->tile_w, opts->tile_h))
+    return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: tile %dx%d not built", opts->tile_w, opts->tile_h);
+  const int bd = opts->batch_depth;
+  if (bd != 32 && bd != 64 && bd != 128 && bd != 256)
+    return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: batch_depth=%d not in {32,64,128,256}", bd);
+  if (opts->loss_mode != 0 && opts->loss_mode != 1)
+    return fail(c, GS_ERR_INVALID, "gs_plan: loss_mode=%d", opts->loss_mode);
+  if (key_capacity < 1 || key_capacity > (int64_t)0x7fffffff)
+    return fail(c, GS_ERR_INVALID, "gs_plan: key_capacity=%lld outside [1, 2^31)", (long long)key_capacity);
+  if ((int64_t)n * n_views >= (int64_t)0xffffffffll)
+    return fail(c, GS_ERR_INVALID, "gs_plan: n * n_views must stay below 2^32");
+  Plan pl;
+  pl.n = n;
+  pl.sh_degree = sh_degree;
+  pl.n_views = n_views;
+  pl.tile_w = opts->tile_w;
+  pl.tile_h = opts->tile_h;
+  pl.batch_depth = bd;
+  for (int k = 0; k < 3; ++k) pl.bg[k] = opts->bg[k];
+  pl.loss_mode = opts->loss_mode;
+  int64_t tiles = 0, pixels = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const gs_camera& cam = cams[v];
+    if (cam.width < 1 || cam.height < 1 || cam.width > 16384 || cam.height > 16384)
+      return fail(c, GS_ERR_INVALID, "gs_plan: view %d size %dx%d outside 1..16384", v, cam.width, cam.height);
+    if (!(cam.fx > 0.f) || !(cam.fy > 0.f) || !std::isfinite(cam.fx) || !std::isfinite(cam.fy))
+      return fail(c, GS_ERR_INVALID, "gs_plan: view %d focal lengths must be finite and positive", v);
+    ViewInfo& vi = pl.views[v];
+    vi.width = cam.width;
+    vi.height = cam.height;
+    vi.tiles_x = (cam.width + pl.tile_w - 1) / pl.tile_w;
+    vi.tiles_y = (cam.height + pl.tile_h - 1) / pl.tile_h;
+    vi.tile_base = (int32_t)tiles;
+    vi.pad = 0;
+    vi.pix_off = pixels;
+    tiles += (int64_t)vi.tiles_x * vi.tiles_y;
+    pixels += (int64_t)cam.width * cam.height;
+  }
+  if (tiles > 0x7fffffff) return fail(c, GS_ERR_INVALID, "gs_plan: too many tiles");
+  pl.total_tiles = (int32_t)tiles;
+  pl.total_pixels = pixels;
+  pl.cap = key_capacity;
+  pl.ws = make_layout(n, n_views, tiles, pixels, key_capacity);
+  // library-owned device tables
+  std::vector<int32_t> tv(tiles);
+  for (int v = 0; v < n_views; ++v) {
+    const int64_t b = pl.views[v].tile_base, e = b + (int64_t)pl.views[v].tiles_x * pl.views[v].tiles_y;
+    for (int64_t t = b; t < e; ++t) tv[t] = v;
+  }
+  GS_HIP(c, hipSetDevice(c->device));
+  if (c->plan.d_views) { (void)hipFree(c->plan.d_views); c->plan.d_views = nullptr; }
+  if (c->plan.d_tile_view) { (void)hipFree(c->plan.d_tile_view); c->plan.d_tile_view = nullptr; }
+  c->plan.valid = false;
+  GS_HIP(c, hipMalloc(&pl.d_views, sizeof(ViewInfo) * n_views));
+  GS_HIP(c, hipMalloc(&pl.d_tile_view, sizeof(int32_t) * (tiles > 0 ? tiles : 1)));
+  GS_HIP(c, hipMemcpy(pl.d_views, pl.views, sizeof(ViewInfo) * n_views, hipMemcpyHostToDevice));
+  GS_HIP(c, hipMemcpy(pl.d_tile_view, tv.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice));
+  pl.valid = true;
+  c->plan = pl;
+  c->plan_gen += 1;
+  *ws_bytes = pl.ws.total;
+  return GS_OK;
+}
+
+gs_status gs_frame_layout(gs_ctx c, int64_t* pix, int32_t* tiles) {
+  if (!c) return GS_ERR_INVALID;
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_frame_layout: no plan");
+  const Plan& pl = c->plan;
+  for (int v = 0; v <= pl.n_views; ++v) {
+    if (pix) pix[v] = v < pl.n_views ? pl.views[v].pix_off : pl.total_pixels;
+    if (tiles) tiles[v] = v < pl.n_views ? pl.views[v].tile_base : pl.total_tiles;
+  }
+  return GS_OK;
+}
+
+gs_status gs_project(gs_ctx c, const gs_params* params, const gs_camera* cams, int32_t v0, int32_t nv, void* ws,
+                     hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  gs_status s = check_range(c, v0, nv, ws, "gs_project");
+  if (s != GS_OK) return s;
+  if ((s = check_params(c, params, "gs_project")) != GS_OK) return s;
+  if (!cams) return fail(c, GS_ERR_INVALID, "gs_project: null cameras");
+  const Plan& pl = c->plan;
+  if (v0 == 0) {   // a new step starts: clear the sticky overflow flag
+    Counters* ctr = seg<Counters>(ws, pl.ws.counters);
+    GS_HIP(c, launch_fill_u32(&ctr->overflow, 0u, 1, st));
+  }
+  GS_HIP(c, launch_project(pl, ptrs(params), cams, v0, nv, ws, st));
+  return GS_OK;
+}
+
+gs_status gs_build_tile_lists(gs_ctx c, int32_t v0, int32_t nv, void* ws, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  gs_status s = check_range(c, v0, nv, ws, "gs_build_tile_lists");
+  if (s != GS_OK) return s;
+  GS_HIP(c, launch_tile_lists(c->plan, v0, nv, ws, st));
+  return GS_OK;
+}
+
+gs_status gs_composite(gs_ctx c, int32_t v0, int32_t nv, void* ws, float* img, float* T, uint32_t* nc,
+                       hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  gs_status s = check_range(c, v0, nv, ws, "gs_composite");
+  if (s != GS_OK) return s;
+  if (!img || !T || !nc) return fail(c, GS_ERR_INVALID, "gs_composite: null output");
+  GS_HIP(c, launch_composite(c->plan, v0, nv, ws, img, T, nc, st));
+  return GS_OK;
+}
+
+gs_status gs_backward(gs_ctx c, const gs_params* params, const gs_camera* cams, int32_t v0, int32_t nv, void* ws,
+                      const float* img, const float* T, const float* up, int32_t mode, const gs_params* grads,
+                      int32_t accumulate, float* loss, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  gs_status s = check_range(c, v0, nv, ws, "gs_backward");
+  if (s != GS_OK) return s;
+  if ((s = check_params(c, params, "gs_backward")) != GS_OK) return s;
+  if ((s = check_params(c, grads, "gs_backward(grads)")) != GS_OK) return s;
+  if (!cams || !img || !T || !up) return fail(c, GS_ERR_INVALID, "gs_backward: null input");
+  if (mode != 0 && mode != 1) return fail(c, GS_ERR_INVALID, "gs_backward: mode=%d", mode);
+  if (mode == 1 && !loss) return fail(c, GS_ERR_INVALID, "gs_backward: mode 1 needs a loss pointer");
+  if (accumulate != 0 && accumulate != 1) return fail(c, GS_ERR_INVALID, "gs_backward: accumulate=%d", accumulate);
+  const Plan& pl = c->plan;
+  GS_HIP(c, launch_composite_bwd(pl, v0, nv, ws, img, T, up, mode, loss, st));
+  GS_HIP(c, launch_project_bwd(pl, ptrs(params), cams, v0, nv, ws, *grads, accumulate, st));
+  return GS_OK;
+}
+
+gs_status gs_adam_step(gs_ctx c, const gs_params* p, const gs_params* g, const gs_params* m, const gs_params* v,
+                       int32_t* step, const gs_adam_hparams* hp, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!p || !g || !m || !v || !step || !hp) return fail(c, GS_ERR_INVALID, "gs_adam_step: null argument");
+  const gs_params* all[4] = {p, g, m, v};
+  for (int k = 0; k < 4; ++k) {
+    if (all[k]->n != p->n || all[k]->sh_degree != p->sh_degree)
+      return fail(c, GS_ERR_INVALID, "gs_adam_step: tensors disagree on n / sh_degree");
+    if (p->n > 0 && (!all[k]->mean || !all[k]->log_scale || !all[k]->quat || !all[k]->opacity_logit || !all[k]->sh))
+      return fail(c, GS_ERR_INVALID, "gs_adam_step: null tensor pointer");
+  }
+  if (p->sh_degree < 0 || p->sh_degree > 3) return fail(c, GS_ERR_INVALID, "gs_adam_step: sh_degree");
+  if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f && hp->eps >= 0.f))
+    return fail(c, GS_ERR_INVALID, "gs_adam_step: betas must lie in [0,1) and eps >= 0");
+  if (p->n == 0) return GS_OK;
+  GS_HIP(c, launch_adam(*p, *g, *m, *v, step, *hp, st));
+  return GS_OK;
+}
+
+gs_status gs_delta_extract(gs_ctx c, const gs_params* cur, const gs_params* base, uint32_t mask, float tau,
+                           uint32_t* out, int64_t cap_words, void* ws, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_delta_extract: no plan");
+  gs_status s;
+  if ((s = check_params(c, cur, "gs_delta_extract(cur)")) != GS_OK) return s;
+  if ((s = check_params(c, base, "gs_delta_extract(baseline)")) != GS_OK) return s;
+  if (!out || !ws) return fail(c, GS_ERR_INVALID, "gs_delta_extract: null output or workspace");
+  if (mask & ~0x3Fu) return fail(c, GS_ERR_INVALID, "gs_delta_extract: group_mask 0x%x has bits above 5", mask);
+  if (!(tau >= 0.f) || !std::isfinite(tau)) return fail(c, GS_ERR_INVALID, "gs_delta_extract: rel_tau must be >= 0");
+  const int64_t n = cur->n;
+  const int nk = (cur->sh_degree + 1) * (cur->sh_degree + 1);
+  const int widths[6] = {1, 3, 3 * (nk - 1), 3, 3, 4};
+  int64_t need = 6;
+  for (int g = 0; g < 6; ++g)
+    if ((mask >> g) & 1u) need += n * (1 + widths[g]);
+  if (cap_words < need)
+    return fail(c, GS_ERR_INVALID, "gs_delta_extract: out_cap_words=%lld < %lld", (long long)cap_words,
+                (long long)need);
+  if (need > (int64_t)0xffffffffll) return fail(c, GS_ERR_INVALID, "gs_delta_extract: output above 2^32 words");
+  GS_HIP(c, launch_delta(c->plan, *cur, *base, mask, tau, out, ws, st));
+  return GS_OK;
+}
+
+gs_status gs_delta_reset_baseline(gs_ctx c, const gs_params* cur, const gs_params* base, uint32_t* epoch,
+                                  hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!cur || !base || !epoch) return fail(c, GS_ERR_INVALID, "gs_delta_reset_baseline: null argument");
+  if (cur->n != base->n || cur->sh_degree != base->sh_degree || cur->sh_degree < 0 || cur->sh_degree > 3)
+    return fail(c, GS_ERR_INVALID, "gs_delta_reset_baseline: tensors disagree on n / sh_degree");
+  const size_t n = (size_t)cur->n;
+  const size_t nk = (size_t)(cur->sh_degree + 1) * (cur->sh_degree + 1);
+  if (n > 0) {
+    GS_HIP(c, hipMemcpyAsync(base->mean, cur->mean, 12 * n, hipMemcpyDeviceToDevice, st));
+    GS_HIP(c, hipMemcpyAsync(base->log_scale, cur->log_scale, 12 * n, hipMemcpyDeviceToDevice, st));
+    GS_HIP(c, hipMemcpyAsync(base->quat, cur->quat, 16 * n, hipMemcpyDeviceToDevice, st));
+    GS_HIP(c, hipMemcpyAsync(base->opacity_logit, cur->opacity_logit, 4 * n, hipMemcpyDeviceToDevice, st));
+    GS_HIP(c, hipMemcpyAsync(base->sh, cur->sh, 12 * nk * n, hipMemcpyDeviceToDevice, st));
+  }
+  GS_HIP(c, launch_epoch_bump(epoch, st));
+  return GS_OK;
+}
+
+gs_status gs_workspace_segment(gs_ctx c, int32_t which, int32_t v0, int32_t nv, size_t* offset, size_t* bytes) {
+  if (!c || !offset || !bytes) return GS_ERR_INVALID;
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_workspace_segment: no plan");
+  const Plan& pl = c->plan;
+  const WsLayout& L = pl.ws;
+  const size_t vn = (size_t)L.vn;
+  switch (which) {
+    case GS_SEG_DEPTH: *offset = L.depth; *bytes = 4 * vn; break;
+    case GS_SEG_COUNT: *offset = L.count; *bytes = 4 * vn; break;
+    case GS_SEG_RECT: *offset = L.rect; *bytes = 8 * vn; break;
+    case GS_SEG_RECORD: *offset = L.rec; *bytes = sizeof(float) * kRecFloats * vn; break;
+    case GS_SEG_GRAD2D: *offset = L.g2; *bytes = sizeof(float) * kG2Stride * vn; break;
+    case GS_SEG_SORTED_VALUES:
+      if (v0 < 0 || nv < 1 || v0 + nv > pl.n_views) return fail(c, GS_ERR_INVALID, "gs_workspace_segment: range");
+      *offset = sorted_values_in_b(pl, v0, nv) ? L.vals_b : L.vals_a;
+      *bytes = 4 * (size_t)L.cap;
+      break;
+    case GS_SEG_RANGES: *offset = L.ranges; *bytes = 8 * (size_t)pl.total_tiles; break;
+    case GS_SEG_LAST: *offset = L.last; *bytes = 4 * (size_t)pl.total_pixels; break;
+    default: return fail(c, GS_ERR_INVALID, "gs_workspace_segment: unknown segment %d", which);
+  }
+  return GS_OK;
+}
+
+gs_status gs_read_counters(gs_ctx c, const void* ws, hipStream_t st, gs_counters* out) {
+  if (!c || !ws || !out) return GS_ERR_INVALID;
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_read_counters: no plan");
+  GS_HIP(c, hipStreamSynchronize(st));
+  Counters h{};
+  GS_HIP(c, hipMemcpy(&h, seg<const char>(const_cast<void*>(ws), c->plan.ws.counters), sizeof(h),
+                      hipMemcpyDeviceToHost));
+  out->visible = h.nvis;
+  out->keys = h.keys;
+  out->key_capacity = c->plan.cap;
+  out->overflow = h.overflow;
+  out->reserved = 0;
+  return GS_OK;
+}
+
+static gs_status run_step(gs_ctx c, const gs_step_args* a, hipStream_t st) {
+  gs_status s;
+  const Plan& pl = c->plan;
+  if (!pl.valid) return fail(c, GS_ERR_INVALID, "gs_step: no plan");
+  if (!a->dev_cams || !a->dev_target || !a->dev_images || !a->dev_T_final || !a->dev_n_contrib || !a->dev_loss ||
+      !a->dev_step || !a->dev_workspace)
+    return fail(c, GS_ERR_INVALID, "gs_step: null pointer in arguments");
+  GS_HIP(c, launch_fill_u32(reinterpret_cast<uint32_t*>(a->dev_loss), 0u, 1, st));
+  const int V = pl.n_views;
+  const int nstep = a->plain ? V : 1;
+  const int per = a->plain ? 1 : V;
+  for (int k = 0; k < nstep; ++k) {
+    const int v0 = k * per;
+    if ((s = gs_project(c, &a->params, a->dev_cams, v0, per, a->dev_workspace, st)) != GS_OK) return s;
+    if ((s = gs_build_tile_lists(c, v0, per, a->dev_workspace, st)) != GS_OK) return s;
+    if ((s = gs_composite(c, v0, per, a->dev_workspace, a->dev_images, a->dev_T_final, a->dev_n_contrib, st)) !=
+        GS_OK)
+      return s;
+    if ((s = gs_backward(c, &a->params, a->dev_cams, v0, per, a->dev_workspace, a->dev_images, a->dev_T_final,
+                         a->dev_target, 1, &a->grads, k > 0 ? 1 : 0, a->dev_loss, st)) != GS_OK)
+      return s;
+  }
+  if ((s = gs_adam_step(c, &a->params, &a->grads, &a->adam_m, &a->adam_v, a->dev_step, &a->hp, st)) != GS_OK)
+    return s;
+  if (a->do_delta) {
+    if ((s = gs_delta_extract(c, &a->params, &a->baseline, a->group_mask, a->rel_tau, a->dev_delta_out,
+                              a->delta_cap_words, a->dev_workspace, st)) != GS_OK)
+      return s;
+  }
+  return GS_OK;
+}
+
+gs_status gs_step(gs_ctx c, const gs_step_args* a, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!a) return fail(c, GS_ERR_INVALID, "gs_step: null arguments");
+  return run_step(c, a, st);
+}
+
+gs_status gs_step_capture(gs_ctx c, const gs_step_args* a, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!a) return fail(c, GS_ERR_INVALID, "gs_step_capture: null arguments");
+  if (st == nullptr) return fail(c, GS_ERR_INVALID, "gs_step_capture: capture needs a non-default stream");
+  if (c->exec) { (void)hipGraphExecDestroy(c->exec); c->exec = nullptr; }
+  if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+  GS_HIP(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  gs_status s = run_step(c, a, st);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &g);
+  if (s != GS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  GS_HIP(c, e);
+  c->graph = g;
+  GS_HIP(c, hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+  c->captured = *a;
+  c->graph_gen = c->plan_gen;
+  return GS_OK;
+}
+
+gs_status gs_step_launch(gs_ctx c, const gs_step_args* a, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!a) return fail(c, GS_ERR_INVALID, "gs_step_launch: null arguments");
+  if (!c->exec) return fail(c, GS_ERR_INVALID, "gs_step_launch: nothing captured");
+  if (c->graph_gen != c->plan_gen || !same_args(*a, c->captured))
+    return fail(c, GS_ERR_STALE, "gs_step_launch: arguments or plan changed since capture");
+  GS_HIP(c, hipGraphLaunch(c->exec, st));
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Internal declarations shared by the gsopt HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/gsopt.h"
+
+namespace gs {
+
+constexpr int kMaxViews = 256;
+constexpr int kRecFloats = 12;    // splat record: 3 x float4
+constexpr int kG2Stride = 12;     // screen-space gradient slots per (view, Gaussian)
+constexpr int kSortBlock = 256;   // threads of the sort / scan kernels
+constexpr int kSortItems = 16;    // keys per thread per chunk
+constexpr int kSortChunk = kSortBlock * kSortItems;
+
+// Thresholds of the compositing rule, as FP32 values.
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr float kCutoff = -4.5f;
+constexpr float kNear = 0.2f;
+constexpr float kDilation = 0.3f;
+constexpr float kGuard = 1.3f;
+
+struct ViewInfo {
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_base;     // first global tile of the view
+  int32_t pad;
+  int64_t pix_off;       // first pixel of the view in the packed frame
+};
+
+// Device counters living at the start of the workspace.
+struct Counters {
+  uint32_t nvis;          // visible (view, Gaussian) pairs of the last project
+  uint32_t keys;          // keys needed by the last tile-list build
+  uint32_t overflow;      // set when keys > capacity
+  uint32_t key_cap;
+  uint32_t pad[4];
+};
+
+// Byte offsets of the workspace segments (computed by the host at plan time).
+struct WsLayout {
+  size_t counters;
+  size_t depth;       // u32 [VN]   FP32 depth key bits
+  size_t count;       // u32 [VN]   tiles touched (0 = culled)
+  size_t rect;        // u16x4 [VN] tile rectangle (tx0, ty0, tx1, ty1)
+  size_t rec;         // float4x3 [VN] splat record
+  size_t g2;          // float x12 [VN] screen-space gradients
+  size_t vis_a, vis_b, vkey_a, vkey_b;  // u32 [VN] visible ids / depth keys (sort ping-pong)
+  size_t koff;        // u32 [VN+1] key offsets in depth order
+  size_t keys_a, keys_b, vals_a, vals_b;  // u32 [cap]
+  size_t hist;        // u32 [256 * max_blocks + 1]
+  size_t partial;     // u32 [scan partials]
+  size_t ranges;      // u32x2 [tiles]
+  size_t last;        // u32 [pixels]
+  size_t dflags;      // u8 [n] delta flags
+  size_t dcount;      // u32 [6 * dblocks + 1] delta block counts (scanned in place)
+  size_t dbase;       // u32 [16] delta section bases
+  size_t total;
+  int64_t vn;
+  int64_t cap;
+  int64_t hist_blocks;
+  int64_t partial_len;
+  int32_t dblocks;
+};
+
+struct Plan {
+  int32_t n = 0, sh_degree = 0, n_views = 0;
+  int32_t tile_w = 16, tile_h = 16, batch_depth = 64;
+  float bg[3] = {0, 0, 0};
+  int32_t loss_mode = 0;
+  int32_t total_tiles = 0;
+  int64_t total_pixels = 0;
+  int64_t cap = 0;
+  ViewInfo views[kMaxViews];
+  WsLayout ws;
+  // library-owned device copies
+  ViewInfo* d_views = nullptr;
+  int32_t* d_tile_view = nullptr;
+  bool valid = false;
+};
+
+template <typename T>
+__host__ __device__ inline T* seg(void* ws, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
+
+// ---------------------------------------------------------------------------
+// Splat record: the projected quantities the compositing loops read.
+//   r0 = (u_hi, w_hi, u_lo, w_lo)   projected mean as a float pair
+//   r1 = (a, r, s, o)               conic in the form
+//        P = -1/2 (a (dx + r dy)^2 + s dy^2) with a = Q00, r = Q01/Q00,
+//        s = det(Q)/Q00 (= 1 / Sigma2_11); o = opacity
+//   r2 = (red, green, blue, 0)
+// ---------------------------------------------------------------------------
+struct SplatEval {
+  float dx, dy, e, P, G, alpha;
+  bool inside;    // passes the 3-sigma test and the 1/255 skip
+  bool clamped;   // alpha hit 0.99
+};
+
+// The one place that decides whether a pixel takes a splat; the forward and
+// backward kernels call it on identical inputs, so they make identical
+// decisions bit for bit.
+__device__ __forceinline__ SplatEval eval_splat(float pxc, float pyc, const float4& r0, const float4& r1) {
+#pragma clang fp contract(off)
+  SplatEval s;
+  s.dx = (pxc - r0.x) - r0.z;
+  s.dy = (pyc - r0.y) - r0.w;
+  s.e = fmaf(r1.y, s.dy, s.dx);
+  const float q = fmaf(r1.x * s.e, s.e, r1.z * (s.dy * s.dy));
+  s.P = -0.5f * q;
+  s.inside = false;
+  s.clamped = false;
+  s.G = 0.f;
+  s.alpha = 0.f;
+  if (s.P < kCutoff) return s;
+  s.G = __builtin_amdgcn_exp2f(s.P * 1.44269504088896341f);
+  const float oG = r1.w * s.G;
+  s.clamped = oG >= kAlphaMax;
+  s.alpha = s.clamped ? kAlphaMax : oG;
+  s.inside = s.alpha >= kAlphaMin;
+  return s;
+}
+
+// ---- launchers implemented in the .hip files -------------------------------
+struct ParamPtrs {
+  const float* mean;
+  const float* lsc;
+  const float* quat;
+  const float* opac;
+  const float* sh;
+  int32_t n, deg;
+};
+
+hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* cams, int v0, int nv, void* ws,
+                          hipStream_t st);
+hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camera* cams, int v0, int nv, void* ws,
+                              const gs_params& grads, int accumulate, hipStream_t st);
+hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream_t st);
+hipError_t launch_composite(const Plan& pl, int v0, int nv, void* ws, float* img, float* T, uint32_t* nc,
+                            hipStream_t st);
+hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const float* img, const float* T,
+                                const float* up, int mode, float* loss, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
+hipError_t launch_adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v,
+                       int32_t* step, const gs_adam_hparams& hp, hipStream_t st);
+hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& base, uint32_t mask, float tau,
+                        uint32_t* out, void* ws, hipStream_t st);
+hipError_t launch_epoch_bump(uint32_t* epoch, hipStream_t st);
+// whether the sorted tile lists of views [v0, v0+nv) end in the second buffer
+bool sorted_values_in_b(const Plan& pl, int v0, int nv);
+
+// exclusive scan of `count` u32 values (count read from *dcount when non-null,
+// capped at `max_count`); total written to *total when non-null.
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t max_count, const uint32_t* dcount,
+                       uint32_t* partial, int64_t partial_len, uint32_t* total, hipStream_t st);
+
+}  // namespace gs

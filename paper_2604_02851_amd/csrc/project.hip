@@ -1,0 +1,430 @@
+// Project/cull (forward) and the projection chain rule (backward).
+//
+// One thread per Gaussian loops over the views of the call, so the
+// parameters are read from HBM once per call, however many views it covers
+// (batched mode: all views of the step).  Geometry (camera-space mean,
+// covariance, screen-space conic, projected mean, tile rectangle) is
+// evaluated in FP64: the projected mean feeds every pixel test at up to
+// 1920 px, where FP32 leaves ~1e-4 px of error; FP64 costs little here
+// because this stage is a small part of the step.  Colour (SH) is FP32.
+#include "internal.h"
+
+namespace gs {
+namespace {
+
+// Real SH basis (orthonormal, (-1)^m sign), k = l*l + l + m, and its
+// gradient with respect to the direction (as polynomials in x, y, z).
+constexpr float Y00 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+constexpr float Y1 = 0.48860251190291992f;    // sqrt(3)/(2 sqrt(pi))
+constexpr float Y2a = 1.0925484305920792f;    // sqrt(15)/(2 sqrt(pi))
+constexpr float Y2b = 0.31539156525252005f;   // sqrt(5)/(4 sqrt(pi))
+constexpr float Y2c = 0.54627421529603959f;   // sqrt(15)/(4 sqrt(pi))
+constexpr float Y3a = 0.59004358992664352f;   // sqrt(35/2)/(4 sqrt(pi))
+constexpr float Y3b = 2.8906114426405538f;    // sqrt(105)/(2 sqrt(pi))
+constexpr float Y3c = 0.45704579946446572f;   // sqrt(21/2)/(4 sqrt(pi))
+constexpr float Y3d = 0.3731763325901154f;    // sqrt(7)/(4 sqrt(pi))
+constexpr float Y3e = 1.4453057213202769f;    // sqrt(105)/(4 sqrt(pi))
+
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
+  Y[0] = Y00;
+  if (deg >= 1) { Y[1] = -Y1 * y; Y[2] = Y1 * z; Y[3] = -Y1 * x; }
+  if (deg >= 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = Y2a * x * y;
+    Y[5] = -Y2a * y * z;
+    Y[6] = Y2b * (2.f * zz - xx - yy);
+    Y[7] = -Y2a * x * z;
+    Y[8] = Y2c * (xx - yy);
+    if (deg >= 3) {
+      Y[9] = -Y3a * y * (3.f * xx - yy);
+      Y[10] = Y3b * x * y * z;
+      Y[11] = -Y3c * y * (4.f * zz - xx - yy);
+      Y[12] = Y3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+      Y[13] = -Y3c * x * (4.f * zz - xx - yy);
+      Y[14] = Y3e * z * (xx - yy);
+      Y[15] = -Y3a * x * (xx - 3.f * yy);
+    }
+  }
+}
+
+// g += sum_k w[k] * grad Y_k(x, y, z)
+__device__ __forceinline__ void sh_grad_accum(int deg, float x, float y, float z, const float* w, float* g) {
+  if (deg < 1) return;
+  g[1] += -Y1 * w[1];
+  g[2] += Y1 * w[2];
+  g[0] += -Y1 * w[3];
+  if (deg < 2) return;
+  g[0] += Y2a * y * w[4];            g[1] += Y2a * x * w[4];
+  g[1] += -Y2a * z * w[5];           g[2] += -Y2a * y * w[5];
+  g[0] += -2.f * Y2b * x * w[6];     g[1] += -2.f * Y2b * y * w[6];  g[2] += 4.f * Y2b * z * w[6];
+  g[0] += -Y2a * z * w[7];           g[2] += -Y2a * x * w[7];
+  g[0] += 2.f * Y2c * x * w[8];      g[1] += -2.f * Y2c * y * w[8];
+  if (deg < 3) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  g[0] += -6.f * Y3a * x * y * w[9];           g[1] += -3.f * Y3a * (xx - yy) * w[9];
+  g[0] += Y3b * y * z * w[10];                 g[1] += Y3b * x * z * w[10];       g[2] += Y3b * x * y * w[10];
+  g[0] += 2.f * Y3c * x * y * w[11];           g[1] += -Y3c * (4.f * zz - xx - 3.f * yy) * w[11];
+  g[2] += -8.f * Y3c * y * z * w[11];
+  g[0] += -6.f * Y3d * x * z * w[12];          g[1] += -6.f * Y3d * y * z * w[12];
+  g[2] += Y3d * (6.f * zz - 3.f * xx - 3.f * yy) * w[12];
+  g[0] += -Y3c * (4.f * zz - 3.f * xx - yy) * w[13];  g[1] += 2.f * Y3c * x * y * w[13];
+  g[2] += -8.f * Y3c * x * z * w[13];
+  g[0] += 2.f * Y3e * x * z * w[14];           g[1] += -2.f * Y3e * y * z * w[14]; g[2] += Y3e * (xx - yy) * w[14];
+  g[0] += -3.f * Y3a * (xx - yy) * w[15];      g[1] += 6.f * Y3a * x * y * w[15];
+}
+
+// FP32 camera depth evaluated in a fixed order with every operation rounded
+// on its own (no fused multiply-add), so that it equals the same expression
+// evaluated anywhere else in IEEE single precision.
+__device__ __noinline__ float depth_key(const gs_camera& c, float mx, float my, float mz) {
+#pragma clang fp contract(off)
+  float a = c.R[6] * mx;
+  float b = c.R[7] * my;
+  float s = a + b;
+  float d = c.R[8] * mz;
+  s = s + d;
+  return s + c.t[2];
+}
+
+struct Gauss {
+  float mu[3];
+  double Sig[6];   // world covariance (00, 01, 02, 11, 12, 22)
+  double Rq[9];    // rotation of the normalised quaternion
+  double rho[4], qn;
+  double e2[3];    // exp(2 s)
+  float o;
+  bool ok;
+};
+
+__device__ __forceinline__ void load_gauss(const ParamPtrs& p, int64_t i, Gauss& g) {
+  const int64_t n = p.n;
+  bool fin = true;
+  for (int k = 0; k < 3; ++k) {
+    g.mu[k] = p.mean[k * n + i];
+    fin &= isfinite(g.mu[k]);
+  }
+  float ls[3], q[4];
+  for (int k = 0; k < 3; ++k) { ls[k] = p.lsc[k * n + i]; fin &= isfinite(ls[k]); }
+  for (int k = 0; k < 4; ++k) { q[k] = p.quat[k * n + i]; fin &= isfinite(q[k]); }
+  const float w = p.opac[i];
+  fin &= isfinite(w);
+  const int nsh = 3 * (p.deg + 1) * (p.deg + 1);
+  for (int k = 0; k < nsh; ++k) fin &= isfinite(p.sh[k * n + i]);
+  const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  g.qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  g.ok = fin && g.qn > 0.0;
+  if (!g.ok) return;
+  const double a = qw / g.qn, b = qx / g.qn, c = qy / g.qn, d = qz / g.qn;
+  g.rho[0] = a; g.rho[1] = b; g.rho[2] = c; g.rho[3] = d;
+  double* R = g.Rq;
+  R[0] = 1 - 2 * (c * c + d * d); R[1] = 2 * (b * c - a * d);     R[2] = 2 * (b * d + a * c);
+  R[3] = 2 * (b * c + a * d);     R[4] = 1 - 2 * (b * b + d * d); R[5] = 2 * (c * d - a * b);
+  R[6] = 2 * (b * d - a * c);     R[7] = 2 * (c * d + a * b);     R[8] = 1 - 2 * (b * b + c * c);
+  for (int k = 0; k < 3; ++k) g.e2[k] = exp(2.0 * (double)ls[k]);
+  // Sigma = Rq diag(e2) Rq^T
+  const int idx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+  for (int t = 0; t < 6; ++t) {
+    const int r = idx[t][0], c2 = idx[t][1];
+    g.Sig[t] = R[r * 3 + 0] * g.e2[0] * R[c2 * 3 + 0] + R[r * 3 + 1] * g.e2[1] * R[c2 * 3 + 1] +
+               R[r * 3 + 2] * g.e2[2] * R[c2 * 3 + 2];
+  }
+  g.o = 1.f / (1.f + expf(-w));
+}
+
+// Per-view geometry of one Gaussian.
+struct ViewGeom {
+  double x[3];
+  double M[6];            // W Sigma W^T (00, 01, 02, 11, 12, 22)
+  double j00, j02, j11, j12;
+  bool clx, cly;
+  double A, B, C, det;
+  double u, w;
+};
+
+__device__ __forceinline__ bool view_geom(const Gauss& g, const gs_camera& cam, ViewGeom& vg) {
+  double W[9];
+  for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
+  for (int r = 0; r < 3; ++r)
+    vg.x[r] = W[r * 3] * (double)g.mu[0] + W[r * 3 + 1] * (double)g.mu[1] + W[r * 3 + 2] * (double)g.mu[2] +
+              (double)cam.t[r];
+  // T = W Sigma
+  const double S[9] = {g.Sig[0], g.Sig[1], g.Sig[2], g.Sig[1], g.Sig[3], g.Sig[4], g.Sig[2], g.Sig[4], g.Sig[5]};
+  double T[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) T[r * 3 + c] = W[r * 3] * S[c] + W[r * 3 + 1] * S[3 + c] + W[r * 3 + 2] * S[6 + c];
+  const int idx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+  for (int t = 0; t < 6; ++t) {
+    const int r = idx[t][0], c = idx[t][1];
+    vg.M[t] = T[r * 3] * W[c * 3] + T[r * 3 + 1] * W[c * 3 + 1] + T[r * 3 + 2] * W[c * 3 + 2];
+  }
+  const double fx = cam.fx, fy = cam.fy, z = vg.x[2];
+  const double limx = (double)kGuard * (0.5 * (double)cam.width) / fx;
+  const double limy = (double)kGuard * (0.5 * (double)cam.height) / fy;
+  double tx = vg.x[0] / z, ty = vg.x[1] / z;
+  vg.clx = tx < -limx || tx > limx;
+  vg.cly = ty < -limy || ty > limy;
+  tx = fmin(limx, fmax(-limx, tx));
+  ty = fmin(limy, fmax(-limy, ty));
+  vg.j00 = fx / z;
+  vg.j02 = -fx * tx / z;
+  vg.j11 = fy / z;
+  vg.j12 = -fy * ty / z;
+  const double M00 = vg.M[0], M01 = vg.M[1], M02 = vg.M[2], M11 = vg.M[3], M12 = vg.M[4], M22 = vg.M[5];
+  const double s00 = vg.j00 * vg.j00 * M00 + 2.0 * vg.j00 * vg.j02 * M02 + vg.j02 * vg.j02 * M22;
+  const double s01 = vg.j00 * vg.j11 * M01 + vg.j00 * vg.j12 * M02 + vg.j02 * vg.j11 * M12 + vg.j02 * vg.j12 * M22;
+  const double s11 = vg.j11 * vg.j11 * M11 + 2.0 * vg.j11 * vg.j12 * M12 + vg.j12 * vg.j12 * M22;
+  vg.A = s00 + (double)kDilation;
+  vg.B = s01;
+  vg.C = s11 + (double)kDilation;
+  vg.det = vg.A * vg.C - vg.B * vg.B;
+  vg.u = fx * vg.x[0] / z + (double)cam.cx;
+  vg.w = fy * vg.x[1] / z + (double)cam.cy;
+  return vg.det > 0.0 && isfinite(vg.det) && isfinite(vg.u) && isfinite(vg.w);
+}
+
+__device__ __forceinline__ void view_dir(const gs_camera& cam, const float* mu, float* d, float* len) {
+  const float vx = mu[0] - cam.campos[0], vy = mu[1] - cam.campos[1], vz = mu[2] - cam.campos[2];
+  const float l = sqrtf(vx * vx + vy * vy + vz * vz);
+  *len = l;
+  const float il = 1.f / l;
+  d[0] = vx * il; d[1] = vy * il; d[2] = vz * il;
+}
+
+struct ProjArgs {
+  ParamPtrs p;
+  const gs_camera* cams;
+  const ViewInfo* views;
+  int v0, nv, tile_w, tile_h;
+  uint32_t* depth;
+  uint32_t* count;
+  ushort4* rect;
+  float4* rec;
+  float4* g2;
+};
+
+__global__ __launch_bounds__(256) void k_project(ProjArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = a.p.n;
+  if (i >= n) return;
+  Gauss g;
+  load_gauss(a.p, i, g);
+  const int nk = (a.p.deg + 1) * (a.p.deg + 1);
+  for (int v = a.v0; v < a.v0 + a.nv; ++v) {
+    const int64_t o = (int64_t)v * n + i;
+    const gs_camera cam = a.cams[v];
+    uint32_t cnt = 0;
+    if (g.ok) {
+      const float z32 = depth_key(cam, g.mu[0], g.mu[1], g.mu[2]);
+      ViewGeom vg;
+      if (z32 >= kNear && view_geom(g, cam, vg)) {
+        const double slack = 1.0 + 0x1p-10;
+        const double hx = 3.0 * sqrt(vg.A) * slack, hy = 3.0 * sqrt(vg.C) * slack;
+        double lx = ceil(vg.u - hx - 0.5), ux = floor(vg.u + hx - 0.5);
+        double ly = ceil(vg.w - hy - 0.5), uy = floor(vg.w + hy - 0.5);
+        lx = fmax(lx, 0.0); ly = fmax(ly, 0.0);
+        ux = fmin(ux, (double)(cam.width - 1)); uy = fmin(uy, (double)(cam.height - 1));
+        if (lx <= ux && ly <= uy) {
+          const int tx0 = (int)lx / a.tile_w, tx1 = (int)ux / a.tile_w;
+          const int ty0 = (int)ly / a.tile_h, ty1 = (int)uy / a.tile_h;
+          cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+          a.rect[o] = make_ushort4((unsigned short)tx0, (unsigned short)ty0, (unsigned short)tx1, (unsigned short)ty1);
+          a.depth[o] = __float_as_uint(z32);
+          // splat record
+          const float uh = (float)vg.u, wh = (float)vg.w;
+          const float ul = (float)(vg.u - (double)uh), wl = (float)(vg.w - (double)wh);
+          const float qa = (float)(vg.C / vg.det);
+          const float qr = (float)(-vg.B / vg.C);
+          const float qs = (float)(1.0 / vg.C);
+          float d[3], len;
+          view_dir(cam, g.mu, d, &len);
+          float Y[16];
+          sh_basis(a.p.deg, d[0], d[1], d[2], Y);
+          float col[3];
+          for (int ch = 0; ch < 3; ++ch) {
+            float s = 0.5f;
+            for (int k = 0; k < nk; ++k) s = fmaf(a.p.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], s);
+            col[ch] = fmaxf(s, 0.f);
+          }
+          a.rec[o * 3 + 0] = make_float4(uh, wh, ul, wl);
+          a.rec[o * 3 + 1] = make_float4(qa, qr, qs, g.o);
+          a.rec[o * 3 + 2] = make_float4(col[0], col[1], col[2], 0.f);
+          const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+          a.g2[o * 3 + 0] = zero;
+          a.g2[o * 3 + 1] = zero;
+          a.g2[o * 3 + 2] = zero;
+        }
+      }
+    }
+    a.count[o] = cnt;
+  }
+}
+
+struct ProjBwdArgs {
+  ParamPtrs p;
+  const gs_camera* cams;
+  int v0, nv;
+  const uint32_t* count;
+  const float4* g2;
+  float* gmean; float* glsc; float* gquat; float* gopac; float* gsh;
+  int accumulate;
+};
+
+__global__ __launch_bounds__(128) void k_project_bwd(ProjBwdArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = a.p.n;
+  if (i >= n) return;
+  Gauss g;
+  load_gauss(a.p, i, g);
+  const int nk = (a.p.deg + 1) * (a.p.deg + 1);
+  double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
+  float gsh[48];
+  for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+  for (int v = a.v0; v < a.v0 + a.nv && g.ok; ++v) {
+    const int64_t o = (int64_t)v * n + i;
+    if (a.count[o] == 0) continue;
+    const float4 t0 = a.g2[o * 3 + 0], t1 = a.g2[o * 3 + 1], t2 = a.g2[o * 3 + 2];
+    const double gu = t0.x, gw = t0.y, ga = t0.z, gb = t0.w, gc = t1.x, gop = t1.y;
+    const float gcol[3] = {t1.z, t1.w, t2.x};
+    const gs_camera cam = a.cams[v];
+    ViewGeom vg;
+    view_geom(g, cam, vg);
+    // opacity
+    go += gop * (double)g.o * (1.0 - (double)g.o);
+    // colour -> SH coefficients and view direction
+    float d[3], len;
+    view_dir(cam, g.mu, d, &len);
+    float Y[16];
+    sh_basis(a.p.deg, d[0], d[1], d[2], Y);
+    float wk[16];
+    for (int k = 0; k < 16; ++k) wk[k] = 0.f;
+    for (int ch = 0; ch < 3; ++ch) {
+      float s = 0.5f;
+      for (int k = 0; k < nk; ++k) s = fmaf(a.p.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], s);
+      const float gcc = s > 0.f ? gcol[ch] : 0.f;
+      for (int k = 0; k < nk; ++k) {
+        gsh[k * 3 + ch] += Y[k] * gcc;
+        wk[k] += gcc * a.p.sh[(int64_t)(k * 3 + ch) * n + i];
+      }
+    }
+    float gd[3] = {0.f, 0.f, 0.f};
+    sh_grad_accum(a.p.deg, d[0], d[1], d[2], wk, gd);
+    const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+    for (int k = 0; k < 3; ++k) gm[k] += (double)((gd[k] - d[k] * dd) / len);
+    // conic -> screen covariance: dL/dSigma2 = -Q G_Q Q
+    const double qa = vg.C / vg.det, qb = -vg.B / vg.det, qc = vg.A / vg.det;
+    const double S00 = -(qa * qa * ga + qa * qb * gb + qb * qb * gc);
+    const double S01 = -(qa * qb * ga + 0.5 * (qb * qb + qa * qc) * gb + qb * qc * gc);
+    const double S11 = -(qb * qb * ga + qb * qc * gb + qc * qc * gc);
+    // Sigma2 = J M J^T + eps I
+    const double j00 = vg.j00, j02 = vg.j02, j11 = vg.j11, j12 = vg.j12;
+    double GM[6];
+    GM[0] = j00 * j00 * S00;
+    GM[1] = j00 * j11 * S01;
+    GM[2] = j00 * (S00 * j02 + S01 * j12);
+    GM[3] = j11 * j11 * S11;
+    GM[4] = j11 * (S01 * j02 + S11 * j12);
+    GM[5] = j02 * j02 * S00 + 2.0 * j02 * j12 * S01 + j12 * j12 * S11;
+    const double M00 = vg.M[0], M01 = vg.M[1], M02 = vg.M[2], M11 = vg.M[3], M12 = vg.M[4], M22 = vg.M[5];
+    const double JM0[3] = {j00 * M00 + j02 * M02, j00 * M01 + j02 * M12, j00 * M02 + j02 * M22};
+    const double JM1[3] = {j11 * M01 + j12 * M02, j11 * M11 + j12 * M12, j11 * M12 + j12 * M22};
+    const double GJ00 = 2.0 * (S00 * JM0[0] + S01 * JM1[0]);
+    const double GJ02 = 2.0 * (S00 * JM0[2] + S01 * JM1[2]);
+    const double GJ11 = 2.0 * (S01 * JM0[1] + S11 * JM1[1]);
+    const double GJ12 = 2.0 * (S01 * JM0[2] + S11 * JM1[2]);
+    const double fx = cam.fx, fy = cam.fy, z = vg.x[2], z2 = z * z;
+    double gx[3];
+    gx[0] = gu * fx / z;
+    gx[1] = gw * fy / z;
+    gx[2] = -gu * fx * vg.x[0] / z2 - gw * fy * vg.x[1] / z2 - GJ00 * fx / z2 - GJ11 * fy / z2;
+    if (!vg.clx) { gx[0] += -GJ02 * fx / z2; gx[2] += GJ02 * 2.0 * fx * vg.x[0] / (z2 * z); }
+    else { gx[2] += -GJ02 * j02 / z; }          // j02 = -fx c / z, c fixed
+    if (!vg.cly) { gx[1] += -GJ12 * fy / z2; gx[2] += GJ12 * 2.0 * fy * vg.x[1] / (z2 * z); }
+    else { gx[2] += -GJ12 * j12 / z; }
+    // x = W mu + t ;  M = W Sigma W^T
+    double W[9];
+    for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
+    for (int c = 0; c < 3; ++c) gm[c] += W[c] * gx[0] + W[3 + c] * gx[1] + W[6 + c] * gx[2];
+    const double G[9] = {GM[0], GM[1], GM[2], GM[1], GM[3], GM[4], GM[2], GM[4], GM[5]};
+    double T[9], G3[9];   // G3 = W^T G W
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) T[r * 3 + c] = W[r] * G[c] + W[3 + r] * G[3 + c] + W[6 + r] * G[6 + c];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) G3[r * 3 + c] = T[r * 3] * W[c] + T[r * 3 + 1] * W[3 + c] + T[r * 3 + 2] * W[6 + c];
+    // Sigma = Rq diag(e2) Rq^T
+    const double* R = g.Rq;
+    double GR[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        GR[r * 3 + c] = 2.0 * (G3[r * 3] * R[c] + G3[r * 3 + 1] * R[3 + c] + G3[r * 3 + 2] * R[6 + c]) * g.e2[c];
+    for (int k = 0; k < 3; ++k) {
+      // (Rq^T G3 Rq)_kk = sum_rc R[r][k] G3[r][c] R[c][k]
+      double s = 0;
+      for (int r = 0; r < 3; ++r)
+        s += R[r * 3 + k] * (G3[r * 3] * R[k] + G3[r * 3 + 1] * R[3 + k] + G3[r * 3 + 2] * R[6 + k]);
+      gs[k] += 2.0 * g.e2[k] * s;
+    }
+    const double w_ = g.rho[0], x_ = g.rho[1], y_ = g.rho[2], z_ = g.rho[3];
+    double gr[4];
+    gr[0] = 2 * (-z_ * GR[1] + y_ * GR[2] + z_ * GR[3] - x_ * GR[5] - y_ * GR[6] + x_ * GR[7]);
+    gr[1] = 2 * (y_ * GR[1] + z_ * GR[2] + y_ * GR[3] - 2 * x_ * GR[4] - w_ * GR[5] + z_ * GR[6] + w_ * GR[7] -
+                 2 * x_ * GR[8]);
+    gr[2] = 2 * (-2 * y_ * GR[0] + x_ * GR[1] + w_ * GR[2] + x_ * GR[3] + z_ * GR[5] - w_ * GR[6] + z_ * GR[7] -
+                 2 * y_ * GR[8]);
+    gr[3] = 2 * (-2 * z_ * GR[0] - w_ * GR[1] + x_ * GR[2] + w_ * GR[3] - 2 * z_ * GR[4] + y_ * GR[5] +
+                 x_ * GR[6] + y_ * GR[7]);
+    const double dot = w_ * gr[0] + x_ * gr[1] + y_ * gr[2] + z_ * gr[3];
+    for (int k = 0; k < 4; ++k) gq[k] += (gr[k] - g.rho[k] * dot) / g.qn;
+  }
+  auto put = [&](float* dst, double val) {
+    if (a.accumulate) *dst += (float)val; else *dst = (float)val;
+  };
+  for (int k = 0; k < 3; ++k) put(&a.gmean[k * n + i], gm[k]);
+  for (int k = 0; k < 3; ++k) put(&a.glsc[k * n + i], gs[k]);
+  for (int k = 0; k < 4; ++k) put(&a.gquat[k * n + i], gq[k]);
+  put(&a.gopac[i], go);
+  for (int k = 0; k < nk * 3; ++k) put(&a.gsh[(int64_t)k * n + i], gsh[k]);
+}
+
+}  // namespace
+
+hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* cams, int v0, int nv, void* ws,
+                          hipStream_t st) {
+  ProjArgs a;
+  a.p = p;
+  a.cams = cams;
+  a.views = pl.d_views;
+  a.v0 = v0;
+  a.nv = nv;
+  a.tile_w = pl.tile_w;
+  a.tile_h = pl.tile_h;
+  a.depth = seg<uint32_t>(ws, pl.ws.depth);
+  a.count = seg<uint32_t>(ws, pl.ws.count);
+  a.rect = seg<ushort4>(ws, pl.ws.rect);
+  a.rec = seg<float4>(ws, pl.ws.rec);
+  a.g2 = seg<float4>(ws, pl.ws.g2);
+  const int blocks = (p.n + 255) / 256;
+  if (blocks > 0) hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camera* cams, int v0, int nv, void* ws,
+                              const gs_params& grads, int accumulate, hipStream_t st) {
+  ProjBwdArgs a;
+  a.p = p;
+  a.cams = cams;
+  a.v0 = v0;
+  a.nv = nv;
+  a.count = seg<uint32_t>(ws, pl.ws.count);
+  a.g2 = seg<float4>(ws, pl.ws.g2);
+  a.gmean = grads.mean;
+  a.glsc = grads.log_scale;
+  a.gquat = grads.quat;
+  a.gopac = grads.opacity_logit;
+  a.gsh = grads.sh;
+  a.accumulate = accumulate;
+  const int blocks = (p.n + 127) / 128;
+  if (blocks > 0) hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(128), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace gs

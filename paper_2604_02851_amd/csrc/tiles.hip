@@ -1,0 +1,379 @@
+// Tile lists: visible compaction, depth pre-sort, key emission, radix sort by
+// tile, per-tile ranges.
+//
+// Order required by the compositing rule: within a tile, splats ascend by
+// (FP32 depth bits, Gaussian index).  Instead of sorting one 64-bit
+// (tile | depth) key per (tile, Gaussian) pair, the visible (view, Gaussian)
+// pairs (a few per Gaussian) are sorted by depth first, keys are emitted in
+// that order, and a stable sort on the tile bits alone finishes the job:
+// 4 passes over the visible pairs plus ceil(tile bits / 8) passes over the
+// keys, instead of ~7 passes over the keys.
+//
+// All kernels are driven by device-side counts so the stage can be captured
+// in a graph: grids are sized for the plan's capacity and idle blocks exit.
+#include "internal.h"
+
+namespace gs {
+namespace {
+
+constexpr int B = kSortBlock;
+constexpr int NW = B / 64;
+
+__device__ __forceinline__ uint32_t dev_count(const uint32_t* dcount, int64_t max_count) {
+  if (!dcount) return (uint32_t)max_count;
+  const uint32_t c = *dcount;
+  return c < (uint64_t)max_count ? c : (uint32_t)max_count;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan over the block (B threads); *total receives the block sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wave, uint32_t* total) {
+  const uint32_t inc = wave_incl_scan(x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint32_t s = s_wave[k];
+    pre += (k < w) ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - x;
+}
+
+// Value source of a scan: a[k], (a[k] != 0), or a[idx[k]].
+struct ScanSrc {
+  const uint32_t* a;
+  const uint32_t* idx;
+  int mode;
+  __device__ __forceinline__ uint32_t operator()(uint32_t k) const {
+    if (mode == 0) return a[k];
+    if (mode == 1) return a[k] != 0u ? 1u : 0u;
+    return a[idx[k]];
+  }
+};
+
+__global__ __launch_bounds__(B) void k_scan_reduce(ScanSrc src, int64_t max_count, const uint32_t* dcount,
+                                                   uint32_t* partial) {
+  __shared__ uint32_t s_wave[NW];
+  const uint32_t n = dev_count(dcount, max_count);
+  const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
+  if (begin >= n) return;
+  const uint64_t end = begin + kSortChunk < n ? begin + kSortChunk : n;
+  uint32_t s = 0;
+  for (uint64_t k = begin + threadIdx.x; k < end; k += B) s += src((uint32_t)k);
+  uint32_t tot;
+  block_excl_scan(s, s_wave, &tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of the per-chunk partial sums in place.
+__global__ __launch_bounds__(1024) void k_scan_partials(int64_t max_count, const uint32_t* dcount, uint32_t* partial,
+                                                        uint32_t* total) {
+  __shared__ uint32_t s_w[16];
+  __shared__ uint32_t s_carry;
+  const uint32_t n = dev_count(dcount, max_count);
+  const uint32_t np = (uint32_t)((n + kSortChunk - 1) / kSortChunk);
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < np; base += 1024) {
+    const uint32_t k = base + threadIdx.x;
+    const uint32_t x = k < np ? partial[k] : 0u;
+    const uint32_t inc = wave_incl_scan(x);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int q = 0; q < 16; ++q) {
+      pre += (q < w) ? s_w[q] : 0u;
+      tot += s_w[q];
+    }
+    const uint32_t carry = s_carry;
+    if (k < np) partial[k] = carry + pre + inc - x;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[np] = s_carry;
+    if (total) *total = s_carry;
+  }
+}
+
+__global__ __launch_bounds__(B) void k_scan_down(ScanSrc src, uint32_t* out, int64_t max_count,
+                                                 const uint32_t* dcount, const uint32_t* partial) {
+  __shared__ uint32_t s_wave[NW];
+  const uint32_t n = dev_count(dcount, max_count);
+  const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
+  if (begin >= n) return;
+  // each thread owns kSortItems consecutive elements
+  const uint64_t mine = begin + (uint64_t)threadIdx.x * kSortItems;
+  uint32_t v[kSortItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const uint64_t k = mine + j;
+    v[j] = k < n ? src((uint32_t)k) : 0u;
+    s += v[j];
+  }
+  uint32_t tot;
+  uint32_t run = partial[blockIdx.x] + block_excl_scan(s, s_wave, &tot);
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const uint64_t k = mine + j;
+    if (k < n) out[k] = run;
+    run += v[j];
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+// ---- visible compaction -----------------------------------------------------
+__global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* count, const uint32_t* depth,
+                                                         const uint32_t* pos, int64_t base, int64_t len,
+                                                         uint32_t* vis_ids, uint32_t* vis_keys) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  if (count[base + k] != 0u) {
+    const uint32_t p = pos[k];
+    vis_ids[p] = (uint32_t)(base + k);
+    vis_keys[p] = depth[base + k];
+  }
+}
+
+// ---- radix sort (LSD, 8-bit digits, stable) ---------------------------------
+__global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, int64_t max_count, const uint32_t* dcount,
+                                                  int shift, int64_t nblocks, uint32_t* hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t n = dev_count(dcount, max_count);
+  const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
+  const uint64_t end = begin + kSortChunk < n ? begin + kSortChunk : n;
+  for (uint64_t k = begin + threadIdx.x; k < end; k += B) atomicAdd(&h[(keys[k] >> shift) & 255u], 1u);
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Scatter of one chunk in input order.  Rank of a key = keys of the same
+// digit in earlier chunks (scanned histogram) + earlier iterations of this
+// chunk + earlier waves of this iteration + earlier lanes of its wave.  Lanes
+// with equal digits are matched with eight ballots.
+__global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+                                                     uint32_t* vout, int64_t max_count, const uint32_t* dcount,
+                                                     int shift, int64_t nblocks, const uint32_t* hist_scanned) {
+  __shared__ uint32_t s_run[256];
+  __shared__ uint32_t s_cnt[NW][256];
+  const uint32_t n = dev_count(dcount, max_count);
+  const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
+  if (begin >= n) return;
+  const uint64_t end = begin + kSortChunk < n ? begin + kSortChunk : n;
+  s_run[threadIdx.x] = hist_scanned[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (uint64_t base = begin; base < end; base += B) {
+    for (int q = threadIdx.x; q < NW * 256; q += B) (&s_cnt[0][0])[q] = 0;
+    __syncthreads();
+    const uint64_t k = base + threadIdx.x;
+    const bool valid = k < end;
+    const uint32_t key = valid ? kin[k] : 0u;
+    const uint32_t val = valid ? vin[k] : 0u;
+    const uint32_t digit = (key >> shift) & 255u;
+    uint64_t match = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (digit >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      match &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(match & lt_mask);
+    if (valid && rank == 0) s_cnt[w][digit] = (uint32_t)__popcll(match);
+    __syncthreads();
+    if (valid) {
+      uint32_t dst = s_run[digit] + rank;
+      for (int q = 0; q < w; ++q) dst += s_cnt[q][digit];
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) add += s_cnt[q][threadIdx.x];
+    s_run[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// ---- key emission in depth order -----------------------------------------
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const uint32_t* koff, const uint32_t* nvis_p,
+                                              const ushort4* rect, const ViewInfo* views, int64_t n_gauss,
+                                              int32_t tile_begin, uint32_t cap, uint32_t* keys, uint32_t* vals) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= *nvis_p) return;
+  const uint32_t vi = sorted_vis[k];
+  const int v = (int)(vi / (uint64_t)n_gauss);
+  const ViewInfo view = views[v];
+  const ushort4 r = rect[vi];
+  uint32_t pos = koff[k];
+  for (int ty = r.y; ty <= r.w; ++ty) {
+    const int32_t row = view.tile_base + ty * view.tiles_x - tile_begin;
+    for (int tx = r.x; tx <= r.z; ++tx) {
+      if (pos < cap) {
+        keys[pos] = (uint32_t)(row + tx);
+        vals[pos] = vi;
+      }
+      ++pos;
+    }
+  }
+}
+
+__global__ void k_key_total(Counters* c, const uint32_t* total_keys, uint32_t cap) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const uint32_t k = *total_keys;
+    c->keys = k;
+    c->key_cap = cap;
+    if (k > cap) c->overflow = 1u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys, const uint32_t* count_p, uint32_t cap,
+                                                int32_t tile_begin, uint2* ranges) {
+  const uint32_t n = min(*count_p, cap);
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t t = keys[k];
+  if (k == 0 || keys[k - 1] != t) ranges[tile_begin + t].x = k;
+  if (k == n - 1 || keys[k + 1] != t) ranges[tile_begin + t].y = k + 1;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st, p, value, count);
+  return hipGetLastError();
+}
+
+static hipError_t scan_src(ScanSrc src, uint32_t* out, int64_t max_count, const uint32_t* dcount, uint32_t* partial,
+                           int64_t partial_len, uint32_t* total, hipStream_t st) {
+  const int64_t nb = cdiv(max_count, kSortChunk);
+  if (nb + 1 > partial_len) return hipErrorInvalidValue;
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(B), 0, st, src, max_count, dcount, partial);
+  }
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, max_count, dcount, partial, total);
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(B), 0, st, src, out, max_count, dcount, partial);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t max_count, const uint32_t* dcount, uint32_t* partial,
+                       int64_t partial_len, uint32_t* total, hipStream_t st) {
+  return scan_src(ScanSrc{in, nullptr, 0}, out, max_count, dcount, partial, partial_len, total, st);
+}
+
+// Sorts (key, value) pairs on key bits [0, bits) in ping-pong buffers; returns
+// through *in_b whether the result landed in the second buffer.
+static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
+                             int64_t max_count, const uint32_t* dcount, int bits, bool* in_b, hipStream_t st) {
+  const int64_t nb = cdiv(max_count, kSortChunk);
+  uint32_t* hist = seg<uint32_t>(ws, pl.ws.hist);
+  uint32_t* partial = seg<uint32_t>(ws, pl.ws.partial);
+  if (nb > pl.ws.hist_blocks) return hipErrorInvalidValue;
+  bool flip = false;
+  for (int shift = 0; shift < bits; shift += 8) {
+    uint32_t* ki = flip ? kb : ka;
+    uint32_t* vi = flip ? vb : va;
+    uint32_t* ko = flip ? ka : kb;
+    uint32_t* vo = flip ? va : vb;
+    if (nb > 0) {
+      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(B), 0, st, ki, max_count, dcount, shift, nb, hist);
+      hipError_t e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * nb, nullptr, partial, pl.ws.partial_len,
+                              nullptr, st);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, max_count, dcount,
+                         shift, nb, hist);
+    }
+    flip = !flip;
+  }
+  *in_b = flip;
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream_t st) {
+  Counters* ctr = seg<Counters>(ws, pl.ws.counters);
+  const int64_t N = pl.n;
+  const int64_t base = (int64_t)v0 * N, len = (int64_t)nv * N;
+  uint32_t* count = seg<uint32_t>(ws, pl.ws.count);
+  uint32_t* depth = seg<uint32_t>(ws, pl.ws.depth);
+  uint32_t* vis_a = seg<uint32_t>(ws, pl.ws.vis_a);
+  uint32_t* vis_b = seg<uint32_t>(ws, pl.ws.vis_b);
+  uint32_t* vkey_a = seg<uint32_t>(ws, pl.ws.vkey_a);
+  uint32_t* vkey_b = seg<uint32_t>(ws, pl.ws.vkey_b);
+  uint32_t* koff = seg<uint32_t>(ws, pl.ws.koff);
+  uint32_t* partial = seg<uint32_t>(ws, pl.ws.partial);
+  uint32_t* keys_a = seg<uint32_t>(ws, pl.ws.keys_a);
+  uint32_t* keys_b = seg<uint32_t>(ws, pl.ws.keys_b);
+  uint32_t* vals_a = seg<uint32_t>(ws, pl.ws.vals_a);
+  uint32_t* vals_b = seg<uint32_t>(ws, pl.ws.vals_b);
+  uint2* ranges = seg<uint2>(ws, pl.ws.ranges);
+  const uint32_t cap = (uint32_t)pl.cap;
+  hipError_t e;
+  if (len == 0) return hipSuccess;
+  // counters of this build
+  e = launch_fill_u32(&ctr->overflow, 0u, 1, st);
+  if (e != hipSuccess) return e;
+  // 1. visible compaction in (view, Gaussian) order: positions -> koff (scratch)
+  e = scan_src(ScanSrc{count + base, nullptr, 1}, koff, len, nullptr, partial, pl.ws.partial_len, &ctr->nvis, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compact_visible, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, count, depth, koff, base,
+                     len, vis_a, vkey_a);
+  // 2. stable depth sort of the visible pairs (ties keep (view, Gaussian) order)
+  bool in_b = false;
+  e = radix_sort(pl, ws, vkey_a, vis_a, vkey_b, vis_b, len, &ctr->nvis, 32, &in_b, st);
+  if (e != hipSuccess) return e;
+  const uint32_t* sorted_vis = in_b ? vis_b : vis_a;
+  // 3. key offsets in depth order
+  e = scan_src(ScanSrc{count, sorted_vis, 2}, koff, len, &ctr->nvis, partial, pl.ws.partial_len, &ctr->keys, st);
+  if (e != hipSuccess) return e;
+  // ctr->keys holds the total; record it and the overflow flag
+  hipLaunchKernelGGL(k_key_total, dim3(1), dim3(64), 0, st, ctr, &ctr->keys, cap);
+  // 4. emit (tile, value) pairs in depth order
+  const int32_t tile_begin = pl.views[v0].tile_base;
+  const int32_t tile_end = (v0 + nv < pl.n_views) ? pl.views[v0 + nv].tile_base : pl.total_tiles;
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, sorted_vis, koff, &ctr->nvis,
+                     seg<ushort4>(ws, pl.ws.rect), pl.d_views, N, tile_begin, cap, keys_a, vals_a);
+  // 5. stable sort by tile (relative to the first tile of the call)
+  const int64_t ntiles = tile_end - tile_begin;
+  int bits = 0;
+  while ((1ll << bits) < ntiles) ++bits;
+  bits = bits == 0 ? 8 : ((bits + 7) / 8) * 8;
+  e = radix_sort(pl, ws, keys_a, vals_a, keys_b, vals_b, pl.cap, &ctr->keys, bits, &in_b, st);
+  if (e != hipSuccess) return e;
+  // 6. ranges
+  e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges + tile_begin), 0u, 2 * ntiles, st);
+  if (e != hipSuccess) return e;
+  const uint32_t* sk = in_b ? keys_b : keys_a;
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)cdiv(pl.cap, 256)), dim3(256), 0, st, sk, &ctr->keys, cap, tile_begin,
+                     ranges);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,210 @@
+// Parameter update (fused Adam over every tensor) and changed-Gaussian delta
+// extraction with stable compaction.  Both are streaming, HBM-bound kernels:
+// one pass over the parameters and their state, coalesced planar accesses.
+#include "internal.h"
+
+namespace gs {
+namespace {
+
+struct AdamSeg {
+  float* theta;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t count;
+  float lr;
+};
+
+struct AdamArgs {
+  AdamSeg seg[6];
+  const int32_t* step;
+  float beta1, beta2, eps;
+};
+
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+  const AdamSeg s = a.seg[blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int t = *a.step + 1;
+  const double b1 = a.beta1, b2 = a.beta2;
+  const float bc1 = (float)(1.0 - pow(b1, (double)t));
+  const float rbc2 = (float)(1.0 / sqrt(1.0 - pow(b2, (double)t)));
+  const float c1 = 1.f - a.beta1, c2 = 1.f - a.beta2;
+  const float step = s.lr / bc1;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < s.count; k += stride) {
+    const float g = s.g[k];
+    const float m = fmaf(a.beta1, s.m[k], c1 * g);
+    const float v = fmaf(a.beta2, s.v[k], c2 * g * g);
+    s.m[k] = m;
+    s.v[k] = v;
+    s.theta[k] -= step * m / (sqrtf(v) * rbc2 + a.eps);
+  }
+}
+
+__global__ void k_bump(int32_t* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
+__global__ void k_bump_u32(uint32_t* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1u;
+}
+
+// ---- delta extraction -------------------------------------------------------
+struct DeltaGroups {
+  const float* cur[6];
+  float* base[6];
+  int32_t width[6];
+};
+
+struct DeltaArgs {
+  DeltaGroups g;
+  int64_t n;
+  uint32_t mask;
+  float tau;
+  uint8_t* flags;
+  uint32_t* bcount;   // [6][nb], scanned in place
+  uint32_t* dbase;    // [0..5] section base, [6..11] count, [15] total
+  int32_t nb;
+  uint32_t* out;
+};
+
+__global__ __launch_bounds__(256) void k_delta_flags(DeltaArgs a) {
+  __shared__ uint32_t s_w[6][4];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  uint32_t f = 0;
+  if (i < a.n) {
+    for (int g = 0; g < 6; ++g) {
+      if (!((a.mask >> g) & 1u)) continue;
+      bool hit = false;
+      for (int k = 0; k < a.g.width[g] && !hit; ++k) {
+        const float p = a.g.cur[g][(int64_t)k * a.n + i];
+        const float b = a.g.base[g][(int64_t)k * a.n + i];
+        const float diff = fabsf(p - b);
+        const float thr = a.tau * fabsf(b);
+        hit = diff > thr;
+      }
+      f |= hit ? (1u << g) : 0u;
+    }
+    a.flags[i] = (uint8_t)f;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int g = 0; g < 6; ++g) {
+    const uint64_t bal = __ballot((f >> g) & 1u);
+    if (lane == 0) s_w[g][w] = (uint32_t)__popcll(bal);
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int g = threadIdx.x;
+    a.bcount[(int64_t)g * a.nb + blockIdx.x] = s_w[g][0] + s_w[g][1] + s_w[g][2] + s_w[g][3];
+  }
+}
+
+__global__ void k_delta_header(DeltaArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t run = 6;
+  for (int g = 0; g < 6; ++g) {
+    const uint32_t lo = a.bcount[(int64_t)g * a.nb];
+    const uint32_t hi = g < 5 ? a.bcount[(int64_t)(g + 1) * a.nb] : a.dbase[15];
+    const uint32_t c = hi - lo;
+    a.dbase[g] = run;
+    a.dbase[6 + g] = c;
+    a.out[g] = c;
+    run += c * (1u + (uint32_t)a.g.width[g]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_delta_write(DeltaArgs a) {
+  __shared__ uint32_t s_w[6][4];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t f = i < a.n ? a.flags[i] : 0u;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  uint32_t wrank[6];
+  for (int g = 0; g < 6; ++g) {
+    const uint64_t bal = __ballot((f >> g) & 1u);
+    wrank[g] = (uint32_t)__popcll(bal & lt);
+    if (lane == 0) s_w[g][w] = (uint32_t)__popcll(bal);
+  }
+  __syncthreads();
+  if (f == 0) return;
+  for (int g = 0; g < 6; ++g) {
+    if (!((f >> g) & 1u)) continue;
+    uint32_t r = wrank[g];
+    for (int q = 0; q < w; ++q) r += s_w[g][q];
+    r += a.bcount[(int64_t)g * a.nb + blockIdx.x] - a.bcount[(int64_t)g * a.nb];
+    const uint32_t base = a.dbase[g], cnt = a.dbase[6 + g];
+    const int wd = a.g.width[g];
+    a.out[base + r] = (uint32_t)i;
+    uint32_t* vals = a.out + base + cnt + (size_t)r * wd;
+    for (int k = 0; k < wd; ++k) {
+      const float p = a.g.cur[g][(int64_t)k * a.n + i];
+      vals[k] = __float_as_uint(p);
+      a.g.base[g][(int64_t)k * a.n + i] = p;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v, int32_t* step,
+                       const gs_adam_hparams& hp, hipStream_t st) {
+  const int64_t n = p.n;
+  const int64_t nk = (int64_t)(p.sh_degree + 1) * (p.sh_degree + 1);
+  AdamArgs a;
+  auto setseg = [&](int s, float* th, float* gr, float* mm, float* vv, int64_t cnt) {
+    a.seg[s] = AdamSeg{th, gr, mm, vv, cnt, hp.lr[s]};
+  };
+  setseg(0, p.mean, g.mean, m.mean, v.mean, 3 * n);
+  setseg(1, p.log_scale, g.log_scale, m.log_scale, v.log_scale, 3 * n);
+  setseg(2, p.quat, g.quat, m.quat, v.quat, 4 * n);
+  setseg(3, p.opacity_logit, g.opacity_logit, m.opacity_logit, v.opacity_logit, n);
+  setseg(4, p.sh, g.sh, m.sh, v.sh, 3 * n);
+  setseg(5, p.sh + 3 * n, g.sh + 3 * n, m.sh + 3 * n, v.sh + 3 * n, (nk - 1) * 3 * n);
+  a.step = step;
+  a.beta1 = hp.beta1;
+  a.beta2 = hp.beta2;
+  a.eps = hp.eps;
+  const int64_t per_block = 256 * 4;
+  int64_t mx = 4 * n > (nk - 1) * 3 * n ? 4 * n : (nk - 1) * 3 * n;
+  int64_t blocks = (mx + per_block - 1) / per_block;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 65535) blocks = 65535;
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks, 6), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, st, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_epoch_bump(uint32_t* epoch, hipStream_t st) {
+  hipLaunchKernelGGL(k_bump_u32, dim3(1), dim3(64), 0, st, epoch);
+  return hipGetLastError();
+}
+
+hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& base, uint32_t mask, float tau,
+                        uint32_t* out, void* ws, hipStream_t st) {
+  DeltaArgs a;
+  const int64_t n = cur.n;
+  const int nk = (cur.sh_degree + 1) * (cur.sh_degree + 1);
+  a.g.cur[0] = cur.opacity_logit;  a.g.base[0] = base.opacity_logit;  a.g.width[0] = 1;
+  a.g.cur[1] = cur.sh;             a.g.base[1] = base.sh;             a.g.width[1] = 3;
+  a.g.cur[2] = cur.sh + 3 * n;     a.g.base[2] = base.sh + 3 * n;     a.g.width[2] = 3 * (nk - 1);
+  a.g.cur[3] = cur.mean;           a.g.base[3] = base.mean;           a.g.width[3] = 3;
+  a.g.cur[4] = cur.log_scale;      a.g.base[4] = base.log_scale;      a.g.width[4] = 3;
+  a.g.cur[5] = cur.quat;           a.g.base[5] = base.quat;           a.g.width[5] = 4;
+  a.n = n;
+  a.mask = mask;
+  a.tau = tau;
+  a.flags = seg<uint8_t>(ws, pl.ws.dflags);
+  a.bcount = seg<uint32_t>(ws, pl.ws.dcount);
+  a.dbase = seg<uint32_t>(ws, pl.ws.dbase);
+  a.nb = (int32_t)((n + 255) / 256);
+  a.out = out;
+  if (a.nb > pl.ws.dblocks) return hipErrorInvalidValue;
+  if (a.nb > 0) hipLaunchKernelGGL(k_delta_flags, dim3(a.nb), dim3(256), 0, st, a);
+  hipError_t e = launch_scan(a.bcount, a.bcount, 6ll * a.nb, nullptr, seg<uint32_t>(ws, pl.ws.partial),
+                             pl.ws.partial_len, a.dbase + 15, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_delta_header, dim3(1), dim3(64), 0, st, a);
+  if (a.nb > 0) hipLaunchKernelGGL(k_delta_write, dim3(a.nb), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,182 @@
+"""Renderer, autograd wrapper and optimize step over the gsopt C ABI.
+
+PyTorch supplies device memory and streams only; every stage of the path
+(project/cull, tile lists, composite, backward, Adam, delta) runs in
+libgsopt.so.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import native as N
+from .native import Context, DeviceParams, GsAdamHparams, GsParams, GsStepArgs
+
+# Learning rates per parameter group: mean, log_scale, quat, opacity_logit,
+# SH DC, SH higher bands.
+DEFAULT_LR = (1e-3, 5e-3, 1e-3, 5e-2, 5e-3, 5e-3)
+
+
+class Renderer:
+    """A planned frame: cameras, tile layout, workspace and output buffers."""
+
+    def __init__(self, cams: np.ndarray, n: int, sh_degree: int, tile=(16, 16), batch_depth: int = 64,
+                 bg=(0.0, 0.0, 0.0), loss_mode: int = 0, key_capacity: int | None = None, device: int = 0,
+                 ctx: Context | None = None):
+        self.device = torch.device("cuda", device)
+        self.ctx = ctx or Context(device)
+        self.cams = np.ascontiguousarray(cams)
+        self.n, self.sh_degree = n, sh_degree
+        self.tile, self.batch_depth, self.bg, self.loss_mode = tuple(tile), batch_depth, tuple(bg), loss_mode
+        self.dev_cams = torch.from_numpy(self.cams.view(np.uint8).copy()).to(self.device)
+        self.key_capacity = int(key_capacity or max(1 << 16, 8 * n * len(self.cams)))
+        self._plan()
+        P = int(self.pix_off[-1])
+        self.images = torch.zeros(3 * P, dtype=torch.float32, device=self.device)
+        self.T = torch.zeros(P, dtype=torch.float32, device=self.device)
+        self.n_contrib = torch.zeros(P, dtype=torch.int32, device=self.device)
+
+    @property
+    def n_views(self) -> int:
+        return len(self.cams)
+
+    def _plan(self):
+        nbytes = self.ctx.plan(self.n, self.sh_degree, self.cams, self.tile, self.batch_depth, self.bg,
+                               self.loss_mode, self.key_capacity)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.pix_off, self.tile_off = self.ctx.frame_layout()
+
+    def replan(self, key_capacity: int):
+        self.key_capacity = int(key_capacity)
+        self.ws = None
+        self._plan()
+
+    def view_image(self, images: torch.Tensor, v: int) -> torch.Tensor:
+        H, W = int(self.cams[v]["height"]), int(self.cams[v]["width"])
+        return images[3 * self.pix_off[v]: 3 * self.pix_off[v + 1]].view(3, H, W)
+
+    def counters(self):
+        return self.ctx.read_counters(self.ws)
+
+    def fit_capacity(self, params: DeviceParams, per_view: bool = False, margin: float = 1.15):
+        """Runs project + tile lists and grows the key capacity if needed."""
+        need = 0
+        ranges = [(v, 1) for v in range(self.n_views)] if per_view else [(0, self.n_views)]
+        for v0, nv in ranges:
+            self.ctx.project(params, self.dev_cams, v0, nv, self.ws)
+            self.ctx.build_tile_lists(v0, nv, self.ws)
+            need = max(need, int(self.counters().keys))
+        if need > self.key_capacity or need * margin * 4 < self.key_capacity:
+            self.replan(max(1024, int(need * margin) + 1024))
+        return need
+
+    # ---- stages -------------------------------------------------------------
+    def forward(self, params: DeviceParams, v0: int = 0, nv: int | None = None):
+        nv = self.n_views - v0 if nv is None else nv
+        self.ctx.project(params, self.dev_cams, v0, nv, self.ws)
+        self.ctx.build_tile_lists(v0, nv, self.ws)
+        self.ctx.composite(v0, nv, self.ws, self.images, self.T, self.n_contrib)
+        return self.images, self.T, self.n_contrib
+
+    def backward(self, params: DeviceParams, upstream: torch.Tensor, mode: int, grads: DeviceParams,
+                 v0: int = 0, nv: int | None = None, accumulate: int = 0, loss: torch.Tensor | None = None):
+        nv = self.n_views - v0 if nv is None else nv
+        self.ctx.backward(params, self.dev_cams, v0, nv, self.ws, self.images, self.T, upstream, mode, grads,
+                          accumulate, loss)
+
+
+class GaussianRasterize(torch.autograd.Function):
+    """images = render(params) over every view of `renderer`, with the
+    hand-written adjoint of the library as backward.  The renderer keeps the
+    tile lists and per-pixel state of the last forward; a backward must follow
+    its own forward before the renderer runs another one."""
+
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, opacity_logit, sh, renderer: Renderer):
+        params = DeviceParams(mean.detach().contiguous(), log_scale.detach().contiguous(),
+                              quat.detach().contiguous(), opacity_logit.detach().contiguous(),
+                              sh.detach().contiguous(), renderer.sh_degree)
+        images, T, _ = renderer.forward(params)
+        ctx.renderer = renderer
+        ctx.params = params
+        out = images.clone()
+        ctx.save_for_backward(out)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_images):
+        r: Renderer = ctx.renderer
+        (images,) = ctx.saved_tensors
+        grads = DeviceParams.zeros_like(ctx.params)
+        up = grad_images.contiguous().float()
+        r.ctx.backward(ctx.params, r.dev_cams, 0, r.n_views, r.ws, images, r.T, up, 0, grads, 0, None)
+        return (*grads.tensors(), None)
+
+
+def rasterize(params_tensors, renderer: Renderer):
+    return GaussianRasterize.apply(*params_tensors, renderer)
+
+
+class Optimizer:
+    """Online optimize step (render reference views, L1 against targets,
+    backward, Adam), batched or plain, eager or replayed from a HIP graph."""
+
+    def __init__(self, renderer: Renderer, params: DeviceParams, targets: torch.Tensor, lr=DEFAULT_LR,
+                 betas=(0.9, 0.999), eps=1e-15, stream: torch.cuda.Stream | None = None):
+        self.r = renderer
+        self.params = params
+        self.targets = targets.contiguous()
+        self.grads = DeviceParams.zeros_like(params)
+        self.m = DeviceParams.zeros_like(params)
+        self.v = DeviceParams.zeros_like(params)
+        dev = renderer.device
+        self.step_count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.lr, self.betas, self.eps = tuple(lr), tuple(betas), eps
+        self.stream = stream
+        self.delta = None
+        self._args_cache = {}
+
+    def enable_delta(self, baseline: DeviceParams, group_mask: int = 0x3F, rel_tau: float = 1e-3):
+        words = N.delta_capacity_words(self.params.n, self.params.sh_degree, group_mask)
+        self.delta = dict(baseline=baseline, mask=group_mask, tau=rel_tau,
+                          out=torch.zeros(words, dtype=torch.int32, device=self.r.device))
+        self._args_cache.clear()
+
+    def args(self, plain: bool) -> GsStepArgs:
+        key = bool(plain)
+        if key in self._args_cache:
+            return self._args_cache[key]
+        a = GsStepArgs()
+        a.params, a.grads, a.adam_m, a.adam_v = (x.struct() for x in (self.params, self.grads, self.m, self.v))
+        a.dev_cams = N.ptr(self.r.dev_cams)
+        a.dev_target = N.ptr(self.targets)
+        a.dev_images = N.ptr(self.r.images)
+        a.dev_T_final = N.ptr(self.r.T)
+        a.dev_n_contrib = N.ptr(self.r.n_contrib)
+        a.dev_loss = N.ptr(self.loss)
+        a.dev_step = N.ptr(self.step_count)
+        a.dev_workspace = N.ptr(self.r.ws)
+        a.hp = GsAdamHparams((N.c_float * 6)(*self.lr), self.betas[0], self.betas[1], self.eps)
+        a.plain = 1 if plain else 0
+        if self.delta is not None:
+            a.do_delta = 1
+            a.baseline = self.delta["baseline"].struct()
+            a.group_mask = self.delta["mask"]
+            a.rel_tau = self.delta["tau"]
+            a.dev_delta_out = N.ptr(self.delta["out"])
+            a.delta_cap_words = self.delta["out"].numel()
+        self._args_cache[key] = a
+        return a
+
+    def invalidate(self):
+        self._args_cache.clear()
+
+    def step(self, plain: bool = False):
+        self.r.ctx.step(self.args(plain), self.stream)
+
+    def capture(self, plain: bool = False):
+        self.r.ctx.step_capture(self.args(plain), self.stream)
+
+    def replay(self, plain: bool = False):
+        self.r.ctx.step_launch(self.args(plain), self.stream)

@@ -1,0 +1,78 @@
+"""Helpers shared by the GPU parity tests (imported by tests only)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+IMG_TOL = 1e-5          # absolute per channel (FP32 image vs FP64 oracle)
+GRAD_REL = 1e-4         # relative
+GRAD_ABS = 1e-6         # absolute floor
+# FP32 accumulation allowance: |error| <= EPS_ACC * (sum of |terms|), the
+# oracle's magnitude scale; 2^-17 is ~128 units of FP32 rounding.
+EPS_ACC = 2.0 ** -17
+
+
+def renderer_for(w, tile=(16, 16), batch=64, bg=(0.0, 0.0, 0.0), loss_mode=0, cap=None):
+    from paper_2604_02851_amd.renderer import Renderer
+    r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, tile=tile, batch_depth=batch, bg=bg, loss_mode=loss_mode,
+                 key_capacity=cap)
+    return r
+
+
+def seg_np(r, name, dtype, v0=0, nv=None):
+    torch.cuda.synchronize()
+    return r.ctx.segment(r.ws, name, v0, nv).cpu().numpy().view(dtype)
+
+
+def compare_images(oracle, w, gpu_img, bg=(0.0, 0.0, 0.0), tol=IMG_TOL, ref=None):
+    """Every pixel within tol of the oracle, or, at pixels with
+    near-threshold decisions, within tol of one of their outcomes.
+    Returns (max error at clean pixels, number of pixels matched through an
+    alternative outcome)."""
+    ref = ref if ref is not None else oracle.render(w.scene, w.cams, bg=bg)
+    off = oracle.pixel_offsets(w.cams)
+    worst = 0.0
+    via_alt = 0
+    for v, cam in enumerate(w.cams):
+        H, W = int(cam["height"]), int(cam["width"])
+        a = gpu_img[3 * off[v]:3 * off[v + 1]].reshape(3, H * W).astype(np.float64)
+        b = ref.image[3 * off[v]:3 * off[v + 1]].reshape(3, H * W)
+        d = np.abs(a - b).max(0)
+        fl = ref.flags[off[v]:off[v + 1]] > 0
+        clean = d[~fl]
+        if clean.size:
+            worst = max(worst, float(clean.max()))
+        bad_clean = np.nonzero((d > tol) & ~fl)[0]
+        assert bad_clean.size == 0, f"view {v}: {bad_clean.size} pixels off by up to {d[bad_clean].max():.3g}"
+        bad = np.nonzero((d > tol) & fl)[0]
+        if bad.size:
+            xy = np.stack([bad % W, bad // W], 1)
+            alts = oracle.render_alternatives(w.scene, w.cams, v, xy, bg=bg)
+            for q, p in enumerate(bad):
+                best = np.abs(alts[q][:, :3] - a[:, p][None, :]).max(1).min()
+                assert best <= tol, f"view {v} pixel {p}: no outcome within tol (best {best:.3g})"
+            via_alt += bad.size
+    return worst, via_alt
+
+
+def flat_grads(grads) -> np.ndarray:
+    n = grads.n
+    return np.concatenate([t.detach().cpu().numpy().reshape(-1, n) for t in grads.tensors()], 0).astype(np.float64)
+
+
+def grad_report(g_gpu: np.ndarray, b, rel=GRAD_REL, floor=GRAD_ABS, eps_acc=EPS_ACC):
+    """Checks |g_gpu - g| <= rel |g| + floor + eps_acc * scale + slack and
+    returns statistics."""
+    err = np.abs(g_gpu - b.grad)
+    strict = rel * np.abs(b.grad) + floor
+    tol = strict + eps_acc * b.scale + b.slack
+    ok = err <= tol
+    return {
+        "max_err_over_tol": float((err / tol).max()),
+        "n": int(err.size),
+        "fail": int((~ok).sum()),
+        "strict_fail": int((err > strict).sum()),
+        "max_rel_err_large": float((err / np.maximum(np.abs(b.grad), 1e-30))[np.abs(b.grad) > 1e-2].max()
+                                   if (np.abs(b.grad) > 1e-2).any() else 0.0),
+        "worst_idx": np.unravel_index(int(np.argmax(err / tol)), err.shape),
+    }
