@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Optimize-step throughput of the 3DGS hot path on one MI355X.
+
+Workload (default): 1M Gaussians, SH degree 3, 16 reference views of mixed
+resolution (640x360 / 1280x720 / 1920x1080) on a sphere of radius 6-12, L1
+loss against targets rendered from a perturbed copy of the model.  A step is
+project/cull -> tile lists -> composite -> backward -> fused Adam over all 16
+views.  `value` is the batched step (one launch per stage for all views, the
+whole step replayed from a HIP graph) in steps/s; the plain path (the same
+kernels one view per launch, eager) is reported beside it.
+
+Also printed: per-stage times from the library's HIP-event timers, the
+roofline position of the dominant kernel, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "optimize steps/sec (fwd+bwd+Adam, 1M Gaussians, 16 mixed views) batched vs plain"
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+# Algorithmic FP32 operations per examined (pixel, splat) pair and per
+# composited pair (counted from the compositing rule and its adjoint).
+FLOPS_TEST = 12
+FLOPS_FWD_COMPOSITED = 12
+FLOPS_BWD_COMPOSITED = 55
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse_tile(s):
+    w, h = s.lower().split("x")
+    return int(w), int(h)
+
+
+def pair_counts(r, torch):
+    """(examined pairs up to each pixel's last composited splat, composited
+    pairs) of the last forward pass."""
+    import numpy as np
+    ranges = r.ctx.segment(r.ws, "ranges").view(torch.int32).view(-1, 2).long()
+    last = r.ctx.segment(r.ws, "last").view(torch.int32).long()
+    E = 0
+    for v in range(r.n_views):
+        W, H = int(r.cams[v]["width"]), int(r.cams[v]["height"])
+        tw, th = r.tile
+        tx = (W + tw - 1) // tw
+        ys = torch.arange(H, device=r.device).view(-1, 1) // th
+        xs = torch.arange(W, device=r.device).view(1, -1) // tw
+        tiles = (int(r.tile_off[v]) + ys * tx + xs).view(-1)
+        p0, p1 = int(r.pix_off[v]), int(r.pix_off[v + 1])
+        E += int((last[p0:p1] - ranges[tiles, 0]).sum().item())
+    C = int(r.n_contrib.long().sum().item())
+    return E, C
+
+
+def cpu_baseline(w, rows: int):
+    """Times the FP64 oracle's forward+backward on a band of rows of view 0
+    (all Gaussians projected) and extrapolates to the whole step."""
+    import numpy as np
+    from oracle import oracle as O
+    import copy
+    cam = w.cams[0:1].copy()
+    H = int(cam[0]["height"])
+    rows = H if rows <= 0 or rows > H else rows
+    y0 = H // 2 - rows // 2
+
+    def crop(nrows, top):
+        c = cam.copy()
+        c[0]["height"] = nrows
+        c[0]["cy"] = np.float32(float(c[0]["cy"]) - top)
+        return c
+
+    tgt_rows = lambda c: np.full(3 * int(c[0]["width"]) * int(c[0]["height"]), 0.5, np.float32)
+    O.lib()
+    c1 = crop(1, y0)
+    t = time.perf_counter()
+    O.backward(w.scene, c1, tgt_rows(c1), mode=1)
+    t_one = time.perf_counter() - t
+    cb = crop(rows, y0)
+    t = time.perf_counter()
+    O.backward(w.scene, cb, tgt_rows(cb), mode=1)
+    t_band = time.perf_counter() - t
+    W = int(cam[0]["width"])
+    t_pix = max(t_band - t_one, 1e-9) / (W * (rows - 1))
+    total_pix = sum(int(c["width"]) * int(c["height"]) for c in w.cams)
+    t_step = len(w.cams) * t_one + total_pix * t_pix
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle forward+backward of view 0 ({W}x{H}), {rows} centre rows "
+                       f"({t_band:.1f} s) and to 1 row ({t_one:.1f} s, projection of all "
+                       f"{w.scene.n} Gaussians); step time extrapolated as 16 projections + "
+                       f"{total_pix} pixels at the band's per-pixel cost = {t_step:.0f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--tile", default=None, help="e.g. 16x16 (default: autotuned)")
+    ap.add_argument("--batch-depth", type=int, default=None)
+    ap.add_argument("--ppt", type=int, default=None, help="pixels per thread (default: autotuned)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=0, help="rows of view 0 in the oracle sample (0 = all)")
+    ap.add_argument("--calib-copy", action="store_true", help="run only a plain 1 GiB device copy (PMC calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
+              "(the multi-GPU design shards views and reduce-scatters gradients; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": src.numel() * 4}))
+        return
+
+    from paper_2604_02851_amd import scenes as S
+    from paper_2604_02851_amd.native import DeviceParams
+    from paper_2604_02851_amd.renderer import Optimizer, Renderer, autotune
+
+    t0 = time.perf_counter()
+    w = S.workload(args.config)
+    log(f"[bench] workload {w.name}: {w.scene.n} Gaussians, {len(w.cams)} views, {w.n_pixels} pixels "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    params = DeviceParams.from_scene(w.scene)
+    pert = DeviceParams.from_scene(w.extra["perturbed"])
+
+    tile, batch, ppt = (16, 16), 64, 1
+    tuned = None
+    if args.tile:
+        tile = parse_tile(args.tile)
+    if args.batch_depth:
+        batch = args.batch_depth
+    if args.ppt:
+        ppt = args.ppt
+    if not args.tile and not args.batch_depth and not args.ppt and not args.no_autotune:
+        tuned = autotune(w.cams, params, pert, stream=stream, log=log)
+        tile, batch, ppt = tuned["tile"], tuned["batch_depth"], tuned["pixels_per_thread"]
+    log(f"[bench] tile {tile[0]}x{tile[1]}, batch depth {batch}, pixels per thread {ppt}")
+
+    r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, tile=tile, batch_depth=batch, loss_mode=1,
+                 pixels_per_thread=ppt)
+    need = r.fit_capacity(pert)
+    need = max(need, r.fit_capacity(params))
+    log(f"[bench] keys {need}, capacity {r.key_capacity}, workspace {r.ws.numel() / 2**30:.2f} GiB")
+    # targets: the perturbed model rendered by the same renderer
+    targets = r.forward(pert)[0].clone()
+    opt = Optimizer(r, params, targets, stream=stream)
+
+    # ---- batched, graph-replayed ------------------------------------------
+    opt.step()                       # eager warm-up (also loads kernels)
+    torch.cuda.synchronize()
+    opt.capture()
+    for _ in range(args.warmup):
+        opt.replay()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        opt.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_batched = ev0.elapsed_time(ev1) / args.steps
+    c = r.counters()
+    if c.overflow:
+        raise SystemExit("key capacity overflowed during the timed steps: measurement invalid")
+    log(f"[bench] batched graph: {ms_batched:.3f} ms/step ({1000 / ms_batched:.2f} steps/s), "
+        f"wall {t_wall / args.steps * 1000:.3f} ms/step, loss {opt.loss.item():.5f}")
+
+    # ---- plain: same kernels, one view per launch, eager ----------------------
+    ms_plain = None
+    if args.plain_steps > 0:
+        opt.step(plain=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.plain_steps):
+            opt.step(plain=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_plain = ev0.elapsed_time(ev1) / args.plain_steps
+        if r.counters().overflow:
+            raise SystemExit("key capacity overflowed in the plain path")
+        log(f"[bench] plain eager: {ms_plain:.3f} ms/step ({1000 / ms_plain:.2f} steps/s)")
+
+    # ---- stage timers (eager batched steps) -------------------------------
+    r.ctx.profile(True)
+    r.ctx.profile_reset()
+    nprof = 3
+    for _ in range(nprof):
+        opt.step()
+    stages = r.ctx.profile_read()
+    r.ctx.profile(False)
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1] > 0}
+    log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+    E, C = pair_counts(r, torch)
+    c = r.counters()
+    # dominant kernel and its roofline position
+    dom = max(("composite", "composite_bwd"), key=lambda k: stage_ms.get(k, 0.0))
+    per_c = FLOPS_FWD_COMPOSITED if dom == "composite" else FLOPS_BWD_COMPOSITED
+    flops = FLOPS_TEST * E + per_c * C
+    achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            if tj.get("kernel_stage") == dom and tj.get("source_hash") == _source_hash():
+                traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+            "units": {"examined_pairs": E, "composited_pairs": C,
+                      "flops_per_examined": FLOPS_TEST, "flops_per_composited": per_c},
+            "avg_ms": round(stage_ms[dom], 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        cpu = cpu_baseline(w, args.cpu_rows)
+        log(f"[bench] cpu baseline {cpu['value']:.3g} steps/s ({time.perf_counter() - t:.1f} s)")
+
+    out = {
+        "metric": METRIC, "value": round(1000.0 / ms_batched, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded; perturbed-copy targets rendered on the GPU)",
+        "config": {"workload": f"{w.name}: {w.scene.n} Gaussians SH{w.scene.sh_degree}, {len(w.cams)} views "
+                               f"({w.n_pixels} px, mixed 640x360/1280x720/1920x1080), batched step "
+                               "replayed from a HIP graph",
+                   "gaussians": w.scene.n, "views": len(w.cams), "pixels": w.n_pixels,
+                   "tile": f"{tile[0]}x{tile[1]}", "batch_depth": batch, "pixels_per_thread": ppt,
+                   "autotuned": tuned is not None,
+                   "keys": int(c.keys), "visible_pairs": int(c.visible), "parallelism": "1 GPU"},
+        "views_per_s": round(len(w.cams) * 1000.0 / ms_batched, 2),
+        "plain": None if ms_plain is None else {"value": round(1000.0 / ms_plain, 3), "unit": "steps/s",
+                                                "ms_per_step": round(ms_plain, 4)},
+        "batched_over_plain": None if ms_plain is None else round(ms_plain / ms_batched, 3),
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2604_02851_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -78,15 +78,18 @@ typedef struct {
 } gs_camera;
 
 /* Rendering options fixed at plan time.
- *  tile_w, tile_h : tile size in pixels, one of 8x8, 16x8, 16x16, 32x16, 32x32
- *  batch_depth    : splat records staged in LDS per batch: 32, 64, 128 or 256
- *  bg             : background colour added with the final transmittance
- *  loss_mode      : L1 reduction, 0 = sum over pixels and channels,
- *                   1 = mean per view (1/(3HW)), summed over views */
+ *  tile_w, tile_h    : tile size in pixels, one of 8x8, 16x8, 16x16, 32x16, 32x32
+ *  batch_depth       : splat records staged in LDS per batch: 32, 64 or 128
+ *  pixels_per_thread : 1, 2 or 4 (0 means 1); 8x8 tiles take 1, 16x8 tiles
+ *                      1 or 2; a workgroup has tile_w*tile_h/pixels_per_thread
+ *                      threads.  Results do not depend on any of these three.
+ *  bg                : background colour added with the final transmittance
+ *  loss_mode         : L1 reduction, 0 = sum over pixels and channels,
+ *                      1 = mean per view (1/(3HW)), summed over views */
 typedef struct {
   int32_t tile_w, tile_h;
   int32_t batch_depth;
-  int32_t reserved0;
+  int32_t pixels_per_thread;
   float bg[3];
   int32_t loss_mode;
 } gs_render_opts;
@@ -224,6 +227,16 @@ typedef enum {
 } gs_segment;
 gs_status gs_workspace_segment(gs_ctx ctx, int32_t which, int32_t view_begin, int32_t view_count,
                                size_t* offset, size_t* bytes);
+
+/* Stage timers: HIP events recorded around each stage's kernels on the
+ * stream of the call (eager calls only; capture ignores them).  Stages:
+ * "project", "tile_lists", "composite", "composite_bwd", "project_bwd",
+ * "adam", "delta".  gs_profile_read waits for the recorded events and returns
+ * the total milliseconds and number of timed calls since the last reset;
+ * unknown names give GS_ERR_INVALID. */
+gs_status gs_profile_enable(gs_ctx ctx, int32_t on);
+gs_status gs_profile_read(gs_ctx ctx, const char* stage, double* total_ms, int64_t* calls);
+gs_status gs_profile_reset(gs_ctx ctx);
 
 /* Synchronous: waits for `stream` and reads the counters of the last step. */
 gs_status gs_read_counters(gs_ctx ctx, const void* dev_workspace, hipStream_t stream, gs_counters* out);

@@ -11,7 +11,23 @@
 
 using namespace gs;
 
+namespace {
+constexpr int kStages = 7;
+const char* const kStageNames[kStages] = {"project", "tile_lists", "composite", "composite_bwd",
+                                          "project_bwd", "adam", "delta"};
+enum { ST_PROJECT, ST_LISTS, ST_COMPOSITE, ST_COMPOSITE_BWD, ST_PROJECT_BWD, ST_ADAM, ST_DELTA };
+struct PendingTimer {
+  int stage;
+  hipEvent_t start, stop;
+};
+}  // namespace
+
 struct gs_context {
+  bool prof = false;
+  bool capturing = false;
+  std::vector<PendingTimer> pending;
+  double stage_ms[kStages] = {0};
+  int64_t stage_calls[kStages] = {0};
   int device = 0;
   std::string err;
   Plan plan;
@@ -48,6 +64,43 @@ gs_status hip_check(gs_ctx c, hipError_t e, const char* what) {
     if (_s != GS_OK) return _s;                           \
   } while (0)
 
+// Runs f() (which enqueues kernels on st), bracketed by timing events when
+// the stage timers are on.
+template <class F>
+hipError_t timed(gs_ctx c, int stage, hipStream_t st, F&& f) {
+  if (!c->prof || c->capturing) return f();
+  PendingTimer t{stage, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&t.start);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&t.stop);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(t.start, st);
+  if (e != hipSuccess) return e;
+  e = f();
+  hipError_t e2 = hipEventRecord(t.stop, st);
+  c->pending.push_back(t);
+  return e != hipSuccess ? e : e2;
+}
+
+hipError_t flush_timers(gs_ctx c) {
+  hipError_t first = hipSuccess;
+  for (auto& t : c->pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(t.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.start, t.stop);
+    if (e == hipSuccess) {
+      c->stage_ms[t.stage] += ms;
+      c->stage_calls[t.stage] += 1;
+    } else if (first == hipSuccess) {
+      first = e;
+    }
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  c->pending.clear();
+  return first;
+}
+
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -61,7 +114,8 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   const int64_t vn = n * nviews;
   L.vn = vn;
   L.cap = cap;
-  const int64_t maxsort = vn > cap ? vn : cap;
+  int64_t maxsort = vn > cap ? vn : cap;
+  if (tiles > maxsort) maxsort = tiles;
   L.hist_blocks = cdiv(maxsort, kSortChunk);
   L.dblocks = (int32_t)cdiv(n, 256);
   int64_t maxscan = maxsort;
@@ -88,6 +142,10 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   L.hist = take(4 * (256 * L.hist_blocks + 1));
   L.partial = take(4 * L.partial_len);
   L.ranges = take(8 * tiles);
+  L.tkey_a = take(4 * tiles);
+  L.tkey_b = take(4 * tiles);
+  L.tval_a = take(4 * tiles);
+  L.tval_b = take(4 * tiles);
   L.last = take(4 * pixels);
   L.dflags = take(n);
   L.dcount = take(4 * (6ll * L.dblocks + 1));
@@ -153,6 +211,7 @@ gs_status gs_create(int32_t hip_device, gs_ctx* out) {
 
 gs_status gs_destroy(gs_ctx c) {
   if (!c) return GS_ERR_INVALID;
+  (void)flush_timers(c);
   if (c->exec) (void)hipGraphExecDestroy(c->exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->plan.d_views) (void)hipFree(c->plan.d_views);
@@ -175,8 +234,12 @@ gs_status gs_plan(gs_ctx c, int32_t n, int32_t sh_degree, int32_t n_views, const
   if (!tile_ok(opts->tile_w, opts->tile_h))
     return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: tile %dx%d not built", opts->tile_w, opts->tile_h);
   const int bd = opts->batch_depth;
-  if (bd != 32 && bd != 64 && bd != 128 && bd != 256)
-    return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: batch_depth=%d not in {32,64,128,256}", bd);
+  if (bd != 32 && bd != 64 && bd != 128)
+    return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: batch_depth=%d not in {32,64,128}", bd);
+  const int ppt = opts->pixels_per_thread == 0 ? 1 : opts->pixels_per_thread;
+  if (!raster_variant_built(opts->tile_w, opts->tile_h, ppt))
+    return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: %d pixels per thread not built for %dx%d tiles", ppt, opts->tile_w,
+                opts->tile_h);
   if (opts->loss_mode != 0 && opts->loss_mode != 1)
     return fail(c, GS_ERR_INVALID, "gs_plan: loss_mode=%d", opts->loss_mode);
   if (key_capacity < 1 || key_capacity > (int64_t)0x7fffffff)
@@ -190,6 +253,7 @@ gs_status gs_plan(gs_ctx c, int32_t n, int32_t sh_degree, int32_t n_views, const
   pl.tile_w = opts->tile_w;
   pl.tile_h = opts->tile_h;
   pl.batch_depth = bd;
+  pl.ppt = ppt;
   for (int k = 0; k < 3; ++k) pl.bg[k] = opts->bg[k];
   pl.loss_mode = opts->loss_mode;
   int64_t tiles = 0, pixels = 0;
@@ -259,7 +323,7 @@ gs_status gs_project(gs_ctx c, const gs_params* params, const gs_camera* cams, i
     Counters* ctr = seg<Counters>(ws, pl.ws.counters);
     GS_HIP(c, launch_fill_u32(&ctr->overflow, 0u, 1, st));
   }
-  GS_HIP(c, launch_project(pl, ptrs(params), cams, v0, nv, ws, st));
+  GS_HIP(c, timed(c, ST_PROJECT, st, [&] { return launch_project(pl, ptrs(params), cams, v0, nv, ws, st); }));
   return GS_OK;
 }
 
@@ -267,7 +331,7 @@ gs_status gs_build_tile_lists(gs_ctx c, int32_t v0, int32_t nv, void* ws, hipStr
   if (!c) return GS_ERR_INVALID;
   gs_status s = check_range(c, v0, nv, ws, "gs_build_tile_lists");
   if (s != GS_OK) return s;
-  GS_HIP(c, launch_tile_lists(c->plan, v0, nv, ws, st));
+  GS_HIP(c, timed(c, ST_LISTS, st, [&] { return launch_tile_lists(c->plan, v0, nv, ws, st); }));
   return GS_OK;
 }
 
@@ -277,7 +341,7 @@ gs_status gs_composite(gs_ctx c, int32_t v0, int32_t nv, void* ws, float* img, f
   gs_status s = check_range(c, v0, nv, ws, "gs_composite");
   if (s != GS_OK) return s;
   if (!img || !T || !nc) return fail(c, GS_ERR_INVALID, "gs_composite: null output");
-  GS_HIP(c, launch_composite(c->plan, v0, nv, ws, img, T, nc, st));
+  GS_HIP(c, timed(c, ST_COMPOSITE, st, [&] { return launch_composite(c->plan, v0, nv, ws, img, T, nc, st); }));
   return GS_OK;
 }
 
@@ -294,8 +358,11 @@ gs_status gs_backward(gs_ctx c, const gs_params* params, const gs_camera* cams, 
   if (mode == 1 && !loss) return fail(c, GS_ERR_INVALID, "gs_backward: mode 1 needs a loss pointer");
   if (accumulate != 0 && accumulate != 1) return fail(c, GS_ERR_INVALID, "gs_backward: accumulate=%d", accumulate);
   const Plan& pl = c->plan;
-  GS_HIP(c, launch_composite_bwd(pl, v0, nv, ws, img, T, up, mode, loss, st));
-  GS_HIP(c, launch_project_bwd(pl, ptrs(params), cams, v0, nv, ws, *grads, accumulate, st));
+  GS_HIP(c, timed(c, ST_COMPOSITE_BWD, st,
+                  [&] { return launch_composite_bwd(pl, v0, nv, ws, img, T, up, mode, loss, st); }));
+  GS_HIP(c, timed(c, ST_PROJECT_BWD, st, [&] {
+    return launch_project_bwd(pl, ptrs(params), cams, v0, nv, ws, *grads, accumulate, st);
+  }));
   return GS_OK;
 }
 
@@ -315,7 +382,7 @@ gs_status gs_adam_step(gs_ctx c, const gs_params* p, const gs_params* g, const g
   if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f && hp->eps >= 0.f))
     return fail(c, GS_ERR_INVALID, "gs_adam_step: betas must lie in [0,1) and eps >= 0");
   if (p->n == 0) return GS_OK;
-  GS_HIP(c, launch_adam(*p, *g, *m, *v, step, *hp, st));
+  GS_HIP(c, timed(c, ST_ADAM, st, [&] { return launch_adam(*p, *g, *m, *v, step, *hp, st); }));
   return GS_OK;
 }
 
@@ -340,7 +407,7 @@ gs_status gs_delta_extract(gs_ctx c, const gs_params* cur, const gs_params* base
     return fail(c, GS_ERR_INVALID, "gs_delta_extract: out_cap_words=%lld < %lld", (long long)cap_words,
                 (long long)need);
   if (need > (int64_t)0xffffffffll) return fail(c, GS_ERR_INVALID, "gs_delta_extract: output above 2^32 words");
-  GS_HIP(c, launch_delta(c->plan, *cur, *base, mask, tau, out, ws, st));
+  GS_HIP(c, timed(c, ST_DELTA, st, [&] { return launch_delta(c->plan, *cur, *base, mask, tau, out, ws, st); }));
   return GS_OK;
 }
 
@@ -384,6 +451,35 @@ gs_status gs_workspace_segment(gs_ctx c, int32_t which, int32_t v0, int32_t nv, 
     case GS_SEG_RANGES: *offset = L.ranges; *bytes = 8 * (size_t)pl.total_tiles; break;
     case GS_SEG_LAST: *offset = L.last; *bytes = 4 * (size_t)pl.total_pixels; break;
     default: return fail(c, GS_ERR_INVALID, "gs_workspace_segment: unknown segment %d", which);
+  }
+  return GS_OK;
+}
+
+gs_status gs_profile_enable(gs_ctx c, int32_t on) {
+  if (!c) return GS_ERR_INVALID;
+  c->prof = on != 0;
+  return GS_OK;
+}
+
+gs_status gs_profile_read(gs_ctx c, const char* stage, double* total_ms, int64_t* calls) {
+  if (!c || !stage || !total_ms || !calls) return GS_ERR_INVALID;
+  GS_HIP(c, flush_timers(c));
+  for (int k = 0; k < kStages; ++k) {
+    if (std::strcmp(stage, kStageNames[k]) == 0) {
+      *total_ms = c->stage_ms[k];
+      *calls = c->stage_calls[k];
+      return GS_OK;
+    }
+  }
+  return fail(c, GS_ERR_INVALID, "gs_profile_read: unknown stage '%s'", stage);
+}
+
+gs_status gs_profile_reset(gs_ctx c) {
+  if (!c) return GS_ERR_INVALID;
+  GS_HIP(c, flush_timers(c));
+  for (int k = 0; k < kStages; ++k) {
+    c->stage_ms[k] = 0.0;
+    c->stage_calls[k] = 0;
   }
   return GS_OK;
 }
@@ -450,7 +546,9 @@ gs_status gs_step_capture(gs_ctx c, const gs_step_args* a, hipStream_t st) {
   if (c->exec) { (void)hipGraphExecDestroy(c->exec); c->exec = nullptr; }
   if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
   GS_HIP(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
   gs_status s = run_step(c, a, st);
+  c->capturing = false;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(st, &g);
   if (s != GS_OK) {

@@ -76,14 +76,14 @@ __device__ __forceinline__ void sh_grad_accum(int deg, float x, float y, float z
 // FP32 camera depth evaluated in a fixed order with every operation rounded
 // on its own (no fused multiply-add), so that it equals the same expression
 // evaluated anywhere else in IEEE single precision.
-__device__ __noinline__ float depth_key(const gs_camera& c, float mx, float my, float mz) {
+__device__ __forceinline__ float depth_key(float r20, float r21, float r22, float t2, float mx, float my, float mz) {
 #pragma clang fp contract(off)
-  float a = c.R[6] * mx;
-  float b = c.R[7] * my;
+  float a = r20 * mx;
+  float b = r21 * my;
   float s = a + b;
-  float d = c.R[8] * mz;
+  float d = r22 * mz;
   s = s + d;
-  return s + c.t[2];
+  return s + t2;
 }
 
 struct Gauss {
@@ -96,6 +96,7 @@ struct Gauss {
   bool ok;
 };
 
+template <int DEG>
 __device__ __forceinline__ void load_gauss(const ParamPtrs& p, int64_t i, Gauss& g) {
   const int64_t n = p.n;
   bool fin = true;
@@ -108,7 +109,8 @@ __device__ __forceinline__ void load_gauss(const ParamPtrs& p, int64_t i, Gauss&
   for (int k = 0; k < 4; ++k) { q[k] = p.quat[k * n + i]; fin &= isfinite(q[k]); }
   const float w = p.opac[i];
   fin &= isfinite(w);
-  const int nsh = 3 * (p.deg + 1) * (p.deg + 1);
+  constexpr int nsh = 3 * (DEG + 1) * (DEG + 1);
+#pragma unroll
   for (int k = 0; k < nsh; ++k) fin &= isfinite(p.sh[k * n + i]);
   const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
   g.qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
@@ -202,19 +204,20 @@ struct ProjArgs {
   float4* g2;
 };
 
+template <int DEG>
 __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = a.p.n;
   if (i >= n) return;
   Gauss g;
-  load_gauss(a.p, i, g);
-  const int nk = (a.p.deg + 1) * (a.p.deg + 1);
+  load_gauss<DEG>(a.p, i, g);
+  constexpr int nk = (DEG + 1) * (DEG + 1);
   for (int v = a.v0; v < a.v0 + a.nv; ++v) {
     const int64_t o = (int64_t)v * n + i;
     const gs_camera cam = a.cams[v];
     uint32_t cnt = 0;
     if (g.ok) {
-      const float z32 = depth_key(cam, g.mu[0], g.mu[1], g.mu[2]);
+      const float z32 = depth_key(cam.R[6], cam.R[7], cam.R[8], cam.t[2], g.mu[0], g.mu[1], g.mu[2]);
       ViewGeom vg;
       if (z32 >= kNear && view_geom(g, cam, vg)) {
         const double slack = 1.0 + 0x1p-10;
@@ -238,10 +241,12 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
           float d[3], len;
           view_dir(cam, g.mu, d, &len);
           float Y[16];
-          sh_basis(a.p.deg, d[0], d[1], d[2], Y);
+          sh_basis(DEG, d[0], d[1], d[2], Y);
           float col[3];
+#pragma unroll
           for (int ch = 0; ch < 3; ++ch) {
             float s = 0.5f;
+#pragma unroll
             for (int k = 0; k < nk; ++k) s = fmaf(a.p.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], s);
             col[ch] = fmaxf(s, 0.f);
           }
@@ -269,16 +274,18 @@ struct ProjBwdArgs {
   int accumulate;
 };
 
+template <int DEG>
 __global__ __launch_bounds__(128) void k_project_bwd(ProjBwdArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = a.p.n;
   if (i >= n) return;
   Gauss g;
-  load_gauss(a.p, i, g);
-  const int nk = (a.p.deg + 1) * (a.p.deg + 1);
+  load_gauss<DEG>(a.p, i, g);
+  constexpr int nk = (DEG + 1) * (DEG + 1);
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
-  float gsh[48];
-  for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+  float gsh[3 * nk];
+#pragma unroll
+  for (int k = 0; k < 3 * nk; ++k) gsh[k] = 0.f;
   for (int v = a.v0; v < a.v0 + a.nv && g.ok; ++v) {
     const int64_t o = (int64_t)v * n + i;
     if (a.count[o] == 0) continue;
@@ -294,20 +301,24 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjBwdArgs a) {
     float d[3], len;
     view_dir(cam, g.mu, d, &len);
     float Y[16];
-    sh_basis(a.p.deg, d[0], d[1], d[2], Y);
+    sh_basis(DEG, d[0], d[1], d[2], Y);
     float wk[16];
+#pragma unroll
     for (int k = 0; k < 16; ++k) wk[k] = 0.f;
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       float s = 0.5f;
+#pragma unroll
       for (int k = 0; k < nk; ++k) s = fmaf(a.p.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], s);
       const float gcc = s > 0.f ? gcol[ch] : 0.f;
+#pragma unroll
       for (int k = 0; k < nk; ++k) {
         gsh[k * 3 + ch] += Y[k] * gcc;
         wk[k] += gcc * a.p.sh[(int64_t)(k * 3 + ch) * n + i];
       }
     }
     float gd[3] = {0.f, 0.f, 0.f};
-    sh_grad_accum(a.p.deg, d[0], d[1], d[2], wk, gd);
+    sh_grad_accum(DEG, d[0], d[1], d[2], wk, gd);
     const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
     for (int k = 0; k < 3; ++k) gm[k] += (double)((gd[k] - d[k] * dd) / len);
     // conic -> screen covariance: dL/dSigma2 = -Q G_Q Q
@@ -382,6 +393,7 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjBwdArgs a) {
   for (int k = 0; k < 3; ++k) put(&a.glsc[k * n + i], gs[k]);
   for (int k = 0; k < 4; ++k) put(&a.gquat[k * n + i], gq[k]);
   put(&a.gopac[i], go);
+#pragma unroll
   for (int k = 0; k < nk * 3; ++k) put(&a.gsh[(int64_t)k * n + i], gsh[k]);
 }
 
@@ -403,7 +415,14 @@ hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* c
   a.rec = seg<float4>(ws, pl.ws.rec);
   a.g2 = seg<float4>(ws, pl.ws.g2);
   const int blocks = (p.n + 255) / 256;
-  if (blocks > 0) hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, a);
+  if (blocks == 0) return hipSuccess;
+  switch (p.deg) {
+    case 0: hipLaunchKernelGGL(k_project<0>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_project<3>, dim3(blocks), dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -423,7 +442,14 @@ hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camer
   a.gsh = grads.sh;
   a.accumulate = accumulate;
   const int blocks = (p.n + 127) / 128;
-  if (blocks > 0) hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(128), 0, st, a);
+  if (blocks == 0) return hipSuccess;
+  switch (p.deg) {
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(blocks), dim3(128), 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(blocks), dim3(128), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(blocks), dim3(128), 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_project_bwd<3>, dim3(blocks), dim3(128), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

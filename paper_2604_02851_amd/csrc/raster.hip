@@ -1,24 +1,84 @@
 // Front-to-back compositing per tile and its adjoint.
 //
-// One workgroup per tile, one thread per pixel.  The tile's list is consumed
-// in batches of BATCH splat records staged in LDS (every pixel of the tile
-// reads every record, so a record is fetched from HBM once per tile).  The
-// forward pass stops a pixel once its transmittance would fall below 1e-4 and
-// the whole workgroup once every pixel has stopped; it saves T_final, the
-// contributor count and the last list position.  The backward pass walks the
-// same list back to front from each pixel's last position, rebuilding the
-// transmittance by division, and reduces each splat's screen-space gradient
-// over the 64 pixels of a wavefront before one LDS atomic per wavefront and
-// one global atomic per (tile, splat, field).
+// One workgroup per tile.  Each thread owns PPT pixels of the tile; each
+// wavefront owns a contiguous band of tile rows (TW x WROWS pixels).  The
+// tile's list is consumed in batches of BATCH splat records staged in LDS:
+// every pixel of the tile reads every record, so a record leaves HBM once per
+// tile.  Before evaluating a splat, a wavefront tests the splat's 3-sigma box
+// against its own band and skips it as a whole when they do not meet; the box
+// is widened so that it contains every pixel whose FP32 ellipse test can
+// pass, so skipping never changes a result.
+//
+// Forward: stops a pixel once its transmittance would fall below 1e-4 and
+// the workgroup once every pixel has stopped; saves T_final, the contributor
+// count and the last composited list position.
+// Backward: walks the list back to front from each pixel's last position,
+// rebuilding the transmittance by division; a splat's screen-space gradient
+// is summed over the thread's pixels in registers, then over the wavefront
+// with DPP row operations, then over the wavefronts of the tile in LDS, and
+// finally added once per (tile, splat, field) to the global accumulator.
 #include "internal.h"
 
 namespace gs {
 namespace {
 
+template <int TW, int TH, int PPT>
+struct Geom {
+  static constexpr int NT = TW * TH / PPT;       // threads per workgroup
+  static constexpr int NWAVES = NT / 64;
+  static constexpr int LROWS = 64 / TW;          // tile rows spanned by one pixel slot of a wave
+  static constexpr int WROWS = LROWS * PPT;      // tile rows owned by one wavefront
+  static_assert(NT % 64 == 0 && 64 % TW == 0 && NWAVES * WROWS == TH, "tile / pixels-per-thread shape");
+};
+
+// 3-sigma box of a splat in pixel-centre coordinates: (xmin, xmax, ymin, ymax).
+// With Q = [[a, a r], [a r, s + a r^2]], Sigma2_00 = 1/a + r^2/s and
+// Sigma2_11 = 1/s; the box is widened by 0.1% + 0.01 px for FP32 rounding.
+__device__ __forceinline__ float4 splat_box(const float4& r0, const float4& r1) {
+  const float sxx = 1.f / r1.x + r1.y * r1.y / r1.z;
+  const float syy = 1.f / r1.z;
+  const float hx = 3.003f * sqrtf(sxx) + 0.01f;
+  const float hy = 3.003f * sqrtf(syy) + 0.01f;
+  const float u = r0.x + r0.z, w = r0.y + r0.w;
+  return make_float4(u - hx, u + hx, w - hy, w + hy);
+}
+
+__device__ __forceinline__ bool box_misses(const float4& b, float xlo, float xhi, float ylo, float yhi) {
+  return b.x > xhi || b.y < xlo || b.z > yhi || b.w < ylo;
+}
+
+// Ranges are clamped to the key capacity so that a workspace whose lists were
+// never built cannot send a read past the key buffers.
+__device__ __forceinline__ uint2 clamp_range(uint2 rg, uint32_t cap) {
+  rg.y = min(rg.y, cap);
+  rg.x = min(rg.x, rg.y);
+  return rg;
+}
+
+// Sum over the 64 lanes: inclusive scan inside each row of 16 lanes, then the
+// row totals are carried across rows; lane 63 ends with the total.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int o = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false);
+  return v + __builtin_bit_cast(float, o);
+}
+
+__device__ __forceinline__ float wave_total_lane63(float v) {
+  v = dpp_add<0x111, 0xf>(v);   // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);   // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);   // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);   // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 struct CompArgs {
   const ViewInfo* views;
   const int32_t* tile_view;
+  const uint32_t* order;     // launch order: block b renders tile tile_begin + order[b]
   int32_t tile_begin;
+  int32_t ntiles;
   const uint2* ranges;
   const uint32_t* vals;
   const float4* rec;
@@ -30,76 +90,102 @@ struct CompArgs {
   float bg0, bg1, bg2;
 };
 
-// Ranges are clamped to the key capacity so that a workspace whose lists were
-// never built cannot send a read past the key buffers.
-__device__ __forceinline__ uint2 clamp_range(uint2 rg, uint32_t cap) {
-  rg.y = min(rg.y, cap);
-  rg.x = min(rg.x, rg.y);
-  return rg;
-}
-
-template <int TW, int TH, int BATCH>
-__global__ __launch_bounds__(TW* TH) void k_composite(CompArgs a) {
-  constexpr int NT = TW * TH;
+template <int TW, int TH, int PPT, int BATCH>
+__global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
+  using G = Geom<TW, TH, PPT>;
   __shared__ float4 s_rec[BATCH * 3];
-  const int t = a.tile_begin + blockIdx.x;
+  __shared__ float4 s_box[BATCH];
+  const uint32_t slot = a.order[blockIdx.x];
+  if (slot >= (uint32_t)a.ntiles) return;   // (whole workgroup) lists never built
+  const int t = a.tile_begin + (int)slot;
   const ViewInfo view = a.views[a.tile_view[t]];
   const int local = t - view.tile_base;
   const int ty = local / view.tiles_x, tx = local - ty * view.tiles_x;
-  const int px = tx * TW + (int)(threadIdx.x % TW), py = ty * TH + (int)(threadIdx.x / TW);
-  const bool inside = px < view.width && py < view.height;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x0 = tx * TW, y0 = ty * TH + wave * G::WROWS;
+  const int px = x0 + lane % TW, py0 = y0 + lane / TW;
+  const float xlo = (float)x0 + 0.5f, xhi = (float)(x0 + TW) - 0.5f;
+  const float ylo = (float)y0 + 0.5f, yhi = (float)(y0 + G::WROWS) - 0.5f;
   const uint2 rg = clamp_range(a.ranges[t], a.cap);
-  const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
-  float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-  uint32_t n = 0, last = rg.x;
-  bool done = !inside;
+  const float pxc = (float)px + 0.5f;
+  float T[PPT], c0[PPT], c1[PPT], c2[PPT];
+  uint32_t n[PPT], last[PPT];
+  bool done[PPT];
+  bool live = false;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    T[q] = 1.f;
+    c0[q] = c1[q] = c2[q] = 0.f;
+    n[q] = 0;
+    last[q] = rg.x;
+    done[q] = !(px < view.width && py0 + q * G::LROWS < view.height);
+    live |= !done[q];
+  }
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(live) == 0) break;
     const uint32_t cnt = min((uint32_t)BATCH, rg.y - b0);
-    for (uint32_t j = threadIdx.x; j < cnt; j += NT) {
+    for (uint32_t j = threadIdx.x; j < cnt; j += G::NT) {
       const uint32_t id = a.vals[b0 + j];
-      s_rec[j * 3 + 0] = a.rec[(size_t)id * 3 + 0];
-      s_rec[j * 3 + 1] = a.rec[(size_t)id * 3 + 1];
+      const float4 r0 = a.rec[(size_t)id * 3 + 0], r1 = a.rec[(size_t)id * 3 + 1];
+      s_rec[j * 3 + 0] = r0;
+      s_rec[j * 3 + 1] = r1;
       s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
+      s_box[j] = splat_box(r0, r1);
     }
     __syncthreads();
-    if (!done) {
+    if (live) {
       for (uint32_t j = 0; j < cnt; ++j) {
-        const SplatEval s = eval_splat(pxc, pyc, s_rec[j * 3], s_rec[j * 3 + 1]);
-        if (!s.inside) continue;
-        const float Tn = T * (1.f - s.alpha);
-        if (Tn < kTMin) {
-          done = true;
-          break;
+        if (box_misses(s_box[j], xlo, xhi, ylo, yhi)) continue;
+        const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          if (done[q]) continue;
+          const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
+          const SplatEval s = eval_splat(pxc, pyc, r0, r1);
+          if (!s.inside) continue;
+          const float Tn = T[q] * (1.f - s.alpha);
+          if (Tn < kTMin) {
+            done[q] = true;
+            continue;
+          }
+          const float4 r2 = s_rec[j * 3 + 2];
+          const float w = s.alpha * T[q];
+          c0[q] = fmaf(r2.x, w, c0[q]);
+          c1[q] = fmaf(r2.y, w, c1[q]);
+          c2[q] = fmaf(r2.z, w, c2[q]);
+          T[q] = Tn;
+          ++n[q];
+          last[q] = b0 + j + 1;
         }
-        const float4 r2 = s_rec[j * 3 + 2];
-        const float w = s.alpha * T;
-        c0 = fmaf(r2.x, w, c0);
-        c1 = fmaf(r2.y, w, c1);
-        c2 = fmaf(r2.z, w, c2);
-        T = Tn;
-        ++n;
-        last = b0 + j + 1;
       }
+      live = false;
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) live |= !done[q];
     }
   }
-  if (inside) {
-    const int64_t HW = (int64_t)view.width * view.height;
-    const int64_t p = (int64_t)py * view.width + px;
-    float* im = a.img + 3 * view.pix_off;
-    im[p] = fmaf(T, a.bg0, c0);
-    im[HW + p] = fmaf(T, a.bg1, c1);
-    im[2 * HW + p] = fmaf(T, a.bg2, c2);
-    a.T[view.pix_off + p] = T;
-    a.ncontrib[view.pix_off + p] = n;
-    a.last[view.pix_off + p] = last;
+  const int64_t HW = (int64_t)view.width * view.height;
+  float* im = a.img + 3 * view.pix_off;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int py = py0 + q * G::LROWS;
+    if (px < view.width && py < view.height) {
+      const int64_t p = (int64_t)py * view.width + px;
+      im[p] = fmaf(T[q], a.bg0, c0[q]);
+      im[HW + p] = fmaf(T[q], a.bg1, c1[q]);
+      im[2 * HW + p] = fmaf(T[q], a.bg2, c2[q]);
+      a.T[view.pix_off + p] = T[q];
+      a.ncontrib[view.pix_off + p] = n[q];
+      a.last[view.pix_off + p] = last[q];
+    }
   }
 }
 
 struct BwdArgs {
   const ViewInfo* views;
   const int32_t* tile_view;
+  const uint32_t* order;
   int32_t tile_begin;
+  int32_t ntiles;
   const uint2* ranges;
   const uint32_t* vals;
   const float4* rec;
@@ -115,145 +201,190 @@ struct BwdArgs {
   float bg0, bg1, bg2;
 };
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
-
-template <int TW, int TH, int BATCH>
-__global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs a) {
-  constexpr int NT = TW * TH;
+template <int TW, int TH, int PPT, int BATCH>
+__global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
+  using G = Geom<TW, TH, PPT>;
+  constexpr bool kMultiWave = G::NWAVES > 1;
   __shared__ float4 s_rec[BATCH * 3];
+  __shared__ float4 s_box[BATCH];
   __shared__ uint32_t s_id[BATCH];
-  __shared__ float s_g[BATCH * 9];
+  __shared__ float s_g[kMultiWave ? BATCH * 9 : 1];
   __shared__ uint32_t s_max;
-  const int t = a.tile_begin + blockIdx.x;
+  const uint32_t slot = a.order[blockIdx.x];
+  if (slot >= (uint32_t)a.ntiles) return;   // (whole workgroup) lists never built
+  const int t = a.tile_begin + (int)slot;
   const ViewInfo view = a.views[a.tile_view[t]];
   const int local = t - view.tile_base;
   const int ty = local / view.tiles_x, tx = local - ty * view.tiles_x;
-  const int px = tx * TW + (int)(threadIdx.x % TW), py = ty * TH + (int)(threadIdx.x / TW);
-  const bool inside = px < view.width && py < view.height;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x0 = tx * TW, y0 = ty * TH + wave * G::WROWS;
+  const int px = x0 + lane % TW, py0 = y0 + lane / TW;
+  const float xlo = (float)x0 + 0.5f, xhi = (float)(x0 + TW) - 0.5f;
+  const float ylo = (float)y0 + 0.5f, yhi = (float)(y0 + G::WROWS) - 0.5f;
   const uint2 rg = clamp_range(a.ranges[t], a.cap);
-  const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
-  const int lane = threadIdx.x & 63;
+  const float pxc = (float)px + 0.5f;
+  const int64_t HW = (int64_t)view.width * view.height;
+  const float wv = a.loss_mode == 1 ? 1.f / (3.f * (float)HW) : 1.f;
   if (threadIdx.x == 0) s_max = rg.x;
   __syncthreads();
-  float G0 = 0.f, G1 = 0.f, G2 = 0.f, lossv = 0.f, T = 1.f;
-  uint32_t my_last = rg.x;
-  if (inside) {
-    const int64_t HW = (int64_t)view.width * view.height;
-    const int64_t p = (int64_t)py * view.width + px;
-    const int64_t ib = 3 * view.pix_off + p;
-    if (a.mode == 0) {
-      G0 = a.up[ib];
-      G1 = a.up[ib + HW];
-      G2 = a.up[ib + 2 * HW];
-    } else {
-      const float wv = a.loss_mode == 1 ? 1.f / (3.f * (float)HW) : 1.f;
-      const float d0 = a.img[ib] - a.up[ib];
-      const float d1 = a.img[ib + HW] - a.up[ib + HW];
-      const float d2 = a.img[ib + 2 * HW] - a.up[ib + 2 * HW];
-      G0 = wv * (float)((d0 > 0.f) - (d0 < 0.f));
-      G1 = wv * (float)((d1 > 0.f) - (d1 < 0.f));
-      G2 = wv * (float)((d2 > 0.f) - (d2 < 0.f));
-      lossv = wv * (fabsf(d0) + fabsf(d1) + fabsf(d2));
+  float G0[PPT], G1[PPT], G2[PPT], T[PPT], S0[PPT], S1[PPT], S2[PPT];
+  uint32_t last[PPT];
+  float lossv = 0.f;
+  uint32_t my_max = rg.x;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    G0[q] = G1[q] = G2[q] = 0.f;
+    T[q] = 1.f;
+    S0[q] = a.bg0;
+    S1[q] = a.bg1;
+    S2[q] = a.bg2;
+    last[q] = rg.x;
+    const int py = py0 + q * G::LROWS;
+    if (px < view.width && py < view.height) {
+      const int64_t p = (int64_t)py * view.width + px;
+      const int64_t ib = 3 * view.pix_off + p;
+      if (a.mode == 0) {
+        G0[q] = a.up[ib];
+        G1[q] = a.up[ib + HW];
+        G2[q] = a.up[ib + 2 * HW];
+      } else {
+        const float d0 = a.img[ib] - a.up[ib];
+        const float d1 = a.img[ib + HW] - a.up[ib + HW];
+        const float d2 = a.img[ib + 2 * HW] - a.up[ib + 2 * HW];
+        G0[q] = wv * (float)((d0 > 0.f) - (d0 < 0.f));
+        G1[q] = wv * (float)((d1 > 0.f) - (d1 < 0.f));
+        G2[q] = wv * (float)((d2 > 0.f) - (d2 < 0.f));
+        lossv += wv * (fabsf(d0) + fabsf(d1) + fabsf(d2));
+      }
+      T[q] = a.T[view.pix_off + p];
+      last[q] = min(max(a.last[view.pix_off + p], rg.x), rg.y);
+      my_max = max(my_max, last[q]);
     }
-    T = a.T[view.pix_off + p];
-    my_last = min(max(a.last[view.pix_off + p], rg.x), rg.y);
-    atomicMax(&s_max, my_last);
   }
-  float S0 = a.bg0, S1 = a.bg1, S2 = a.bg2;
+  atomicMax(&s_max, my_max);
   __syncthreads();
   const uint32_t end_all = s_max;
   for (uint32_t b_end = end_all; b_end > rg.x;) {
     const uint32_t b_begin = (b_end - rg.x > (uint32_t)BATCH) ? b_end - BATCH : rg.x;
     const uint32_t cnt = b_end - b_begin;
-    for (uint32_t j = threadIdx.x; j < cnt; j += NT) {
+    for (uint32_t j = threadIdx.x; j < cnt; j += G::NT) {
       const uint32_t id = a.vals[b_begin + j];
+      const float4 r0 = a.rec[(size_t)id * 3 + 0], r1 = a.rec[(size_t)id * 3 + 1];
       s_id[j] = id;
-      s_rec[j * 3 + 0] = a.rec[(size_t)id * 3 + 0];
-      s_rec[j * 3 + 1] = a.rec[(size_t)id * 3 + 1];
+      s_rec[j * 3 + 0] = r0;
+      s_rec[j * 3 + 1] = r1;
       s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
+      s_box[j] = splat_box(r0, r1);
     }
-    for (uint32_t q = threadIdx.x; q < cnt * 9; q += NT) s_g[q] = 0.f;
+    if (kMultiWave)
+      for (uint32_t q = threadIdx.x; q < cnt * 9; q += G::NT) s_g[q] = 0.f;
     __syncthreads();
     for (int j = (int)cnt - 1; j >= 0; --j) {
+      if (box_misses(s_box[j], xlo, xhi, ylo, yhi)) continue;
+      const uint32_t pos = b_begin + (uint32_t)j;
+      const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1];
       float g[9];
 #pragma unroll
       for (int f = 0; f < 9; ++f) g[f] = 0.f;
       bool contrib = false;
-      if (inside && b_begin + (uint32_t)j < my_last) {
-        const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1];
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        if (pos >= last[q]) continue;
+        const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
         const SplatEval s = eval_splat(pxc, pyc, r0, r1);
-        if (s.inside) {
-          contrib = true;
-          const float4 r2 = s_rec[j * 3 + 2];
-          const float al = s.alpha;
-          const float Tj = T / (1.f - al);
-          const float at = al * Tj;
-          g[6] = at * G0;
-          g[7] = at * G1;
-          g[8] = at * G2;
-          const float dLda = Tj * ((r2.x - S0) * G0 + (r2.y - S1) * G1 + (r2.z - S2) * G2);
-          S0 = fmaf(al, r2.x - S0, S0);
-          S1 = fmaf(al, r2.y - S1, S1);
-          S2 = fmaf(al, r2.z - S2, S2);
-          T = Tj;
-          if (!s.clamped) {
-            const float dLdP = dLda * al;
-            g[5] = dLda * s.G;
-            const float ae = r1.x * s.e;
-            g[0] = dLdP * ae;
-            g[1] = dLdP * fmaf(ae, r1.y, r1.z * s.dy);
-            g[2] = -0.5f * dLdP * s.dx * s.dx;
-            g[3] = -dLdP * s.dx * s.dy;
-            g[4] = -0.5f * dLdP * s.dy * s.dy;
-          }
+        if (!s.inside) continue;
+        contrib = true;
+        const float4 r2 = s_rec[j * 3 + 2];
+        const float al = s.alpha;
+        const float Tj = T[q] * __builtin_amdgcn_rcpf(1.f - al);
+        const float at = al * Tj;
+        g[6] = fmaf(at, G0[q], g[6]);
+        g[7] = fmaf(at, G1[q], g[7]);
+        g[8] = fmaf(at, G2[q], g[8]);
+        const float dLda = Tj * ((r2.x - S0[q]) * G0[q] + (r2.y - S1[q]) * G1[q] + (r2.z - S2[q]) * G2[q]);
+        S0[q] = fmaf(al, r2.x - S0[q], S0[q]);
+        S1[q] = fmaf(al, r2.y - S1[q], S1[q]);
+        S2[q] = fmaf(al, r2.z - S2[q], S2[q]);
+        T[q] = Tj;
+        if (!s.clamped) {
+          const float dLdP = dLda * al;
+          g[5] = fmaf(dLda, s.G, g[5]);
+          const float ae = r1.x * s.e;
+          g[0] = fmaf(dLdP, ae, g[0]);
+          g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * s.dy), g[1]);
+          const float hm = -0.5f * dLdP;
+          g[2] = fmaf(hm * s.dx, s.dx, g[2]);
+          g[3] = fmaf(2.f * hm * s.dx, s.dy, g[3]);
+          g[4] = fmaf(hm * s.dy, s.dy, g[4]);
         }
       }
-      if (__ballot(contrib) != 0ull) {
+      if (__ballot(contrib) == 0ull) continue;
 #pragma unroll
-        for (int f = 0; f < 9; ++f) g[f] = wave_sum(g[f]);
-        if (lane == 0) {
+      for (int f = 0; f < 9; ++f) g[f] = wave_total_lane63(g[f]);
+      if (lane == 63) {
+        if (kMultiWave) {
 #pragma unroll
           for (int f = 0; f < 9; ++f) atomicAdd(&s_g[j * 9 + f], g[f]);
+        } else {
+          float* dst = a.g2 + (size_t)s_id[j] * kG2Stride;
+#pragma unroll
+          for (int f = 0; f < 9; ++f)
+            if (g[f] != 0.f) atomicAdd(dst + f, g[f]);
         }
       }
     }
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < cnt * 9; q += NT) {
-      const float v = s_g[q];
-      if (v != 0.f) atomicAdd(&a.g2[(size_t)s_id[q / 9] * kG2Stride + (q % 9)], v);
+    if (kMultiWave) {
+      for (uint32_t q = threadIdx.x; q < cnt * 9; q += G::NT) {
+        const float v = s_g[q];
+        if (v != 0.f) atomicAdd(&a.g2[(size_t)s_id[q / 9] * kG2Stride + (q % 9)], v);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     b_end = b_begin;
   }
   if (a.mode == 1) {
-    lossv = wave_sum(lossv);
-    if (lane == 0 && lossv != 0.f) atomicAdd(a.loss, lossv);
+    lossv = wave_total_lane63(lossv);
+    if (lane == 63 && lossv != 0.f) atomicAdd(a.loss, lossv);
   }
 }
 
-template <int TW, int TH>
-hipError_t comp_batch(int batch, dim3 grid, hipStream_t st, const CompArgs& a) {
+// ---- dispatch over the built (tile, pixels-per-thread, batch) variants ----
+#define GS_RASTER_LIST(X) \
+  X(8, 8, 1)              \
+  X(16, 8, 1)             \
+  X(16, 8, 2)             \
+  X(16, 16, 1)            \
+  X(16, 16, 2)            \
+  X(16, 16, 4)            \
+  X(32, 16, 1)            \
+  X(32, 16, 2)            \
+  X(32, 16, 4)            \
+  X(32, 32, 1)            \
+  X(32, 32, 2)            \
+  X(32, 32, 4)            \
+  X(32, 16, 8)            \
+  X(32, 32, 8)
+
+template <int TW, int TH, int PPT, typename Args>
+hipError_t launch_fwd(int batch, dim3 grid, hipStream_t st, const Args& a) {
+  constexpr int NT = TW * TH / PPT;
   switch (batch) {
-    case 32: hipLaunchKernelGGL((k_composite<TW, TH, 32>), grid, dim3(TW * TH), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((k_composite<TW, TH, 64>), grid, dim3(TW * TH), 0, st, a); break;
-    case 128: hipLaunchKernelGGL((k_composite<TW, TH, 128>), grid, dim3(TW * TH), 0, st, a); break;
-    case 256: hipLaunchKernelGGL((k_composite<TW, TH, 256>), grid, dim3(TW * TH), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_composite<TW, TH, PPT, 32>), grid, dim3(NT), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((k_composite<TW, TH, PPT, 64>), grid, dim3(NT), 0, st, a); break;
+    case 128: hipLaunchKernelGGL((k_composite<TW, TH, PPT, 128>), grid, dim3(NT), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <int TW, int TH>
-hipError_t bwd_batch(int batch, dim3 grid, hipStream_t st, const BwdArgs& a) {
+template <int TW, int TH, int PPT, typename Args>
+hipError_t launch_bwd(int batch, dim3 grid, hipStream_t st, const Args& a) {
+  constexpr int NT = TW * TH / PPT;
   switch (batch) {
-    case 32: hipLaunchKernelGGL((k_composite_bwd<TW, TH, 32>), grid, dim3(TW * TH), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((k_composite_bwd<TW, TH, 64>), grid, dim3(TW * TH), 0, st, a); break;
-    case 128: hipLaunchKernelGGL((k_composite_bwd<TW, TH, 128>), grid, dim3(TW * TH), 0, st, a); break;
-    case 256: hipLaunchKernelGGL((k_composite_bwd<TW, TH, 256>), grid, dim3(TW * TH), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, 32>), grid, dim3(NT), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, 64>), grid, dim3(NT), 0, st, a); break;
+    case 128: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, 128>), grid, dim3(NT), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -266,6 +397,14 @@ void tile_span(const Plan& pl, int v0, int nv, int32_t* tb, int32_t* ntiles) {
 }
 
 }  // namespace
+
+bool raster_variant_built(int tw, int th, int ppt) {
+#define GS_HAS(W, H, P) \
+  if (tw == W && th == H && ppt == P) return true;
+  GS_RASTER_LIST(GS_HAS)
+#undef GS_HAS
+  return false;
+}
 
 bool sorted_values_in_b(const Plan& pl, int v0, int nv) {
   const int32_t tb = pl.views[v0].tile_base;
@@ -281,8 +420,10 @@ hipError_t launch_composite(const Plan& pl, int v0, int nv, void* ws, float* img
   CompArgs a;
   a.views = pl.d_views;
   a.tile_view = pl.d_tile_view;
+  a.order = seg<uint32_t>(ws, pl.ws.tval_a);
   int32_t ntiles;
   tile_span(pl, v0, nv, &a.tile_begin, &ntiles);
+  a.ntiles = ntiles;
   a.ranges = seg<uint2>(ws, pl.ws.ranges);
   a.vals = seg<uint32_t>(ws, sorted_values_in_b(pl, v0, nv) ? pl.ws.vals_b : pl.ws.vals_a);
   a.rec = seg<float4>(ws, pl.ws.rec);
@@ -296,12 +437,11 @@ hipError_t launch_composite(const Plan& pl, int v0, int nv, void* ws, float* img
   a.bg2 = pl.bg[2];
   if (ntiles <= 0) return hipSuccess;
   const dim3 grid(ntiles);
-  const int tw = pl.tile_w, th = pl.tile_h, b = pl.batch_depth;
-  if (tw == 8 && th == 8) return comp_batch<8, 8>(b, grid, st, a);
-  if (tw == 16 && th == 8) return comp_batch<16, 8>(b, grid, st, a);
-  if (tw == 16 && th == 16) return comp_batch<16, 16>(b, grid, st, a);
-  if (tw == 32 && th == 16) return comp_batch<32, 16>(b, grid, st, a);
-  if (tw == 32 && th == 32) return comp_batch<32, 32>(b, grid, st, a);
+  const int tw = pl.tile_w, th = pl.tile_h, ppt = pl.ppt, b = pl.batch_depth;
+#define GS_FWD(W, H, P) \
+  if (tw == W && th == H && ppt == P) return launch_fwd<W, H, P>(b, grid, st, a);
+  GS_RASTER_LIST(GS_FWD)
+#undef GS_FWD
   return hipErrorInvalidValue;
 }
 
@@ -310,8 +450,10 @@ hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const 
   BwdArgs a;
   a.views = pl.d_views;
   a.tile_view = pl.d_tile_view;
+  a.order = seg<uint32_t>(ws, pl.ws.tval_a);
   int32_t ntiles;
   tile_span(pl, v0, nv, &a.tile_begin, &ntiles);
+  a.ntiles = ntiles;
   a.ranges = seg<uint2>(ws, pl.ws.ranges);
   a.vals = seg<uint32_t>(ws, sorted_values_in_b(pl, v0, nv) ? pl.ws.vals_b : pl.ws.vals_a);
   a.rec = seg<float4>(ws, pl.ws.rec);
@@ -329,12 +471,11 @@ hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const 
   a.bg2 = pl.bg[2];
   if (ntiles <= 0) return hipSuccess;
   const dim3 grid(ntiles);
-  const int tw = pl.tile_w, th = pl.tile_h, b = pl.batch_depth;
-  if (tw == 8 && th == 8) return bwd_batch<8, 8>(b, grid, st, a);
-  if (tw == 16 && th == 8) return bwd_batch<16, 8>(b, grid, st, a);
-  if (tw == 16 && th == 16) return bwd_batch<16, 16>(b, grid, st, a);
-  if (tw == 32 && th == 16) return bwd_batch<32, 16>(b, grid, st, a);
-  if (tw == 32 && th == 32) return bwd_batch<32, 32>(b, grid, st, a);
+  const int tw = pl.tile_w, th = pl.tile_h, ppt = pl.ppt, b = pl.batch_depth;
+#define GS_BWD(W, H, P) \
+  if (tw == W && th == H && ppt == P) return launch_bwd<W, H, P>(b, grid, st, a);
+  GS_RASTER_LIST(GS_BWD)
+#undef GS_BWD
   return hipErrorInvalidValue;
 }
 

@@ -220,24 +220,55 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
 }
 
 // ---- key emission in depth order -----------------------------------------
+// One wavefront writes the keys of 64 consecutive depth-sorted visible pairs:
+// lane l produces output slots start + l, start + l + 64, ... (coalesced),
+// and finds the pair owning a slot by binary search over the 64 start
+// offsets, so a pair touching many tiles does not serialise its wavefront.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const uint32_t* koff, const uint32_t* nvis_p,
-                                              const ushort4* rect, const ViewInfo* views, int64_t n_gauss,
-                                              int32_t tile_begin, uint32_t cap, uint32_t* keys, uint32_t* vals) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= *nvis_p) return;
-  const uint32_t vi = sorted_vis[k];
-  const int v = (int)(vi / (uint64_t)n_gauss);
-  const ViewInfo view = views[v];
-  const ushort4 r = rect[vi];
-  uint32_t pos = koff[k];
-  for (int ty = r.y; ty <= r.w; ++ty) {
-    const int32_t row = view.tile_base + ty * view.tiles_x - tile_begin;
-    for (int tx = r.x; tx <= r.z; ++tx) {
-      if (pos < cap) {
-        keys[pos] = (uint32_t)(row + tx);
-        vals[pos] = vi;
-      }
-      ++pos;
+                                              const uint32_t* count, const ushort4* rect, const ViewInfo* views,
+                                              int64_t n_gauss, int32_t tile_begin, uint32_t cap, uint32_t* keys,
+                                              uint32_t* vals) {
+  __shared__ uint32_t s_off[4][64];
+  __shared__ uint32_t s_vi[4][64];
+  __shared__ ushort4 s_rect[4][64];
+  __shared__ int32_t s_row[4][64];   // first tile of the pair's view, relative to the call's first tile
+  __shared__ int32_t s_tx[4][64];    // tiles per row in the pair's view
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t nvis = *nvis_p;
+  const uint32_t k0 = (blockIdx.x * 4u + (uint32_t)w) * 64u;
+  const uint32_t nent = k0 < nvis ? min(64u, nvis - k0) : 0u;
+  const bool valid = (uint32_t)lane < nent;
+  uint32_t off = 0xffffffffu, end = 0;
+  if (valid) {
+    const uint32_t vi = sorted_vis[k0 + lane];
+    off = koff[k0 + lane];
+    end = off + count[vi];
+    const int v = (int)(vi / (uint64_t)n_gauss);
+    s_vi[w][lane] = vi;
+    s_rect[w][lane] = rect[vi];
+    s_row[w][lane] = views[v].tile_base - tile_begin;
+    s_tx[w][lane] = views[v].tiles_x;
+  }
+  s_off[w][lane] = off;
+  __syncthreads();
+  if (nent == 0) return;
+  const uint32_t start = s_off[w][0];
+  uint32_t stop = end;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) stop = max(stop, (uint32_t)__shfl_xor((int)stop, d, 64));
+  for (uint32_t slot = start + (uint32_t)lane; slot < stop; slot += 64) {
+    int lo = 0, hi = (int)nent - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[w][mid] <= slot) lo = mid; else hi = mid - 1;
+    }
+    const ushort4 r = s_rect[w][lo];
+    const uint32_t m = slot - s_off[w][lo];
+    const uint32_t width = (uint32_t)r.z - r.x + 1u;
+    const uint32_t ty = r.y + m / width, tx = r.x + m % width;
+    if (slot < cap) {
+      keys[slot] = (uint32_t)(s_row[w][lo] + (int32_t)(ty * (uint32_t)s_tx[w][lo] + tx));
+      vals[slot] = s_vi[w][lo];
     }
   }
 }
@@ -254,11 +285,23 @@ __global__ void k_key_total(Counters* c, const uint32_t* total_keys, uint32_t ca
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys, const uint32_t* count_p, uint32_t cap,
                                                 int32_t tile_begin, uint2* ranges) {
   const uint32_t n = min(*count_p, cap);
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const uint32_t t = keys[k];
-  if (k == 0 || keys[k - 1] != t) ranges[tile_begin + t].x = k;
-  if (k == n - 1 || keys[k + 1] != t) ranges[tile_begin + t].y = k + 1;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const uint32_t t = keys[k];
+    if (k == 0 || keys[k - 1] != t) ranges[tile_begin + t].x = k;
+    if (k == n - 1 || keys[k + 1] != t) ranges[tile_begin + t].y = k + 1;
+  }
+}
+
+// Sort keys that put the longest tile lists first (tile order of the
+// compositing launches, so that the longest tiles start earliest).
+__global__ __launch_bounds__(256) void k_tile_order_keys(const uint2* ranges, int32_t tile_begin, int32_t ntiles,
+                                                         uint32_t* tkey, uint32_t* tval) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const uint2 r = ranges[tile_begin + t];
+  const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
+  tkey[t] = 0xffffu - min(len, 0xffffu);
+  tval[t] = (uint32_t)t;
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -337,9 +380,6 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   const uint32_t cap = (uint32_t)pl.cap;
   hipError_t e;
   if (len == 0) return hipSuccess;
-  // counters of this build
-  e = launch_fill_u32(&ctr->overflow, 0u, 1, st);
-  if (e != hipSuccess) return e;
   // 1. visible compaction in (view, Gaussian) order: positions -> koff (scratch)
   e = scan_src(ScanSrc{count + base, nullptr, 1}, koff, len, nullptr, partial, pl.ws.partial_len, &ctr->nvis, st);
   if (e != hipSuccess) return e;
@@ -358,7 +398,7 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   // 4. emit (tile, value) pairs in depth order
   const int32_t tile_begin = pl.views[v0].tile_base;
   const int32_t tile_end = (v0 + nv < pl.n_views) ? pl.views[v0 + nv].tile_base : pl.total_tiles;
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, sorted_vis, koff, &ctr->nvis,
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, sorted_vis, koff, &ctr->nvis, count,
                      seg<ushort4>(ws, pl.ws.rect), pl.d_views, N, tile_begin, cap, keys_a, vals_a);
   // 5. stable sort by tile (relative to the first tile of the call)
   const int64_t ntiles = tile_end - tile_begin;
@@ -371,8 +411,17 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges + tile_begin), 0u, 2 * ntiles, st);
   if (e != hipSuccess) return e;
   const uint32_t* sk = in_b ? keys_b : keys_a;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)cdiv(pl.cap, 256)), dim3(256), 0, st, sk, &ctr->keys, cap, tile_begin,
-                     ranges);
+  const int64_t rblocks = cdiv(pl.cap, 256) < 8192 ? cdiv(pl.cap, 256) : 8192;
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)rblocks), dim3(256), 0, st, sk, &ctr->keys, cap, tile_begin, ranges);
+  // 7. launch order of the tiles: longest lists first
+  uint32_t* tkey_a = seg<uint32_t>(ws, pl.ws.tkey_a);
+  uint32_t* tkey_b = seg<uint32_t>(ws, pl.ws.tkey_b);
+  uint32_t* tval_a = seg<uint32_t>(ws, pl.ws.tval_a);
+  uint32_t* tval_b = seg<uint32_t>(ws, pl.ws.tval_b);
+  hipLaunchKernelGGL(k_tile_order_keys, dim3((unsigned)cdiv(ntiles, 256)), dim3(256), 0, st, ranges, tile_begin,
+                     (int32_t)ntiles, tkey_a, tval_a);
+  e = radix_sort(pl, ws, tkey_a, tval_a, tkey_b, tval_b, ntiles, nullptr, 16, &in_b, st);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS
 EXPORTED = ("gs_create", "gs_destroy", "gs_last_error", "gs_plan", "gs_frame_layout", "gs_project",
             "gs_build_tile_lists", "gs_composite", "gs_backward", "gs_adam_step", "gs_delta_extract",
             "gs_delta_reset_baseline", "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
-            "gs_step_launch")
+            "gs_step_launch", "gs_profile_enable", "gs_profile_read", "gs_profile_reset")
+STAGES = ("project", "tile_lists", "composite", "composite_bwd", "project_bwd", "adam", "delta")
 SEG = {"depth": 0, "count": 1, "rect": 2, "record": 3, "grad2d": 4, "sorted_values": 5, "ranges": 6, "last": 7}
 
 
@@ -39,7 +40,7 @@ class GsParams(ctypes.Structure):
 
 
 class GsRenderOpts(ctypes.Structure):
-    _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("batch_depth", c_int32), ("reserved0", c_int32),
+    _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("batch_depth", c_int32), ("pixels_per_thread", c_int32),
                 ("bg", c_float * 3), ("loss_mode", c_int32)]
 
 
@@ -93,6 +94,9 @@ def lib() -> ctypes.CDLL:
         L.gs_delta_reset_baseline.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), c_void_p, c_void_p]
         L.gs_read_counters.argtypes = [ctx, c_void_p, c_void_p, POINTER(GsCounters)]
         L.gs_workspace_segment.argtypes = [ctx, c_int32, c_int32, c_int32, POINTER(c_size_t), POINTER(c_size_t)]
+        L.gs_profile_enable.argtypes = [ctx, c_int32]
+        L.gs_profile_read.argtypes = [ctx, ctypes.c_char_p, POINTER(ctypes.c_double), POINTER(c_int64)]
+        L.gs_profile_reset.argtypes = [ctx]
         L.gs_step.argtypes = [ctx, POINTER(GsStepArgs), c_void_p]
         L.gs_step_capture.argtypes = [ctx, POINTER(GsStepArgs), c_void_p]
         L.gs_step_launch.argtypes = [ctx, POINTER(GsStepArgs), c_void_p]
@@ -180,9 +184,9 @@ class Context:
             raise GsError(s, self.L.gs_last_error(self.h).decode())
 
     def plan(self, n, sh_degree, cams: np.ndarray, tile=(16, 16), batch_depth=64, bg=(0.0, 0.0, 0.0),
-             loss_mode=0, key_capacity=1 << 20) -> int:
+             loss_mode=0, key_capacity=1 << 20, pixels_per_thread=1) -> int:
         cams = np.ascontiguousarray(cams)
-        opts = GsRenderOpts(tile[0], tile[1], batch_depth, 0, (c_float * 3)(*bg), loss_mode)
+        opts = GsRenderOpts(tile[0], tile[1], batch_depth, pixels_per_thread, (c_float * 3)(*bg), loss_mode)
         out = c_size_t()
         self._chk(self.L.gs_plan(self.h, n, sh_degree, len(cams), cams.ctypes.data_as(c_void_p), ctypes.byref(opts),
                                  int(key_capacity), ctypes.byref(out)))
@@ -240,6 +244,20 @@ class Context:
         off, nb = c_size_t(), c_size_t()
         self._chk(self.L.gs_workspace_segment(self.h, SEG[name], v0, nv, ctypes.byref(off), ctypes.byref(nb)))
         return ws[off.value: off.value + nb.value]
+
+    def profile(self, on: bool = True):
+        self._chk(self.L.gs_profile_enable(self.h, 1 if on else 0))
+
+    def profile_reset(self):
+        self._chk(self.L.gs_profile_reset(self.h))
+
+    def profile_read(self) -> dict:
+        out = {}
+        for s in STAGES:
+            ms, calls = ctypes.c_double(), c_int64()
+            self._chk(self.L.gs_profile_read(self.h, s.encode(), ctypes.byref(ms), ctypes.byref(calls)))
+            out[s] = (float(ms.value), int(calls.value))
+        return out
 
     def step(self, args: GsStepArgs, stream=None):
         self._chk(self.L.gs_step(self.h, ctypes.byref(args), stream_handle(stream)))

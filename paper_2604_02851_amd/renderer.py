@@ -6,6 +6,8 @@ libgsopt.so.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import torch
 
@@ -22,12 +24,13 @@ class Renderer:
 
     def __init__(self, cams: np.ndarray, n: int, sh_degree: int, tile=(16, 16), batch_depth: int = 64,
                  bg=(0.0, 0.0, 0.0), loss_mode: int = 0, key_capacity: int | None = None, device: int = 0,
-                 ctx: Context | None = None):
+                 ctx: Context | None = None, pixels_per_thread: int = 1):
         self.device = torch.device("cuda", device)
         self.ctx = ctx or Context(device)
         self.cams = np.ascontiguousarray(cams)
         self.n, self.sh_degree = n, sh_degree
         self.tile, self.batch_depth, self.bg, self.loss_mode = tuple(tile), batch_depth, tuple(bg), loss_mode
+        self.ppt = pixels_per_thread
         self.dev_cams = torch.from_numpy(self.cams.view(np.uint8).copy()).to(self.device)
         self.key_capacity = int(key_capacity or max(1 << 16, 8 * n * len(self.cams)))
         self._plan()
@@ -42,7 +45,7 @@ class Renderer:
 
     def _plan(self):
         nbytes = self.ctx.plan(self.n, self.sh_degree, self.cams, self.tile, self.batch_depth, self.bg,
-                               self.loss_mode, self.key_capacity)
+                               self.loss_mode, self.key_capacity, self.ppt)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.pix_off, self.tile_off = self.ctx.frame_layout()
 
@@ -180,3 +183,79 @@ class Optimizer:
 
     def replay(self, plain: bool = False):
         self.r.ctx.step_launch(self.args(plain), self.stream)
+
+
+# ---------------------------------------------------------------------------
+# Autotuner: tile shape x batch depth, timed on the actual workload and cached
+# by (device arch, Gaussian-count bucket, view-set signature).
+# ---------------------------------------------------------------------------
+# (tile, batch depth, pixels per thread)
+TUNE_CANDIDATES = [((16, 16), 64, 2), ((16, 16), 64, 4), ((32, 16), 64, 4), ((32, 16), 128, 4),
+                   ((32, 16), 64, 8), ((32, 32), 64, 4), ((32, 32), 128, 4), ((32, 32), 64, 8),
+                   ((32, 32), 128, 8), ((32, 32), 32, 8)]
+
+
+def _tune_key(cams, n, sh_degree, device=0):
+    import hashlib
+    arch = torch.cuda.get_device_properties(device).gcnArchName if torch.cuda.is_available() else "cpu"
+    sig = hashlib.sha256(np.ascontiguousarray(cams).tobytes()).hexdigest()[:16]
+    bucket = 1 << max(0, int(n - 1).bit_length())
+    return f"{arch}|n<={bucket}|sh{sh_degree}|views{len(cams)}|{sig}"
+
+
+def _cache_path():
+    return os.environ.get("GSOPT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "gsopt", "tune.json"))
+
+
+def autotune(cams, params: DeviceParams, target_params: DeviceParams, candidates=TUNE_CANDIDATES,
+             stream=None, steps: int = 2, log=print, use_cache: bool = True) -> dict:
+    """Times the batched optimize step for each (tile, batch depth) candidate
+    and returns the fastest; the parameters given are not modified."""
+    import json
+    key = _tune_key(cams, params.n, params.sh_degree)
+    path = _cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            cache = json.load(open(path))
+        except Exception:
+            cache = {}
+    if key in cache:
+        hit = cache[key]
+        return {"tile": tuple(hit["tile"]), "batch_depth": hit["batch_depth"], "pixels_per_thread": hit["ppt"],
+                "cached": True, "times": hit.get("times")}
+    times = {}
+    ctx = None
+    for tile, batch, ppt in candidates:
+        r = Renderer(cams, params.n, params.sh_degree, tile=tile, batch_depth=batch, loss_mode=1, ctx=ctx,
+                     pixels_per_thread=ppt)
+        ctx = r.ctx
+        r.fit_capacity(target_params)
+        r.fit_capacity(params)
+        targets = r.forward(target_params)[0].clone()
+        opt = Optimizer(r, params.clone(), targets, stream=stream)
+        opt.step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s = stream or torch.cuda.current_stream()
+        e0.record(s)
+        for _ in range(steps):
+            opt.step()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        times[f"{tile[0]}x{tile[1]}/{batch}/{ppt}"] = round(ms, 3)
+        log(f"[autotune] tile {tile[0]}x{tile[1]} batch {batch} px/thread {ppt}: {ms:.3f} ms/step")
+        del opt, r, targets
+    best = min(times, key=times.get)
+    t, b, p = best.split("/")
+    tile = tuple(int(x) for x in t.split("x"))
+    res = {"tile": tile, "batch_depth": int(b), "pixels_per_thread": int(p), "cached": False, "times": times}
+    if use_cache:
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            cache[key] = {"tile": list(tile), "batch_depth": int(b), "ppt": int(p), "times": times}
+            json.dump(cache, open(path, "w"), indent=1)
+        except OSError:
+            pass
+    return res

@@ -12,10 +12,10 @@ GRAD_ABS = 1e-6         # absolute floor
 EPS_ACC = 2.0 ** -17
 
 
-def renderer_for(w, tile=(16, 16), batch=64, bg=(0.0, 0.0, 0.0), loss_mode=0, cap=None):
+def renderer_for(w, tile=(16, 16), batch=64, bg=(0.0, 0.0, 0.0), loss_mode=0, cap=None, ppt=1):
     from paper_2604_02851_amd.renderer import Renderer
     r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, tile=tile, batch_depth=batch, bg=bg, loss_mode=loss_mode,
-                 key_capacity=cap)
+                 key_capacity=cap, pixels_per_thread=ppt)
     return r
 
 

@@ -85,20 +85,41 @@ def test_composite_matches_oracle(oracle, bg):
     assert ref.n_contrib.max() > 20
 
 
-def test_tile_and_batch_invariance_bit_identical():
+VARIANTS = [((8, 8), 1), ((16, 8), 1), ((16, 8), 2), ((16, 16), 1), ((16, 16), 2), ((16, 16), 4),
+            ((32, 16), 1), ((32, 16), 2), ((32, 16), 4), ((32, 32), 1), ((32, 32), 2), ((32, 32), 4),
+            ((32, 16), 8), ((32, 32), 8)]
+
+
+def test_tile_batch_and_thread_shape_invariance_bit_identical():
     w = small(seed=104)
     P = DeviceParams.from_scene(w.scene)
     base = None
-    for tile in [(16, 16), (8, 8), (16, 8), (32, 16), (32, 32)]:
-        for batch in [32, 64, 128, 256]:
-            r = renderer_for(w, tile=tile, batch=batch)
+    for tile, ppt in VARIANTS:
+        for batch in [32, 64, 128]:
+            r = renderer_for(w, tile=tile, batch=batch, ppt=ppt)
             img, T, nc = r.forward(P)
             cur = (img.cpu().numpy(), T.cpu().numpy(), nc.cpu().numpy())
             if base is None:
                 base = cur
             else:
                 for a, b in zip(base, cur):
-                    assert np.array_equal(a, b), (tile, batch)
+                    assert np.array_equal(a, b), (tile, batch, ppt)
+
+
+@pytest.mark.parametrize("tile,ppt", [((16, 16), 4), ((32, 32), 2), ((32, 16), 4), ((16, 8), 2), ((32, 32), 8)])
+def test_backward_variants_match_oracle(oracle, tile, ppt):
+    w = small(seed=110, n=1200, sizes=((70, 50), (33, 64)))
+    r = renderer_for(w, tile=tile, ppt=ppt)
+    P = DeviceParams.from_scene(w.scene)
+    G = _up(w, 3)
+    r.forward(P)
+    grads = DeviceParams.zeros_like(P)
+    r.backward(P, torch.from_numpy(G).cuda(), 0, grads)
+    torch.cuda.synchronize()
+    b = oracle.backward(w.scene, w.cams, G, mode=0)
+    rep = grad_report(flat_grads(grads), b)
+    print(tile, ppt, rep)
+    assert rep["fail"] == 0
 
 
 def test_backward_matches_oracle_gradient(oracle):
