@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--tile", default=None, help="e.g. 16x16 (default: autotuned)")
     ap.add_argument("--batch-depth", type=int, default=None)
     ap.add_argument("--ppt", type=int, default=None, help="pixels per thread (default: autotuned)")
+    ap.add_argument("--wave-w", type=int, default=None, help="wave sub-tile width (default: autotuned)")
+    ap.add_argument("--schedule", type=int, default=None, help="tile schedule 0/1 (default: autotuned)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of view 0 in the oracle sample (0 = all)")
@@ -136,7 +138,7 @@ def main():
 
     from paper_2604_02851_amd import scenes as S
     from paper_2604_02851_amd.native import DeviceParams
-    from paper_2604_02851_amd.renderer import Optimizer, Renderer, autotune
+    from paper_2604_02851_amd.renderer import SHAPE_KEYS, Optimizer, Renderer, autotune
 
     t0 = time.perf_counter()
     w = S.workload(args.config)
@@ -147,21 +149,19 @@ def main():
     params = DeviceParams.from_scene(w.scene)
     pert = DeviceParams.from_scene(w.extra["perturbed"])
 
-    tile, batch, ppt = (16, 16), 64, 1
+    shape = dict(tile=(32, 32), batch_depth=128, pixels_per_thread=4, wave_w=0, schedule=0)
     tuned = None
-    if args.tile:
-        tile = parse_tile(args.tile)
-    if args.batch_depth:
-        batch = args.batch_depth
-    if args.ppt:
-        ppt = args.ppt
-    if not args.tile and not args.batch_depth and not args.ppt and not args.no_autotune:
+    manual = dict(tile=args.tile and parse_tile(args.tile), batch_depth=args.batch_depth,
+                  pixels_per_thread=args.ppt, wave_w=args.wave_w, schedule=args.schedule)
+    if all(v is None for v in manual.values()) and not args.no_autotune:
         tuned = autotune(w.cams, params, pert, stream=stream, log=log)
-        tile, batch, ppt = tuned["tile"], tuned["batch_depth"], tuned["pixels_per_thread"]
-    log(f"[bench] tile {tile[0]}x{tile[1]}, batch depth {batch}, pixels per thread {ppt}")
+        shape.update({k: tuned[k] for k in SHAPE_KEYS})
+    else:
+        shape.update({k: v for k, v in manual.items() if v is not None})
+    tile, batch, ppt = shape["tile"], shape["batch_depth"], shape["pixels_per_thread"]
+    log(f"[bench] launch shape {shape}")
 
-    r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, tile=tile, batch_depth=batch, loss_mode=1,
-                 pixels_per_thread=ppt)
+    r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, loss_mode=1, **shape)
     need = r.fit_capacity(pert)
     need = max(need, r.fit_capacity(params))
     log(f"[bench] keys {need}, capacity {r.key_capacity}, workspace {r.ws.numel() / 2**30:.2f} GiB")
@@ -254,6 +254,7 @@ def main():
                                "replayed from a HIP graph",
                    "gaussians": w.scene.n, "views": len(w.cams), "pixels": w.n_pixels,
                    "tile": f"{tile[0]}x{tile[1]}", "batch_depth": batch, "pixels_per_thread": ppt,
+                   "wave_w": r.wave_w, "schedule": r.schedule,
                    "autotuned": tuned is not None,
                    "keys": int(c.keys), "visible_pairs": int(c.visible), "parallelism": "1 GPU"},
         "views_per_s": round(len(w.cams) * 1000.0 / ms_batched, 2),

@@ -80,9 +80,14 @@ typedef struct {
 /* Rendering options fixed at plan time.
  *  tile_w, tile_h    : tile size in pixels, one of 8x8, 16x8, 16x16, 32x16, 32x32
  *  batch_depth       : splat records staged in LDS per batch: 32, 64 or 128
- *  pixels_per_thread : 1, 2 or 4 (0 means 1); 8x8 tiles take 1, 16x8 tiles
- *                      1 or 2; a workgroup has tile_w*tile_h/pixels_per_thread
- *                      threads.  Results do not depend on any of these three.
+ *  pixels_per_thread : 1, 2 or 4 (0 means 1); a workgroup has
+ *                      tile_w*tile_h/pixels_per_thread threads
+ *  wave_w            : width of the sub-tile one wavefront owns (0 = tile_w;
+ *                      16 is also built for 32-wide tiles)
+ *  schedule          : 0 = workgroups take tiles in row-major order;
+ *                      1 = each XCD takes a contiguous run of tiles
+ *  Unsupported combinations give GS_ERR_UNSUPPORTED; results do not depend on
+ *  tile size, batch depth, pixels per thread, wave shape or schedule.
  *  bg                : background colour added with the final transmittance
  *  loss_mode         : L1 reduction, 0 = sum over pixels and channels,
  *                      1 = mean per view (1/(3HW)), summed over views */
@@ -90,6 +95,8 @@ typedef struct {
   int32_t tile_w, tile_h;
   int32_t batch_depth;
   int32_t pixels_per_thread;
+  int32_t wave_w;
+  int32_t schedule;
   float bg[3];
   int32_t loss_mode;
 } gs_render_opts;

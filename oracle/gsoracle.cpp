@@ -694,18 +694,24 @@ void or_render_alternatives(const float* mean, const float* lsc, const float* qu
 //  s3     magnitude scale: sum over views of |J|^T (sum over pixels of |2D terms|)
 //  k3     slack: |J|^T (largest change of the 2D terms over the alternative
 //         outcomes of near-threshold decisions and L1 sign ambiguities)
+//  t3     depth-weighted scale: |J|^T (sum over pixels of |2D terms| times
+//         E_p = sum over the pixel's composited splats of 1/(1 - alpha)),
+//         the condition number of the pixel's transmittance product: an
+//         evaluation whose alphas carry relative error u has transmittances
+//         off by at most about u * E_p relative.
 //  loss   (mode 1) the loss value; also images/T/n of the primary path.
 // `kink` is the |img - target| margin below which an L1 sign is ambiguous.
 void or_backward(const float* mean, const float* lsc, const float* quat, const float* opac, const float* sh,
                  int64_t n, int deg, const void* cams_v, int nv, const double* bg,
                  const float* up, int mode, int loss_mode, double kink,
-                 double* g3, double* s3, double* k3, double* loss_out, double* out_img) {
+                 double* g3, double* s3, double* k3, double* t3, double* loss_out, double* out_img) {
   const Cam* cams = (const Cam*)cams_v;
   Params P = make_params(mean, lsc, quat, opac, sh, n, deg);
   const int np = nparam_of(deg);
   std::memset(g3, 0, sizeof(double) * np * n);
   std::memset(s3, 0, sizeof(double) * np * n);
   std::memset(k3, 0, sizeof(double) * np * n);
+  std::memset(t3, 0, sizeof(double) * np * n);
   double loss = 0.0;
   int64_t pix_off = 0;
   using Acc = std::vector<std::pair<int32_t, std::array<double, 9>>>;
@@ -718,12 +724,13 @@ void or_backward(const float* mean, const float* lsc, const float* quat, const f
     build_view(P, cam, vd, 0, H);
     const size_t nvis = vd.ids.size();
     const int nth = omp_get_max_threads();
-    std::vector<std::vector<double>> accG(nth), accS(nth), accK(nth);
+    std::vector<std::vector<double>> accG(nth), accS(nth), accK(nth), accT(nth);
     std::vector<double> lossT(nth, 0.0);
     #pragma omp parallel
     {
       const int tid = omp_get_thread_num();
       accG[tid].assign(nvis * 9, 0.0); accS[tid].assign(nvis * 9, 0.0); accK[tid].assign(nvis * 9, 0.0);
+      accT[tid].assign(nvis * 9, 0.0);
       std::vector<Contrib> cs, cs_alt;
       Acc d0, db, dk;
       std::vector<std::array<double, 9>> dmax;
@@ -747,10 +754,13 @@ void or_backward(const float* mean, const float* lsc, const float* quat, const f
           if (mode == 1)
             for (int ch = 0; ch < 3; ++ch) lossT[tid] += wv * std::fabs(res.C[ch] - (double)up[3 * pix_off + ch * HW + p]);
           pixel_backward(vd, cs, res.T, bg, Gup, &d0);
+          double Ep = 0.0;
+          for (const Contrib& c : cs) Ep += 1.0 / (1.0 - c.alpha);
           for (auto& e : d0)
             for (int f = 0; f < 9; ++f) {
               accG[tid][e.first * 9 + f] += e.second[f];
               accS[tid][e.first * 9 + f] += std::fabs(e.second[f]);
+              accT[tid][e.first * 9 + f] += std::fabs(e.second[f]) * Ep;
             }
           // L1 sign ambiguity on the primary path: the channel's upstream may
           // be -w, 0 or +w, so the terms may move by up to 2 w |d/dG_ch|.
@@ -809,9 +819,11 @@ void or_backward(const float* mean, const float* lsc, const float* quat, const f
     }
     for (int t = 0; t < nth; ++t) loss += lossT[t];
     // reduce thread accumulators
-    std::vector<double> G2(nvis * 9, 0.0), S2(nvis * 9, 0.0), K2(nvis * 9, 0.0);
+    std::vector<double> G2(nvis * 9, 0.0), S2(nvis * 9, 0.0), K2(nvis * 9, 0.0), T2(nvis * 9, 0.0);
     for (int t = 0; t < nth; ++t)
-      for (size_t k = 0; k < nvis * 9; ++k) { G2[k] += accG[t][k]; S2[k] += accS[t][k]; K2[k] += accK[t][k]; }
+      for (size_t k = 0; k < nvis * 9; ++k) {
+        G2[k] += accG[t][k]; S2[k] += accS[t][k]; K2[k] += accK[t][k]; T2[k] += accT[t][k];
+      }
     // chain rule per visible Gaussian; |J| from unit 2D vectors
     #pragma omp parallel
     {
@@ -821,7 +833,7 @@ void or_backward(const float* mean, const float* lsc, const float* quat, const f
         const int64_t i = vd.ids[e];
         std::fill(gl.begin(), gl.end(), 0.0);
         chain_rule(P, i, cam, vd.pr[e], &G2[e * 9], gl.data());
-        std::vector<double> sl(np, 0.0), kl(np, 0.0);
+        std::vector<double> sl(np, 0.0), kl(np, 0.0), tl(np, 0.0);
         for (int f = 0; f < 9; ++f) {
           if (S2[e * 9 + f] == 0.0 && K2[e * 9 + f] == 0.0) continue;
           double unit[9] = {0}; unit[f] = 1.0;
@@ -830,6 +842,7 @@ void or_backward(const float* mean, const float* lsc, const float* quat, const f
           for (int k = 0; k < np; ++k) {
             sl[k] += std::fabs(col[k]) * S2[e * 9 + f];
             kl[k] += std::fabs(col[k]) * K2[e * 9 + f];
+            tl[k] += std::fabs(col[k]) * T2[e * 9 + f];
           }
         }
         // each Gaussian appears once per view: no write conflicts within a view
@@ -837,6 +850,7 @@ void or_backward(const float* mean, const float* lsc, const float* quat, const f
           g3[k * n + i] += gl[k];
           s3[k * n + i] += sl[k];
           k3[k * n + i] += kl[k];
+          t3[k * n + i] += tl[k];
         }
       }
     }

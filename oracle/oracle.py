@@ -48,7 +48,7 @@ def lib():
         L.or_tile_lists.restype = i64
         L.or_render.argtypes = params + [P, i32, P, i32, i32, P, P, P, P]
         L.or_render_alternatives.argtypes = params + [P, i32, P, P, i32, P, P]
-        L.or_backward.argtypes = params + [P, i32, P, P, i32, i32, dbl, P, P, P, P, P]
+        L.or_backward.argtypes = params + [P, i32, P, P, i32, i32, dbl, P, P, P, P, P, P]
         L.or_adam.argtypes = [P, P, P, P, i64, flt, flt, flt, flt, i32, P, P, P]
         L.or_delta.argtypes = [P, P, P, i64, u32, flt, P]
         L.or_delta.restype = i64
@@ -169,6 +169,7 @@ class Backward:
     grad: np.ndarray      # [nparam, N]
     scale: np.ndarray     # [nparam, N]  |J|^T sum |2D terms|
     slack: np.ndarray     # [nparam, N]  branch / sign-ambiguity allowance
+    scale_t: np.ndarray   # [nparam, N]  |J|^T sum |2D terms| * E_p (transmittance condition)
     loss: float
     image: np.ndarray     # primary image [3*P]
 
@@ -191,13 +192,15 @@ def backward(scene, cams, upstream, mode: int, loss_mode: int = 0, bg=(0.0, 0.0,
     g = np.zeros(npar * N)
     s = np.zeros(npar * N)
     k = np.zeros(npar * N)
+    t = np.zeros(npar * N)
     loss = np.zeros(1)
     img = np.zeros(3 * P)
     bgv = np.asarray(bg, np.float64)
     keep, args = _scene_args(scene)
     lib().or_backward(*args, _p(cams), len(cams), _p(bgv), _p(up), mode, loss_mode, float(kink),
-                      _p(g), _p(s), _p(k), _p(loss), _p(img))
-    return Backward(g.reshape(npar, N), s.reshape(npar, N), k.reshape(npar, N), float(loss[0]), img)
+                      _p(g), _p(s), _p(k), _p(t), _p(loss), _p(img))
+    return Backward(g.reshape(npar, N), s.reshape(npar, N), k.reshape(npar, N), t.reshape(npar, N),
+                    float(loss[0]), img)
 
 
 def adam(theta, g, m, v, lr, beta1, beta2, eps, step):

@@ -142,10 +142,6 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   L.hist = take(4 * (256 * L.hist_blocks + 1));
   L.partial = take(4 * L.partial_len);
   L.ranges = take(8 * tiles);
-  L.tkey_a = take(4 * tiles);
-  L.tkey_b = take(4 * tiles);
-  L.tval_a = take(4 * tiles);
-  L.tval_b = take(4 * tiles);
   L.last = take(4 * pixels);
   L.dflags = take(n);
   L.dcount = take(4 * (6ll * L.dblocks + 1));
@@ -237,9 +233,12 @@ gs_status gs_plan(gs_ctx c, int32_t n, int32_t sh_degree, int32_t n_views, const
   if (bd != 32 && bd != 64 && bd != 128)
     return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: batch_depth=%d not in {32,64,128}", bd);
   const int ppt = opts->pixels_per_thread == 0 ? 1 : opts->pixels_per_thread;
-  if (!raster_variant_built(opts->tile_w, opts->tile_h, ppt))
-    return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: %d pixels per thread not built for %dx%d tiles", ppt, opts->tile_w,
-                opts->tile_h);
+  const int wave_w = opts->wave_w == 0 ? opts->tile_w : opts->wave_w;
+  if (!raster_variant_built(opts->tile_w, opts->tile_h, ppt, wave_w))
+    return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: %d pixels per thread with %d-wide wave tiles not built for %dx%d tiles",
+                ppt, wave_w, opts->tile_w, opts->tile_h);
+  if (opts->schedule != 0 && opts->schedule != 1)
+    return fail(c, GS_ERR_INVALID, "gs_plan: schedule=%d not in {0,1}", opts->schedule);
   if (opts->loss_mode != 0 && opts->loss_mode != 1)
     return fail(c, GS_ERR_INVALID, "gs_plan: loss_mode=%d", opts->loss_mode);
   if (key_capacity < 1 || key_capacity > (int64_t)0x7fffffff)
@@ -254,6 +253,8 @@ gs_status gs_plan(gs_ctx c, int32_t n, int32_t sh_degree, int32_t n_views, const
   pl.tile_h = opts->tile_h;
   pl.batch_depth = bd;
   pl.ppt = ppt;
+  pl.wave_w = wave_w;
+  pl.schedule = opts->schedule;
   for (int k = 0; k < 3; ++k) pl.bg[k] = opts->bg[k];
   pl.loss_mode = opts->loss_mode;
   int64_t tiles = 0, pixels = 0;

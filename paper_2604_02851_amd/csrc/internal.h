@@ -56,7 +56,6 @@ struct WsLayout {
   size_t hist;        // u32 [256 * max_blocks + 1]
   size_t partial;     // u32 [scan partials]
   size_t ranges;      // u32x2 [tiles]
-  size_t tkey_a, tkey_b, tval_a, tval_b;  // u32 [tiles] launch order of the tiles (result in tval_a)
   size_t last;        // u32 [pixels]
   size_t dflags;      // u8 [n] delta flags
   size_t dcount;      // u32 [6 * dblocks + 1] delta block counts (scanned in place)
@@ -71,7 +70,7 @@ struct WsLayout {
 
 struct Plan {
   int32_t n = 0, sh_degree = 0, n_views = 0;
-  int32_t tile_w = 16, tile_h = 16, batch_depth = 64, ppt = 1;
+  int32_t tile_w = 16, tile_h = 16, batch_depth = 64, ppt = 1, wave_w = 16, schedule = 0;
   float bg[3] = {0, 0, 0};
   int32_t loss_mode = 0;
   int32_t total_tiles = 0;
@@ -156,7 +155,7 @@ hipError_t launch_epoch_bump(uint32_t* epoch, hipStream_t st);
 // whether the sorted tile lists of views [v0, v0+nv) end in the second buffer
 bool sorted_values_in_b(const Plan& pl, int v0, int nv);
 // whether compositing kernels were built for this tile shape / pixels per thread
-bool raster_variant_built(int tile_w, int tile_h, int ppt);
+bool raster_variant_built(int tile_w, int tile_h, int ppt, int wave_w);
 
 // exclusive scan of `count` u32 values (count read from *dcount when non-null,
 // capped at `max_count`); total written to *total when non-null.

@@ -1,11 +1,12 @@
 // Front-to-back compositing per tile and its adjoint.
 //
 // One workgroup per tile.  Each thread owns PPT pixels of the tile; each
-// wavefront owns a contiguous band of tile rows (TW x WROWS pixels).  The
+// wavefront owns an SW x WROWS sub-tile (a band of whole rows when SW = TW,
+// squarer blocks otherwise, which a splat's box misses more often).  The
 // tile's list is consumed in batches of BATCH splat records staged in LDS:
 // every pixel of the tile reads every record, so a record leaves HBM once per
 // tile.  Before evaluating a splat, a wavefront tests the splat's 3-sigma box
-// against its own band and skips it as a whole when they do not meet; the box
+// against its own sub-tile and skips it as a whole when they do not meet; the box
 // is widened so that it contains every pixel whose FP32 ellipse test can
 // pass, so skipping never changes a result.
 //
@@ -13,23 +14,38 @@
 // the workgroup once every pixel has stopped; saves T_final, the contributor
 // count and the last composited list position.
 // Backward: walks the list back to front from each pixel's last position,
-// rebuilding the transmittance by division; a splat's screen-space gradient
-// is summed over the thread's pixels in registers, then over the wavefront
-// with DPP row operations, then over the wavefronts of the tile in LDS, and
-// finally added once per (tile, splat, field) to the global accumulator.
+// rebuilding the transmittance by division (in FP64); a splat's screen-space
+// gradient is summed over the thread's pixels in registers, then over the
+// wavefront with DPP row operations, then over the wavefronts of the tile in
+// LDS, and finally added once per (tile, splat, field) to the global
+// accumulator.
 #include "internal.h"
 
 namespace gs {
 namespace {
 
-template <int TW, int TH, int PPT>
+// A wavefront owns an SW x WROWS sub-tile; lane l covers column l % SW and
+// rows l / SW + q * LROWS for q < PPT.
+template <int TW, int TH, int PPT, int SW>
 struct Geom {
   static constexpr int NT = TW * TH / PPT;       // threads per workgroup
   static constexpr int NWAVES = NT / 64;
-  static constexpr int LROWS = 64 / TW;          // tile rows spanned by one pixel slot of a wave
-  static constexpr int WROWS = LROWS * PPT;      // tile rows owned by one wavefront
-  static_assert(NT % 64 == 0 && 64 % TW == 0 && NWAVES * WROWS == TH, "tile / pixels-per-thread shape");
+  static constexpr int LROWS = 64 / SW;          // sub-tile rows spanned by one pixel slot of a wave
+  static constexpr int WROWS = LROWS * PPT;      // sub-tile height
+  static constexpr int WPR = TW / SW;            // wavefronts per tile row
+  static_assert(NT % 64 == 0 && 64 % SW == 0 && TW % SW == 0 && TH % WROWS == 0 &&
+                    NWAVES == WPR * (TH / WROWS),
+                "tile / pixels-per-thread / wave shape");
 };
+
+// Workgroup -> tile.  Schedule 0: row-major tile order.  Schedule 1: each
+// XCD (workgroups are dealt to the 8 XCDs round-robin) receives a contiguous
+// run of tiles, so neighbouring tiles share splat records in that XCD's L2.
+__device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t ntiles, int schedule) {
+  if (schedule == 0) return b;
+  const uint32_t xcd = b & 7u, k = b >> 3;
+  return xcd * (ntiles >> 3) + min(xcd, ntiles & 7u) + k;
+}
 
 // 3-sigma box of a splat in pixel-centre coordinates: (xmin, xmax, ymin, ymax).
 // With Q = [[a, a r], [a r, s + a r^2]], Sigma2_00 = 1/a + r^2/s and
@@ -76,9 +92,9 @@ __device__ __forceinline__ float wave_total_lane63(float v) {
 struct CompArgs {
   const ViewInfo* views;
   const int32_t* tile_view;
-  const uint32_t* order;     // launch order: block b renders tile tile_begin + order[b]
   int32_t tile_begin;
   int32_t ntiles;
+  int32_t schedule;
   const uint2* ranges;
   const uint32_t* vals;
   const float4* rec;
@@ -90,21 +106,20 @@ struct CompArgs {
   float bg0, bg1, bg2;
 };
 
-template <int TW, int TH, int PPT, int BATCH>
+template <int TW, int TH, int PPT, int SW, int BATCH>
 __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
-  using G = Geom<TW, TH, PPT>;
+  using G = Geom<TW, TH, PPT, SW>;
   __shared__ float4 s_rec[BATCH * 3];
   __shared__ float4 s_box[BATCH];
-  const uint32_t slot = a.order[blockIdx.x];
-  if (slot >= (uint32_t)a.ntiles) return;   // (whole workgroup) lists never built
+  const uint32_t slot = tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule);
   const int t = a.tile_begin + (int)slot;
   const ViewInfo view = a.views[a.tile_view[t]];
   const int local = t - view.tile_base;
   const int ty = local / view.tiles_x, tx = local - ty * view.tiles_x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int x0 = tx * TW, y0 = ty * TH + wave * G::WROWS;
-  const int px = x0 + lane % TW, py0 = y0 + lane / TW;
-  const float xlo = (float)x0 + 0.5f, xhi = (float)(x0 + TW) - 0.5f;
+  const int x0 = tx * TW + (wave % G::WPR) * SW, y0 = ty * TH + (wave / G::WPR) * G::WROWS;
+  const int px = x0 + lane % SW, py0 = y0 + lane / SW;
+  const float xlo = (float)x0 + 0.5f, xhi = (float)(x0 + SW) - 0.5f;
   const float ylo = (float)y0 + 0.5f, yhi = (float)(y0 + G::WROWS) - 0.5f;
   const uint2 rg = clamp_range(a.ranges[t], a.cap);
   const float pxc = (float)px + 0.5f;
@@ -183,9 +198,9 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
 struct BwdArgs {
   const ViewInfo* views;
   const int32_t* tile_view;
-  const uint32_t* order;
   int32_t tile_begin;
   int32_t ntiles;
+  int32_t schedule;
   const uint2* ranges;
   const uint32_t* vals;
   const float4* rec;
@@ -201,25 +216,32 @@ struct BwdArgs {
   float bg0, bg1, bg2;
 };
 
-template <int TW, int TH, int PPT, int BATCH>
+// Adjoint of the compositing of one pixel, walked back to front from the
+// pixel's last composited splat (Sj = colour arriving from behind splat j,
+// background included; T rebuilt from T_final by division):
+//   T_j = T_{j+1} / (1 - alpha_j)
+//   d out / d col_j   = alpha_j T_j
+//   d out / d alpha_j = T_j (col_j - S_j),   S_{j-1} = alpha_j col_j + (1 - alpha_j) S_j
+// The division chain runs in FP64, so the rebuilt T_j carry only the FP32
+// rounding of the forward product they start from.
+template <int TW, int TH, int PPT, int SW, int BATCH>
 __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
-  using G = Geom<TW, TH, PPT>;
+  using G = Geom<TW, TH, PPT, SW>;
   constexpr bool kMultiWave = G::NWAVES > 1;
   __shared__ float4 s_rec[BATCH * 3];
   __shared__ float4 s_box[BATCH];
   __shared__ uint32_t s_id[BATCH];
   __shared__ float s_g[kMultiWave ? BATCH * 9 : 1];
   __shared__ uint32_t s_max;
-  const uint32_t slot = a.order[blockIdx.x];
-  if (slot >= (uint32_t)a.ntiles) return;   // (whole workgroup) lists never built
+  const uint32_t slot = tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule);
   const int t = a.tile_begin + (int)slot;
   const ViewInfo view = a.views[a.tile_view[t]];
   const int local = t - view.tile_base;
   const int ty = local / view.tiles_x, tx = local - ty * view.tiles_x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int x0 = tx * TW, y0 = ty * TH + wave * G::WROWS;
-  const int px = x0 + lane % TW, py0 = y0 + lane / TW;
-  const float xlo = (float)x0 + 0.5f, xhi = (float)(x0 + TW) - 0.5f;
+  const int x0 = tx * TW + (wave % G::WPR) * SW, y0 = ty * TH + (wave / G::WPR) * G::WROWS;
+  const int px = x0 + lane % SW, py0 = y0 + lane / SW;
+  const float xlo = (float)x0 + 0.5f, xhi = (float)(x0 + SW) - 0.5f;
   const float ylo = (float)y0 + 0.5f, yhi = (float)(y0 + G::WROWS) - 0.5f;
   const uint2 rg = clamp_range(a.ranges[t], a.cap);
   const float pxc = (float)px + 0.5f;
@@ -227,14 +249,15 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   const float wv = a.loss_mode == 1 ? 1.f / (3.f * (float)HW) : 1.f;
   if (threadIdx.x == 0) s_max = rg.x;
   __syncthreads();
-  float G0[PPT], G1[PPT], G2[PPT], T[PPT], S0[PPT], S1[PPT], S2[PPT];
+  float G0[PPT], G1[PPT], G2[PPT], S0[PPT], S1[PPT], S2[PPT];
+  double T[PPT];
   uint32_t last[PPT];
   float lossv = 0.f;
   uint32_t my_max = rg.x;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     G0[q] = G1[q] = G2[q] = 0.f;
-    T[q] = 1.f;
+    T[q] = 1.0;
     S0[q] = a.bg0;
     S1[q] = a.bg1;
     S2[q] = a.bg2;
@@ -256,7 +279,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         G2[q] = wv * (float)((d2 > 0.f) - (d2 < 0.f));
         lossv += wv * (fabsf(d0) + fabsf(d1) + fabsf(d2));
       }
-      T[q] = a.T[view.pix_off + p];
+      T[q] = (double)a.T[view.pix_off + p];
       last[q] = min(max(a.last[view.pix_off + p], rg.x), rg.y);
       my_max = max(my_max, last[q]);
     }
@@ -296,7 +319,9 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         contrib = true;
         const float4 r2 = s_rec[j * 3 + 2];
         const float al = s.alpha;
-        const float Tj = T[q] * __builtin_amdgcn_rcpf(1.f - al);
+        const double Tjd = T[q] * __builtin_amdgcn_rcp(1.0 - (double)al);
+        T[q] = Tjd;
+        const float Tj = (float)Tjd;
         const float at = al * Tj;
         g[6] = fmaf(at, G0[q], g[6]);
         g[7] = fmaf(at, G1[q], g[7]);
@@ -305,7 +330,6 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         S0[q] = fmaf(al, r2.x - S0[q], S0[q]);
         S1[q] = fmaf(al, r2.y - S1[q], S1[q]);
         S2[q] = fmaf(al, r2.z - S2[q], S2[q]);
-        T[q] = Tj;
         if (!s.clamped) {
           const float dLdP = dLda * al;
           g[5] = fmaf(dLda, s.G, g[5]);
@@ -351,40 +375,42 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
 
 // ---- dispatch over the built (tile, pixels-per-thread, batch) variants ----
 #define GS_RASTER_LIST(X) \
-  X(8, 8, 1)              \
-  X(16, 8, 1)             \
-  X(16, 8, 2)             \
-  X(16, 16, 1)            \
-  X(16, 16, 2)            \
-  X(16, 16, 4)            \
-  X(32, 16, 1)            \
-  X(32, 16, 2)            \
-  X(32, 16, 4)            \
-  X(32, 32, 1)            \
-  X(32, 32, 2)            \
-  X(32, 32, 4)            \
-  X(32, 16, 8)            \
-  X(32, 32, 8)
+  X(8, 8, 1, 8)           \
+  X(16, 8, 1, 16)         \
+  X(16, 8, 2, 16)         \
+  X(16, 16, 1, 16)        \
+  X(16, 16, 2, 16)        \
+  X(16, 16, 4, 16)        \
+  X(32, 16, 1, 32)        \
+  X(32, 16, 2, 32)        \
+  X(32, 16, 4, 32)        \
+  X(32, 16, 2, 16)        \
+  X(32, 16, 4, 16)        \
+  X(32, 32, 1, 32)        \
+  X(32, 32, 2, 32)        \
+  X(32, 32, 4, 32)        \
+  X(32, 32, 2, 16)        \
+  X(32, 32, 4, 16)
 
-template <int TW, int TH, int PPT, typename Args>
+template <int TW, int TH, int PPT, int SW, typename Args>
 hipError_t launch_fwd(int batch, dim3 grid, hipStream_t st, const Args& a) {
   constexpr int NT = TW * TH / PPT;
   switch (batch) {
-    case 32: hipLaunchKernelGGL((k_composite<TW, TH, PPT, 32>), grid, dim3(NT), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((k_composite<TW, TH, PPT, 64>), grid, dim3(NT), 0, st, a); break;
-    case 128: hipLaunchKernelGGL((k_composite<TW, TH, PPT, 128>), grid, dim3(NT), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_composite<TW, TH, PPT, SW, 32>), grid, dim3(NT), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((k_composite<TW, TH, PPT, SW, 64>), grid, dim3(NT), 0, st, a); break;
+    case 128: hipLaunchKernelGGL((k_composite<TW, TH, PPT, SW, 128>), grid, dim3(NT), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <int TW, int TH, int PPT, typename Args>
+template <int TW, int TH, int PPT, int SW, typename Args>
 hipError_t launch_bwd(int batch, dim3 grid, hipStream_t st, const Args& a) {
   constexpr int NT = TW * TH / PPT;
   switch (batch) {
-    case 32: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, 32>), grid, dim3(NT), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, 64>), grid, dim3(NT), 0, st, a); break;
-    case 128: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, 128>), grid, dim3(NT), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, SW, 32>), grid, dim3(NT), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, SW, 64>), grid, dim3(NT), 0, st, a); break;
+    case 128: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, SW, 128>), grid, dim3(NT), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -398,9 +424,9 @@ void tile_span(const Plan& pl, int v0, int nv, int32_t* tb, int32_t* ntiles) {
 
 }  // namespace
 
-bool raster_variant_built(int tw, int th, int ppt) {
-#define GS_HAS(W, H, P) \
-  if (tw == W && th == H && ppt == P) return true;
+bool raster_variant_built(int tw, int th, int ppt, int sw) {
+#define GS_HAS(W, H, P, S) \
+  if (tw == W && th == H && ppt == P && sw == S) return true;
   GS_RASTER_LIST(GS_HAS)
 #undef GS_HAS
   return false;
@@ -420,7 +446,7 @@ hipError_t launch_composite(const Plan& pl, int v0, int nv, void* ws, float* img
   CompArgs a;
   a.views = pl.d_views;
   a.tile_view = pl.d_tile_view;
-  a.order = seg<uint32_t>(ws, pl.ws.tval_a);
+  a.schedule = pl.schedule;
   int32_t ntiles;
   tile_span(pl, v0, nv, &a.tile_begin, &ntiles);
   a.ntiles = ntiles;
@@ -437,9 +463,9 @@ hipError_t launch_composite(const Plan& pl, int v0, int nv, void* ws, float* img
   a.bg2 = pl.bg[2];
   if (ntiles <= 0) return hipSuccess;
   const dim3 grid(ntiles);
-  const int tw = pl.tile_w, th = pl.tile_h, ppt = pl.ppt, b = pl.batch_depth;
-#define GS_FWD(W, H, P) \
-  if (tw == W && th == H && ppt == P) return launch_fwd<W, H, P>(b, grid, st, a);
+  const int tw = pl.tile_w, th = pl.tile_h, ppt = pl.ppt, sw = pl.wave_w, b = pl.batch_depth;
+#define GS_FWD(W, H, P, S) \
+  if (tw == W && th == H && ppt == P && sw == S) return launch_fwd<W, H, P, S>(b, grid, st, a);
   GS_RASTER_LIST(GS_FWD)
 #undef GS_FWD
   return hipErrorInvalidValue;
@@ -450,7 +476,7 @@ hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const 
   BwdArgs a;
   a.views = pl.d_views;
   a.tile_view = pl.d_tile_view;
-  a.order = seg<uint32_t>(ws, pl.ws.tval_a);
+  a.schedule = pl.schedule;
   int32_t ntiles;
   tile_span(pl, v0, nv, &a.tile_begin, &ntiles);
   a.ntiles = ntiles;
@@ -471,9 +497,9 @@ hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const 
   a.bg2 = pl.bg[2];
   if (ntiles <= 0) return hipSuccess;
   const dim3 grid(ntiles);
-  const int tw = pl.tile_w, th = pl.tile_h, ppt = pl.ppt, b = pl.batch_depth;
-#define GS_BWD(W, H, P) \
-  if (tw == W && th == H && ppt == P) return launch_bwd<W, H, P>(b, grid, st, a);
+  const int tw = pl.tile_w, th = pl.tile_h, ppt = pl.ppt, sw = pl.wave_w, b = pl.batch_depth;
+#define GS_BWD(W, H, P, S) \
+  if (tw == W && th == H && ppt == P && sw == S) return launch_bwd<W, H, P, S>(b, grid, st, a);
   GS_RASTER_LIST(GS_BWD)
 #undef GS_BWD
   return hipErrorInvalidValue;

@@ -292,18 +292,6 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys, const uint
   }
 }
 
-// Sort keys that put the longest tile lists first (tile order of the
-// compositing launches, so that the longest tiles start earliest).
-__global__ __launch_bounds__(256) void k_tile_order_keys(const uint2* ranges, int32_t tile_begin, int32_t ntiles,
-                                                         uint32_t* tkey, uint32_t* tval) {
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntiles) return;
-  const uint2 r = ranges[tile_begin + t];
-  const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
-  tkey[t] = 0xffffu - min(len, 0xffffu);
-  tval[t] = (uint32_t)t;
-}
-
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -413,15 +401,6 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   const uint32_t* sk = in_b ? keys_b : keys_a;
   const int64_t rblocks = cdiv(pl.cap, 256) < 8192 ? cdiv(pl.cap, 256) : 8192;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)rblocks), dim3(256), 0, st, sk, &ctr->keys, cap, tile_begin, ranges);
-  // 7. launch order of the tiles: longest lists first
-  uint32_t* tkey_a = seg<uint32_t>(ws, pl.ws.tkey_a);
-  uint32_t* tkey_b = seg<uint32_t>(ws, pl.ws.tkey_b);
-  uint32_t* tval_a = seg<uint32_t>(ws, pl.ws.tval_a);
-  uint32_t* tval_b = seg<uint32_t>(ws, pl.ws.tval_b);
-  hipLaunchKernelGGL(k_tile_order_keys, dim3((unsigned)cdiv(ntiles, 256)), dim3(256), 0, st, ranges, tile_begin,
-                     (int32_t)ntiles, tkey_a, tval_a);
-  e = radix_sort(pl, ws, tkey_a, tval_a, tkey_b, tval_b, ntiles, nullptr, 16, &in_b, st);
-  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

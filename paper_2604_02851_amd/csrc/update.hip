@@ -30,36 +30,13 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   const float rbc2 = (float)(1.0 / sqrt(1.0 - pow(b2, (double)t)));
   const float c1 = 1.f - a.beta1, c2 = 1.f - a.beta2;
   const float step = s.lr / bc1;
-  auto upd = [&](float th, float g, float& m, float& v) {
-    m = fmaf(a.beta1, m, c1 * g);
-    v = fmaf(a.beta2, v, c2 * g * g);
-    return th - step * m / (sqrtf(v) * rbc2 + a.eps);
-  };
-  const bool vec = (s.count % 4 == 0) && ((reinterpret_cast<uintptr_t>(s.theta) | reinterpret_cast<uintptr_t>(s.g) |
-                                           reinterpret_cast<uintptr_t>(s.m) | reinterpret_cast<uintptr_t>(s.v)) % 16 == 0);
-  if (vec) {
-    float4* th4 = reinterpret_cast<float4*>(s.theta);
-    const float4* g4 = reinterpret_cast<const float4*>(s.g);
-    float4* m4 = reinterpret_cast<float4*>(s.m);
-    float4* v4 = reinterpret_cast<float4*>(s.v);
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < s.count / 4; k += stride) {
-      float4 th = th4[k], m = m4[k], v = v4[k];
-      const float4 g = g4[k];
-      th.x = upd(th.x, g.x, m.x, v.x);
-      th.y = upd(th.y, g.y, m.y, v.y);
-      th.z = upd(th.z, g.z, m.z, v.z);
-      th.w = upd(th.w, g.w, m.w, v.w);
-      th4[k] = th;
-      m4[k] = m;
-      v4[k] = v;
-    }
-  } else {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < s.count; k += stride) {
-      float m = s.m[k], v = s.v[k];
-      s.theta[k] = upd(s.theta[k], s.g[k], m, v);
-      s.m[k] = m;
-      s.v[k] = v;
-    }
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < s.count; k += stride) {
+    const float g = s.g[k];
+    const float m = fmaf(a.beta1, s.m[k], c1 * g);
+    const float v = fmaf(a.beta2, s.v[k], c2 * g * g);
+    s.m[k] = m;
+    s.v[k] = v;
+    s.theta[k] -= step * m / (sqrtf(v) * rbc2 + a.eps);
   }
 }
 

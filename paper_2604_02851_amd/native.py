@@ -41,7 +41,7 @@ class GsParams(ctypes.Structure):
 
 class GsRenderOpts(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("batch_depth", c_int32), ("pixels_per_thread", c_int32),
-                ("bg", c_float * 3), ("loss_mode", c_int32)]
+                ("wave_w", c_int32), ("schedule", c_int32), ("bg", c_float * 3), ("loss_mode", c_int32)]
 
 
 class GsAdamHparams(ctypes.Structure):
@@ -184,9 +184,10 @@ class Context:
             raise GsError(s, self.L.gs_last_error(self.h).decode())
 
     def plan(self, n, sh_degree, cams: np.ndarray, tile=(16, 16), batch_depth=64, bg=(0.0, 0.0, 0.0),
-             loss_mode=0, key_capacity=1 << 20, pixels_per_thread=1) -> int:
+             loss_mode=0, key_capacity=1 << 20, pixels_per_thread=1, wave_w=0, schedule=0) -> int:
         cams = np.ascontiguousarray(cams)
-        opts = GsRenderOpts(tile[0], tile[1], batch_depth, pixels_per_thread, (c_float * 3)(*bg), loss_mode)
+        opts = GsRenderOpts(tile[0], tile[1], batch_depth, pixels_per_thread, wave_w, schedule, (c_float * 3)(*bg),
+                            loss_mode)
         out = c_size_t()
         self._chk(self.L.gs_plan(self.h, n, sh_degree, len(cams), cams.ctypes.data_as(c_void_p), ctypes.byref(opts),
                                  int(key_capacity), ctypes.byref(out)))

@@ -24,13 +24,13 @@ class Renderer:
 
     def __init__(self, cams: np.ndarray, n: int, sh_degree: int, tile=(16, 16), batch_depth: int = 64,
                  bg=(0.0, 0.0, 0.0), loss_mode: int = 0, key_capacity: int | None = None, device: int = 0,
-                 ctx: Context | None = None, pixels_per_thread: int = 1):
+                 ctx: Context | None = None, pixels_per_thread: int = 1, wave_w: int = 0, schedule: int = 0):
         self.device = torch.device("cuda", device)
         self.ctx = ctx or Context(device)
         self.cams = np.ascontiguousarray(cams)
         self.n, self.sh_degree = n, sh_degree
         self.tile, self.batch_depth, self.bg, self.loss_mode = tuple(tile), batch_depth, tuple(bg), loss_mode
-        self.ppt = pixels_per_thread
+        self.ppt, self.wave_w, self.schedule = pixels_per_thread, wave_w or tile[0], schedule
         self.dev_cams = torch.from_numpy(self.cams.view(np.uint8).copy()).to(self.device)
         self.key_capacity = int(key_capacity or max(1 << 16, 8 * n * len(self.cams)))
         self._plan()
@@ -45,7 +45,7 @@ class Renderer:
 
     def _plan(self):
         nbytes = self.ctx.plan(self.n, self.sh_degree, self.cams, self.tile, self.batch_depth, self.bg,
-                               self.loss_mode, self.key_capacity, self.ppt)
+                               self.loss_mode, self.key_capacity, self.ppt, self.wave_w, self.schedule)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.pix_off, self.tile_off = self.ctx.frame_layout()
 
@@ -69,7 +69,9 @@ class Renderer:
             self.ctx.project(params, self.dev_cams, v0, nv, self.ws)
             self.ctx.build_tile_lists(v0, nv, self.ws)
             need = max(need, int(self.counters().keys))
-        if need > self.key_capacity or need * margin * 4 < self.key_capacity:
+        # grow when short, shrink when far above the need (sort grids and the
+        # histogram scans are sized by the capacity)
+        if need > self.key_capacity or need * margin * 1.5 < self.key_capacity:
             self.replan(max(1024, int(need * margin) + 1024))
         return need
 
@@ -189,10 +191,12 @@ class Optimizer:
 # Autotuner: tile shape x batch depth, timed on the actual workload and cached
 # by (device arch, Gaussian-count bucket, view-set signature).
 # ---------------------------------------------------------------------------
-# (tile, batch depth, pixels per thread)
-TUNE_CANDIDATES = [((16, 16), 64, 2), ((16, 16), 64, 4), ((32, 16), 64, 4), ((32, 16), 128, 4),
-                   ((32, 16), 64, 8), ((32, 32), 64, 4), ((32, 32), 128, 4), ((32, 32), 64, 8),
-                   ((32, 32), 128, 8), ((32, 32), 32, 8)]
+# (tile, batch depth, pixels per thread, wave sub-tile width, tile schedule)
+TUNE_CANDIDATES = [((16, 16), 64, 2, 16, 0), ((16, 16), 64, 4, 16, 0), ((32, 16), 128, 4, 32, 0),
+                   ((32, 16), 128, 4, 16, 0), ((32, 32), 64, 4, 32, 0), ((32, 32), 128, 4, 32, 0),
+                   ((32, 32), 128, 2, 16, 0), ((32, 32), 128, 4, 16, 0), ((32, 32), 128, 4, 32, 1),
+                   ((32, 32), 128, 4, 16, 1)]
+SHAPE_KEYS = ("tile", "batch_depth", "pixels_per_thread", "wave_w", "schedule")
 
 
 def _tune_key(cams, n, sh_degree, device=0):
@@ -209,8 +213,9 @@ def _cache_path():
 
 def autotune(cams, params: DeviceParams, target_params: DeviceParams, candidates=TUNE_CANDIDATES,
              stream=None, steps: int = 2, log=print, use_cache: bool = True) -> dict:
-    """Times the batched optimize step for each (tile, batch depth) candidate
-    and returns the fastest; the parameters given are not modified."""
+    """Times the batched optimize step for each launch shape and returns the
+    fastest as Renderer keyword arguments; the parameters given are not
+    modified."""
     import json
     key = _tune_key(cams, params.n, params.sh_degree)
     path = _cache_path()
@@ -220,15 +225,16 @@ def autotune(cams, params: DeviceParams, target_params: DeviceParams, candidates
             cache = json.load(open(path))
         except Exception:
             cache = {}
-    if key in cache:
-        hit = cache[key]
-        return {"tile": tuple(hit["tile"]), "batch_depth": hit["batch_depth"], "pixels_per_thread": hit["ppt"],
-                "cached": True, "times": hit.get("times")}
+    hit = cache.get(key)
+    if hit and all(k in hit for k in SHAPE_KEYS):
+        res = {k: hit[k] for k in SHAPE_KEYS}
+        res["tile"] = tuple(res["tile"])
+        return dict(res, cached=True, times=hit.get("times"))
     times = {}
     ctx = None
-    for tile, batch, ppt in candidates:
-        r = Renderer(cams, params.n, params.sh_degree, tile=tile, batch_depth=batch, loss_mode=1, ctx=ctx,
-                     pixels_per_thread=ppt)
+    for cand in candidates:
+        shape = dict(zip(SHAPE_KEYS, cand))
+        r = Renderer(cams, params.n, params.sh_degree, loss_mode=1, ctx=ctx, **shape)
         ctx = r.ctx
         r.fit_capacity(target_params)
         r.fit_capacity(params)
@@ -244,18 +250,17 @@ def autotune(cams, params: DeviceParams, target_params: DeviceParams, candidates
         e1.record(s)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        times[f"{tile[0]}x{tile[1]}/{batch}/{ppt}"] = round(ms, 3)
-        log(f"[autotune] tile {tile[0]}x{tile[1]} batch {batch} px/thread {ppt}: {ms:.3f} ms/step")
+        name = "{}x{}/{}/{}/{}/{}".format(*cand[0], *cand[1:])
+        times[name] = round(ms, 3)
+        log(f"[autotune] tile/batch/px-per-thread/wave-width/schedule {name}: {ms:.3f} ms/step")
         del opt, r, targets
-    best = min(times, key=times.get)
-    t, b, p = best.split("/")
-    tile = tuple(int(x) for x in t.split("x"))
-    res = {"tile": tile, "batch_depth": int(b), "pixels_per_thread": int(p), "cached": False, "times": times}
+    best = candidates[min(range(len(candidates)), key=lambda i: list(times.values())[i])]
+    res = dict(zip(SHAPE_KEYS, best))
     if use_cache:
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
-            cache[key] = {"tile": list(tile), "batch_depth": int(b), "ppt": int(p), "times": times}
+            cache[key] = dict(res, tile=list(best[0]), times=times)
             json.dump(cache, open(path, "w"), indent=1)
         except OSError:
             pass
-    return res
+    return dict(res, cached=False, times=times)

@@ -31,14 +31,31 @@ def test_library_exports_every_declared_symbol():
     assert set(declared()) == set(native.EXPORTED)
 
 
-def test_binding_structs_match_the_c_layout():
+def test_binding_structs_match_the_c_layout(tmp_path):
+    """Size and every field offset of each binding struct equal what the C
+    compiler lays out from the header."""
+    import subprocess
     from paper_2604_02851_amd import native, scenes
-    assert ctypes.sizeof(native.GsParams) == 48
-    assert ctypes.sizeof(native.GsRenderOpts) == 32
-    assert ctypes.sizeof(native.GsAdamHparams) == 36
-    assert ctypes.sizeof(native.GsCounters) == 32
-    assert scenes.CAM_DTYPE.itemsize == 84
-    assert ctypes.sizeof(native.GsStepArgs) == 376
+    structs = {"gs_params": native.GsParams, "gs_render_opts": native.GsRenderOpts,
+               "gs_adam_hparams": native.GsAdamHparams, "gs_counters": native.GsCounters,
+               "gs_step_args": native.GsStepArgs}
+    lines, expect = [], []
+    for cname, cls in structs.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(cls))
+        for f in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f[0]}));')
+            expect.append(getattr(cls, f[0]).offset)
+    lines.append('printf("%zu\\n", sizeof(gs_camera));')
+    expect.append(scenes.CAM_DTYPE.itemsize)
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include "gsopt.h"\nint main(void) {\n' + "\n".join(lines) +
+                   "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                           "-I", "/opt/rocm/include", "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == expect
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -85,31 +85,42 @@ def test_composite_matches_oracle(oracle, bg):
     assert ref.n_contrib.max() > 20
 
 
-VARIANTS = [((8, 8), 1), ((16, 8), 1), ((16, 8), 2), ((16, 16), 1), ((16, 16), 2), ((16, 16), 4),
-            ((32, 16), 1), ((32, 16), 2), ((32, 16), 4), ((32, 32), 1), ((32, 32), 2), ((32, 32), 4),
-            ((32, 16), 8), ((32, 32), 8)]
+# (tile, pixels per thread, wave sub-tile width); every built variant
+VARIANTS = [((8, 8), 1, 8), ((16, 8), 1, 16), ((16, 8), 2, 16), ((16, 16), 1, 16), ((16, 16), 2, 16),
+            ((16, 16), 4, 16), ((32, 16), 1, 32), ((32, 16), 2, 32), ((32, 16), 4, 32), ((32, 16), 2, 16),
+            ((32, 16), 4, 16), ((32, 32), 1, 32), ((32, 32), 2, 32), ((32, 32), 4, 32), ((32, 32), 2, 16),
+            ((32, 32), 4, 16)]
 
 
 def test_tile_batch_and_thread_shape_invariance_bit_identical():
     w = small(seed=104)
     P = DeviceParams.from_scene(w.scene)
     base = None
-    for tile, ppt in VARIANTS:
-        for batch in [32, 64, 128]:
-            r = renderer_for(w, tile=tile, batch=batch, ppt=ppt)
+    for tile, ppt, sw in VARIANTS:
+        for batch, schedule in [(32, 0), (64, 1), (128, 0)]:
+            r = renderer_for(w, tile=tile, batch=batch, ppt=ppt, wave_w=sw, schedule=schedule)
             img, T, nc = r.forward(P)
             cur = (img.cpu().numpy(), T.cpu().numpy(), nc.cpu().numpy())
             if base is None:
                 base = cur
             else:
                 for a, b in zip(base, cur):
-                    assert np.array_equal(a, b), (tile, batch, ppt)
+                    assert np.array_equal(a, b), (tile, batch, ppt, sw, schedule)
 
 
-@pytest.mark.parametrize("tile,ppt", [((16, 16), 4), ((32, 32), 2), ((32, 16), 4), ((16, 8), 2), ((32, 32), 8)])
-def test_backward_variants_match_oracle(oracle, tile, ppt):
+def test_unbuilt_launch_shape_is_refused():
+    from paper_2604_02851_amd.native import GsError
+    w = small(seed=104)
+    for kw in (dict(tile=(32, 32), ppt=8), dict(tile=(16, 16), ppt=4, wave_w=8), dict(tile=(16, 16), schedule=2)):
+        with pytest.raises(GsError):
+            renderer_for(w, **kw)
+
+
+@pytest.mark.parametrize("tile,ppt,sw,schedule", [((16, 16), 4, 16, 0), ((32, 32), 2, 32, 1), ((32, 16), 4, 32, 0),
+                                                   ((16, 8), 2, 16, 1), ((32, 32), 4, 16, 0), ((32, 16), 2, 16, 1)])
+def test_backward_variants_match_oracle(oracle, tile, ppt, sw, schedule):
     w = small(seed=110, n=1200, sizes=((70, 50), (33, 64)))
-    r = renderer_for(w, tile=tile, ppt=ppt)
+    r = renderer_for(w, tile=tile, ppt=ppt, wave_w=sw, schedule=schedule)
     P = DeviceParams.from_scene(w.scene)
     G = _up(w, 3)
     r.forward(P)
@@ -118,7 +129,7 @@ def test_backward_variants_match_oracle(oracle, tile, ppt):
     torch.cuda.synchronize()
     b = oracle.backward(w.scene, w.cams, G, mode=0)
     rep = grad_report(flat_grads(grads), b)
-    print(tile, ppt, rep)
+    print(tile, ppt, sw, schedule, rep)
     assert rep["fail"] == 0
 
 
