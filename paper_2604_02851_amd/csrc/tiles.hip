@@ -18,6 +18,7 @@ namespace {
 
 constexpr int B = kSortBlock;
 constexpr int NW = B / 64;
+static_assert(B == 256, "one thread per radix digit");
 
 __device__ __forceinline__ uint32_t dev_count(const uint32_t* dcount, int64_t max_count) {
   if (!dcount) return (uint32_t)max_count;
@@ -63,7 +64,43 @@ struct ScanSrc {
     if (mode == 1) return a[k] != 0u ? 1u : 0u;
     return a[idx[k]];
   }
+  // Four consecutive values from k (a multiple of 4) with one 16-byte load of
+  // the directly indexed array.
+  __device__ __forceinline__ void four(uint32_t k, uint32_t v[4]) const {
+    const uint4 x = *reinterpret_cast<const uint4*>((mode == 2 ? idx : a) + k);
+    if (mode == 0) {
+      v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+    } else if (mode == 1) {
+      v[0] = x.x != 0u, v[1] = x.y != 0u, v[2] = x.z != 0u, v[3] = x.w != 0u;
+    } else {
+      v[0] = a[x.x], v[1] = a[x.y], v[2] = a[x.z], v[3] = a[x.w];
+    }
+  }
+  __device__ __forceinline__ bool vec_ok() const {
+    return ((reinterpret_cast<uintptr_t>(mode == 2 ? idx : a)) & 15u) == 0;
+  }
 };
+
+// Chunk layout of the scan kernels: thread t holds elements
+//   begin + r * 4B + 4t + c   (round r < kRounds, component c < 4),
+// so every round is one coalesced 16-byte load per thread.
+constexpr int kRounds = kSortItems / 4;
+static_assert(kRounds * 4 * B == kSortChunk, "scan chunk layout");
+
+__device__ __forceinline__ void load_chunk(const ScanSrc& src, uint64_t begin, uint32_t n,
+                                           uint32_t v[kRounds][4]) {
+  const bool full = begin + kSortChunk <= n && src.vec_ok();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint64_t k = begin + (uint64_t)r * 4 * B + 4u * threadIdx.x;
+    if (full) {
+      src.four((uint32_t)k, v[r]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[r][c] = k + c < n ? src((uint32_t)(k + c)) : 0u;
+    }
+  }
+}
 
 __global__ __launch_bounds__(B) void k_scan_reduce(ScanSrc src, int64_t max_count, const uint32_t* dcount,
                                                    uint32_t* partial) {
@@ -71,9 +108,11 @@ __global__ __launch_bounds__(B) void k_scan_reduce(ScanSrc src, int64_t max_coun
   const uint32_t n = dev_count(dcount, max_count);
   const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
   if (begin >= n) return;
-  const uint64_t end = begin + kSortChunk < n ? begin + kSortChunk : n;
+  uint32_t v[kRounds][4];
+  load_chunk(src, begin, n, v);
   uint32_t s = 0;
-  for (uint64_t k = begin + threadIdx.x; k < end; k += B) s += src((uint32_t)k);
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) s += (v[r][0] + v[r][1]) + (v[r][2] + v[r][3]);
   uint32_t tot;
   block_excl_scan(s, s_wave, &tot);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -114,27 +153,48 @@ __global__ __launch_bounds__(1024) void k_scan_partials(int64_t max_count, const
 
 __global__ __launch_bounds__(B) void k_scan_down(ScanSrc src, uint32_t* out, int64_t max_count,
                                                  const uint32_t* dcount, const uint32_t* partial) {
-  __shared__ uint32_t s_wave[NW];
+  __shared__ uint32_t s_wave[kRounds][NW];
   const uint32_t n = dev_count(dcount, max_count);
   const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
   if (begin >= n) return;
-  // each thread owns kSortItems consecutive elements
-  const uint64_t mine = begin + (uint64_t)threadIdx.x * kSortItems;
-  uint32_t v[kSortItems];
-  uint32_t s = 0;
+  uint32_t v[kRounds][4];
+  load_chunk(src, begin, n, v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t s[kRounds], inc[kRounds];
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const uint64_t k = mine + j;
-    v[j] = k < n ? src((uint32_t)k) : 0u;
-    s += v[j];
+  for (int r = 0; r < kRounds; ++r) {
+    s[r] = (v[r][0] + v[r][1]) + (v[r][2] + v[r][3]);
+    inc[r] = wave_incl_scan(s[r]);
+    if (lane == 63) s_wave[r][w] = inc[r];
   }
-  uint32_t tot;
-  uint32_t run = partial[blockIdx.x] + block_excl_scan(s, s_wave, &tot);
+  __syncthreads();
+  uint32_t carry = partial[blockIdx.x];
+  const bool full = begin + kSortChunk <= n && ((reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const uint64_t k = mine + j;
-    if (k < n) out[k] = run;
-    run += v[j];
+  for (int r = 0; r < kRounds; ++r) {
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const uint32_t x = s_wave[r][q];
+      before += (q < w) ? x : 0u;
+      tot += x;
+    }
+    uint32_t run = carry + before + inc[r] - s[r];
+    carry += tot;
+    const uint64_t k = begin + (uint64_t)r * 4 * B + 4u * threadIdx.x;
+    uint32_t o[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      o[c] = run;
+      run += v[r][c];
+    }
+    if (full) {
+      *reinterpret_cast<uint4*>(out + k) = make_uint4(o[0], o[1], o[2], o[3]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (k + c < n) out[k + c] = o[c];
+    }
   }
 }
 
@@ -164,36 +224,63 @@ __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, int64_t 
   __syncthreads();
   const uint32_t n = dev_count(dcount, max_count);
   const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
-  const uint64_t end = begin + kSortChunk < n ? begin + kSortChunk : n;
-  for (uint64_t k = begin + threadIdx.x; k < end; k += B) atomicAdd(&h[(keys[k] >> shift) & 255u], 1u);
+  if (begin < n) {
+    uint32_t v[kRounds][4];
+    load_chunk(ScanSrc{keys, nullptr, 0}, begin, n, v);
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint64_t k = begin + (uint64_t)r * 4 * B + 4u * threadIdx.x;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (k + c < n) atomicAdd(&h[(v[r][c] >> shift) & 255u], 1u);
+    }
+  }
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Scatter of one chunk in input order.  Rank of a key = keys of the same
-// digit in earlier chunks (scanned histogram) + earlier iterations of this
-// chunk + earlier waves of this iteration + earlier lanes of its wave.  Lanes
-// with equal digits are matched with eight ballots.
+// Scatter of one chunk (kSortChunk keys, split into NW contiguous wavefront
+// ranges).  1) Each wavefront ranks its keys stably within (wavefront, digit):
+// lanes with equal digits are matched with eight ballots and a per-wavefront
+// counter per digit advances by the group size.  2) Per digit, the chunk-local
+// start (scan over digits) and the start of each wavefront's group.  3) Keys
+// are placed in LDS in digit order (stable), 4) then written out with
+// consecutive threads taking consecutive local positions, so each digit's run
+// is stored contiguously: global position = scanned histogram of (digit,
+// chunk) + position within the digit's run.
+constexpr int kWaveKeys = kSortChunk / NW;
+constexpr int kWaveRounds = kWaveKeys / 64;
+
 __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                                                      uint32_t* vout, int64_t max_count, const uint32_t* dcount,
                                                      int shift, int64_t nblocks, const uint32_t* hist_scanned) {
-  __shared__ uint32_t s_run[256];
-  __shared__ uint32_t s_cnt[NW][256];
+  __shared__ uint32_t s_key[kSortChunk];
+  __shared__ uint32_t s_val[kSortChunk];
+  __shared__ uint32_t s_wc[NW][256];
+  __shared__ uint32_t s_gbase[256];
+  __shared__ uint32_t s_tmp[NW];
   const uint32_t n = dev_count(dcount, max_count);
   const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
   if (begin >= n) return;
-  const uint64_t end = begin + kSortChunk < n ? begin + kSortChunk : n;
-  s_run[threadIdx.x] = hist_scanned[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+  const uint32_t cnt = (uint32_t)min((uint64_t)kSortChunk, (uint64_t)n - begin);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (uint64_t base = begin; base < end; base += B) {
-    for (int q = threadIdx.x; q < NW * 256; q += B) (&s_cnt[0][0])[q] = 0;
-    __syncthreads();
-    const uint64_t k = base + threadIdx.x;
-    const bool valid = k < end;
-    const uint32_t key = valid ? kin[k] : 0u;
-    const uint32_t val = valid ? vin[k] : 0u;
-    const uint32_t digit = (key >> shift) & 255u;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) s_wc[q][threadIdx.x] = 0;
+  uint32_t key[kWaveRounds], val[kWaveRounds], lr[kWaveRounds];
+#pragma unroll
+  for (int r = 0; r < kWaveRounds; ++r) {
+    const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
+    key[r] = li < cnt ? kin[begin + li] : 0u;
+    val[r] = li < cnt ? vin[begin + li] : 0u;
+  }
+  __syncthreads();
+  // 1. stable ranks within (wavefront, digit)
+#pragma unroll
+  for (int r = 0; r < kWaveRounds; ++r) {
+    const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
+    const bool valid = li < cnt;
+    const uint32_t digit = (key[r] >> shift) & 255u;
     uint64_t match = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -201,21 +288,51 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
       const uint64_t bb = __ballot(bit);
       match &= bit ? bb : ~bb;
     }
-    const uint32_t rank = (uint32_t)__popcll(match & lt_mask);
-    if (valid && rank == 0) s_cnt[w][digit] = (uint32_t)__popcll(match);
-    __syncthreads();
-    if (valid) {
-      uint32_t dst = s_run[digit] + rank;
-      for (int q = 0; q < w; ++q) dst += s_cnt[q][digit];
-      kout[dst] = key;
-      vout[dst] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0;
+    const uint32_t below = (uint32_t)__popcll(match & lt_mask);
+    const uint32_t before = valid ? s_wc[w][digit] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    lr[r] = before + below;
+    if (valid && below == 0) s_wc[w][digit] = before + (uint32_t)__popcll(match);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // 2. chunk-local digit starts and per-wavefront group starts
+  {
+    const int d = threadIdx.x;
+    uint32_t c[NW], tot = 0;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) add += s_cnt[q][threadIdx.x];
-    s_run[threadIdx.x] += add;
-    __syncthreads();
+    for (int q = 0; q < NW; ++q) {
+      c[q] = s_wc[q][d];
+      tot += c[q];
+    }
+    uint32_t all;
+    const uint32_t lstart = block_excl_scan(tot, s_tmp, &all);
+    uint32_t run = lstart;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      s_wc[q][d] = run;
+      run += c[q];
+    }
+    s_gbase[d] = hist_scanned[(int64_t)d * nblocks + blockIdx.x] - lstart;
+  }
+  __syncthreads();
+  // 3. local placement in digit order
+#pragma unroll
+  for (int r = 0; r < kWaveRounds; ++r) {
+    const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
+    if (li < cnt) {
+      const uint32_t pos = s_wc[w][(key[r] >> shift) & 255u] + lr[r];
+      s_key[pos] = key[r];
+      s_val[pos] = val[r];
+    }
+  }
+  __syncthreads();
+  // 4. coalesced write-out
+  for (uint32_t i = threadIdx.x; i < cnt; i += B) {
+    const uint32_t k = s_key[i];
+    const uint32_t dst = s_gbase[(k >> shift) & 255u] + i;
+    kout[dst] = k;
+    vout[dst] = s_val[i];
   }
 }
 
@@ -225,7 +342,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
 // and finds the pair owning a slot by binary search over the 64 start
 // offsets, so a pair touching many tiles does not serialise its wavefront.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const uint32_t* koff, const uint32_t* nvis_p,
-                                              const uint32_t* count, const ushort4* rect, const ViewInfo* views,
+                                              const uint32_t* total_keys, const ushort4* rect, const ViewInfo* views,
                                               int64_t n_gauss, int32_t tile_begin, uint32_t cap, uint32_t* keys,
                                               uint32_t* vals) {
   __shared__ uint32_t s_off[4][64];
@@ -242,7 +359,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const 
   if (valid) {
     const uint32_t vi = sorted_vis[k0 + lane];
     off = koff[k0 + lane];
-    end = off + count[vi];
+    end = k0 + lane + 1 < nvis ? koff[k0 + lane + 1] : *total_keys;
     const int v = (int)(vi / (uint64_t)n_gauss);
     s_vi[w][lane] = vi;
     s_rect[w][lane] = rect[vi];
@@ -386,7 +503,7 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   // 4. emit (tile, value) pairs in depth order
   const int32_t tile_begin = pl.views[v0].tile_base;
   const int32_t tile_end = (v0 + nv < pl.n_views) ? pl.views[v0 + nv].tile_base : pl.total_tiles;
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, sorted_vis, koff, &ctr->nvis, count,
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, sorted_vis, koff, &ctr->nvis, &ctr->keys,
                      seg<ushort4>(ws, pl.ws.rect), pl.d_views, N, tile_begin, cap, keys_a, vals_a);
   // 5. stable sort by tile (relative to the first tile of the call)
   const int64_t ntiles = tile_end - tile_begin;
