@@ -63,43 +63,40 @@ def pair_counts(r, torch):
     return E, C
 
 
-def cpu_baseline(w, rows: int):
-    """Times the FP64 oracle's forward+backward on a band of rows of view 0
-    (all Gaussians projected) and extrapolates to the whole step."""
+def cpu_baseline(w, min_seconds: float):
+    """Times the FP64 oracle's optimize step on whole views of the workload,
+    in view order, until at least `min_seconds` have passed (forward,
+    L1 backward with its projection adjoint, then Adam over all parameters),
+    and scales the view part to the step by pixel count."""
     import numpy as np
     from oracle import oracle as O
-    import copy
-    cam = w.cams[0:1].copy()
-    H = int(cam[0]["height"])
-    rows = H if rows <= 0 or rows > H else rows
-    y0 = H // 2 - rows // 2
-
-    def crop(nrows, top):
-        c = cam.copy()
-        c[0]["height"] = nrows
-        c[0]["cy"] = np.float32(float(c[0]["cy"]) - top)
-        return c
-
-    tgt_rows = lambda c: np.full(3 * int(c[0]["width"]) * int(c[0]["height"]), 0.5, np.float32)
     O.lib()
-    c1 = crop(1, y0)
+    t0 = time.perf_counter()
+    done_px, views = 0, 0
+    for v in range(len(w.cams)):
+        c = w.cams[v:v + 1].copy()
+        npx = int(c[0]["width"]) * int(c[0]["height"])
+        O.backward(w.scene, c, np.full(3 * npx, 0.5, np.float32), mode=1, loss_mode=1)
+        done_px += npx
+        views += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    t_views = time.perf_counter() - t0
     t = time.perf_counter()
-    O.backward(w.scene, c1, tgt_rows(c1), mode=1)
-    t_one = time.perf_counter() - t
-    cb = crop(rows, y0)
-    t = time.perf_counter()
-    O.backward(w.scene, cb, tgt_rows(cb), mode=1)
-    t_band = time.perf_counter() - t
-    W = int(cam[0]["width"])
-    t_pix = max(t_band - t_one, 1e-9) / (W * (rows - 1))
-    total_pix = sum(int(c["width"]) * int(c["height"]) for c in w.cams)
-    t_step = len(w.cams) * t_one + total_pix * t_pix
+    g = np.zeros_like(w.scene.sh)
+    O.adam(w.scene.sh, g, g, g, 5e-3, 0.9, 0.999, 1e-15, 1)
+    for name in ("mean", "log_scale", "quat", "opacity_logit"):
+        a = getattr(w.scene, name)
+        O.adam(a, np.zeros_like(a), np.zeros_like(a), np.zeros_like(a), 1e-3, 0.9, 0.999, 1e-15, 1)
+    t_adam = time.perf_counter() - t
+    total_px = sum(int(c["width"]) * int(c["height"]) for c in w.cams)
+    t_step = t_views * total_px / done_px + t_adam
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": cores, "kind": "oracle",
-            "sample": (f"FP64 oracle forward+backward of view 0 ({W}x{H}), {rows} centre rows "
-                       f"({t_band:.1f} s) and to 1 row ({t_one:.1f} s, projection of all "
-                       f"{w.scene.n} Gaussians); step time extrapolated as 16 projections + "
-                       f"{total_pix} pixels at the band's per-pixel cost = {t_step:.0f} s")}
+            "sample": (f"FP64 oracle step on views 0-{views - 1} of {len(w.cams)} ({done_px} of {total_px} px: "
+                       f"forward, L1 backward, projection adjoint of all {w.scene.n} Gaussians per view) "
+                       f"in {t_views:.1f} s, Adam over all parameters in {t_adam:.1f} s; view part scaled "
+                       f"by pixel count to {t_step:.1f} s per step")}
 
 
 def main():
@@ -116,7 +113,7 @@ def main():
     ap.add_argument("--schedule", type=int, default=None, help="tile schedule 0/1 (default: autotuned)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=0, help="rows of view 0 in the oracle sample (0 = all)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time of the CPU baseline sample")
     ap.add_argument("--calib-copy", action="store_true", help="run only a plain 1 GiB device copy (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -241,7 +238,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
-        cpu = cpu_baseline(w, args.cpu_rows)
+        cpu = cpu_baseline(w, args.cpu_seconds)
         log(f"[bench] cpu baseline {cpu['value']:.3g} steps/s ({time.perf_counter() - t:.1f} s)")
 
     out = {

@@ -89,6 +89,57 @@ __device__ __forceinline__ float wave_total_lane63(float v) {
   return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_get(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+
+// a + b after exchanging the upper 32 lanes of a with the lower 32 lanes of b
+// (resp. the odd 16-lane rows of a with the even rows of b): each result lane
+// holds a partial sum of one of the two inputs.  Written as inline assembly
+// because the compiler's builtin for these gfx950 swaps loses one of its two
+// results here; the s_nop gives the two wait states a cross-lane read needs
+// after a VALU write of its operands.
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+  return a + b;
+}
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+  return a + b;
+}
+
+// Transposed reduction of eight per-lane values over the wavefront: two
+// levels of lane-group swaps halve the values per lane while folding lanes,
+// then a row mirror merges the last pair and three DPP steps finish the
+// 8-lane groups.  Afterwards every lane of 8-lane group k holds the wave
+// total of one field; which field is fixed by the lane position and found
+// once per kernel by reducing one-hot tags (reduce8_field).
+__device__ __forceinline__ float reduce8(const float* g, bool lo8) {
+  const float w0 = swap32_sum(g[0], g[1]);
+  const float w1 = swap32_sum(g[2], g[3]);
+  const float w2 = swap32_sum(g[4], g[5]);
+  const float w3 = swap32_sum(g[6], g[7]);
+  const float x0 = swap16_sum(w0, w1);
+  const float x1 = swap16_sum(w2, w3);
+  const float s = lo8 ? x0 : x1, z = lo8 ? x1 : x0;
+  float y = s + dpp_get<0x140>(z);   // row_mirror: lane i of a row reads lane 15 - i
+  y += dpp_get<0x141>(y);            // row_half_mirror: lane i of 8 reads lane 7 - i
+  y += dpp_get<0x4e>(y);             // quad_perm [2,3,0,1]
+  y += dpp_get<0xb1>(y);             // quad_perm [1,0,3,2]
+  return y;
+}
+
+// Field whose total reduce8 leaves in this lane (exact: sums of 0 and a
+// single power of two).
+__device__ __forceinline__ int reduce8_field(int lane, bool lo8) {
+  float tag[8];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) tag[f] = lane == 0 ? (float)(1 << f) : 0.f;
+  const uint32_t bits = (uint32_t)reduce8(tag, lo8);
+  return __builtin_ctz(bits | 256u) & 7;
+}
+
 struct CompArgs {
   const ViewInfo* views;
   const int32_t* tile_view;
@@ -231,7 +282,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   __shared__ float4 s_rec[BATCH * 3];
   __shared__ float4 s_box[BATCH];
   __shared__ uint32_t s_id[BATCH];
-  __shared__ float s_g[kMultiWave ? BATCH * 9 : 1];
+  __shared__ float s_g[kMultiWave ? G::NWAVES * BATCH * 9 : 1];   // per-wavefront splat sums of a batch
   __shared__ uint32_t s_max;
   const uint32_t slot = tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule);
   const int t = a.tile_begin + (int)slot;
@@ -247,6 +298,9 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   const float pxc = (float)px + 0.5f;
   const int64_t HW = (int64_t)view.width * view.height;
   const float wv = a.loss_mode == 1 ? 1.f / (3.f * (float)HW) : 1.f;
+  const bool lo8 = (lane & 8) == 0;
+  const int my_field = reduce8_field(lane, lo8);
+  const bool writer = (lane & 7) == 0;
   if (threadIdx.x == 0) s_max = rg.x;
   __syncthreads();
   float G0[PPT], G1[PPT], G2[PPT], S0[PPT], S1[PPT], S2[PPT];
@@ -300,7 +354,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       s_box[j] = splat_box(r0, r1);
     }
     if (kMultiWave)
-      for (uint32_t q = threadIdx.x; q < cnt * 9; q += G::NT) s_g[q] = 0.f;
+      for (uint32_t q = threadIdx.x; q < G::NWAVES * BATCH * 9; q += G::NT) s_g[q] = 0.f;
     __syncthreads();
     for (int j = (int)cnt - 1; j >= 0; --j) {
       if (box_misses(s_box[j], xlo, xhi, ylo, yhi)) continue;
@@ -343,24 +397,24 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         }
       }
       if (__ballot(contrib) == 0ull) continue;
-#pragma unroll
-      for (int f = 0; f < 9; ++f) g[f] = wave_total_lane63(g[f]);
-      if (lane == 63) {
-        if (kMultiWave) {
-#pragma unroll
-          for (int f = 0; f < 9; ++f) atomicAdd(&s_g[j * 9 + f], g[f]);
-        } else {
-          float* dst = a.g2 + (size_t)s_id[j] * kG2Stride;
-#pragma unroll
-          for (int f = 0; f < 9; ++f)
-            if (g[f] != 0.f) atomicAdd(dst + f, g[f]);
-        }
+      const float tot8 = reduce8(g, lo8);
+      const float tot9 = wave_total_lane63(g[8]);
+      if (kMultiWave) {
+        float* dst = s_g + (wave * BATCH + j) * 9;
+        if (writer) dst[my_field] = tot8;
+        if (lane == 63) dst[8] = tot9;
+      } else {
+        float* dst = a.g2 + (size_t)s_id[j] * kG2Stride;
+        if (writer && tot8 != 0.f) atomicAdd(dst + my_field, tot8);
+        if (lane == 63 && tot9 != 0.f) atomicAdd(dst + 8, tot9);
       }
     }
     __syncthreads();
     if (kMultiWave) {
       for (uint32_t q = threadIdx.x; q < cnt * 9; q += G::NT) {
-        const float v = s_g[q];
+        float v = 0.f;
+#pragma unroll
+        for (int w = 0; w < G::NWAVES; ++w) v += s_g[w * BATCH * 9 + q];
         if (v != 0.f) atomicAdd(&a.g2[(size_t)s_id[q / 9] * kG2Stride + (q % 9)], v);
       }
       __syncthreads();

@@ -194,9 +194,10 @@ def test_graph_replay_matches_eager(oracle):
             graph.replay()
             s.synchronize()
             if k == 0:
-                # same inputs, same kernels: the forward pass is bit-identical
+                # same inputs, same kernels: the forward pass is bit-identical;
+                # the loss is summed with atomics, so only up to rounding
                 assert torch.equal(r1.images, r2.images)
-                assert eager.loss.item() == graph.loss.item()
+                assert abs(eager.loss.item() - graph.loss.item()) <= 1e-6 * eager.loss.item()
             else:
                 # gradients are summed with atomics in arbitrary order, so later
                 # steps agree to rounding (Adam turns a sign flip of a
