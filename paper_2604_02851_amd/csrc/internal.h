@@ -97,34 +97,35 @@ __host__ __device__ inline T* seg(void* ws, size_t off) {
 //        s = det(Q)/Q00 (= 1 / Sigma2_11); o = opacity
 //   r2 = (red, green, blue, 0)
 // ---------------------------------------------------------------------------
-struct SplatEval {
-  float dx, dy, e, P, G, alpha;
-  bool inside;    // passes the 3-sigma test and the 1/255 skip
-  bool clamped;   // alpha hit 0.99
+// Evaluation of one splat at one pixel centre, in two parts so that a
+// wavefront can skip the second when no lane passes the first.  These are
+// the one place that decides whether a pixel takes a splat; the forward and
+// backward kernels call them on identical inputs, so they make identical
+// decisions bit for bit.
+struct SplatGeom {
+  float dx, dy, e, P;
 };
 
-// The one place that decides whether a pixel takes a splat; the forward and
-// backward kernels call it on identical inputs, so they make identical
-// decisions bit for bit.
-__device__ __forceinline__ SplatEval eval_splat(float pxc, float pyc, const float4& r0, const float4& r1) {
+__device__ __forceinline__ SplatGeom splat_power(float pxc, float pyc, const float4& r0, const float4& r1) {
 #pragma clang fp contract(off)
-  SplatEval s;
-  s.dx = (pxc - r0.x) - r0.z;
-  s.dy = (pyc - r0.y) - r0.w;
-  s.e = fmaf(r1.y, s.dy, s.dx);
-  const float q = fmaf(r1.x * s.e, s.e, r1.z * (s.dy * s.dy));
-  s.P = -0.5f * q;
-  s.inside = false;
-  s.clamped = false;
-  s.G = 0.f;
-  s.alpha = 0.f;
-  if (s.P < kCutoff) return s;
-  s.G = __builtin_amdgcn_exp2f(s.P * 1.44269504088896341f);
-  const float oG = r1.w * s.G;
-  s.clamped = oG >= kAlphaMax;
-  s.alpha = s.clamped ? kAlphaMax : oG;
-  s.inside = s.alpha >= kAlphaMin;
-  return s;
+  SplatGeom g;
+  g.dx = (pxc - r0.x) - r0.z;
+  g.dy = (pyc - r0.y) - r0.w;
+  g.e = fmaf(r1.y, g.dy, g.dx);
+  const float q = fmaf(r1.x * g.e, g.e, r1.z * (g.dy * g.dy));
+  g.P = -0.5f * q;
+  return g;
+}
+
+// Opacity part, for a pixel that passed the 3-sigma test (P >= kCutoff):
+// returns whether alpha reaches the 1/255 skip threshold.
+__device__ __forceinline__ bool splat_alpha(float P, float opacity, float& G, float& alpha, bool& clamped) {
+#pragma clang fp contract(off)
+  G = __builtin_amdgcn_exp2f(P * 1.44269504088896341f);
+  const float oG = opacity * G;
+  clamped = oG >= kAlphaMax;
+  alpha = clamped ? kAlphaMax : oG;
+  return alpha >= kAlphaMin;
 }
 
 // ---- launchers implemented in the .hip files -------------------------------

@@ -202,26 +202,29 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
     if (live) {
       for (uint32_t j = 0; j < cnt; ++j) {
         if (box_misses(s_box[j], xlo, xhi, ylo, yhi)) continue;
-        const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1];
+        const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1], r2 = s_rec[j * 3 + 2];
+        const uint32_t pos1 = b0 + j + 1;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-          if (done[q]) continue;
           const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
-          const SplatEval s = eval_splat(pxc, pyc, r0, r1);
-          if (!s.inside) continue;
-          const float Tn = T[q] * (1.f - s.alpha);
-          if (Tn < kTMin) {
-            done[q] = true;
-            continue;
-          }
-          const float4 r2 = s_rec[j * 3 + 2];
-          const float w = s.alpha * T[q];
+          const SplatGeom sg = splat_power(pxc, pyc, r0, r1);
+          const bool cand = !done[q] && sg.P >= kCutoff;
+          if (__ballot(cand) == 0ull) continue;   // uniform: no lane of this row slot is near the splat
+          float Gs, al;
+          bool clamped;
+          const bool take = splat_alpha(sg.P, r1.w, Gs, al, clamped) && cand;
+          // predicated from here on: no divergent branches in the hot loop
+          const float Tn = T[q] * (1.f - al);
+          const bool stop = take && Tn < kTMin;
+          const bool comp = take && !stop;
+          done[q] = done[q] || stop;
+          const float w = comp ? al * T[q] : 0.f;
           c0[q] = fmaf(r2.x, w, c0[q]);
           c1[q] = fmaf(r2.y, w, c1[q]);
           c2[q] = fmaf(r2.z, w, c2[q]);
-          T[q] = Tn;
-          ++n[q];
-          last[q] = b0 + j + 1;
+          T[q] = comp ? Tn : T[q];
+          n[q] += comp ? 1u : 0u;
+          last[q] = comp ? pos1 : last[q];
         }
       }
       live = false;
@@ -360,41 +363,44 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       if (box_misses(s_box[j], xlo, xhi, ylo, yhi)) continue;
       const uint32_t pos = b_begin + (uint32_t)j;
       const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1];
+      const float4 r2 = s_rec[j * 3 + 2];
       float g[9];
 #pragma unroll
       for (int f = 0; f < 9; ++f) g[f] = 0.f;
       bool contrib = false;
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        if (pos >= last[q]) continue;
         const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
-        const SplatEval s = eval_splat(pxc, pyc, r0, r1);
-        if (!s.inside) continue;
-        contrib = true;
-        const float4 r2 = s_rec[j * 3 + 2];
-        const float al = s.alpha;
+        const SplatGeom sg = splat_power(pxc, pyc, r0, r1);
+        const bool cand = pos < last[q] && sg.P >= kCutoff;
+        if (__ballot(cand) == 0ull) continue;   // uniform
+        float Gs, al;
+        bool clamped;
+        const bool take = splat_alpha(sg.P, r1.w, Gs, al, clamped) && cand;
+        contrib = contrib || take;
+        // predicated from here on; lanes that do not take the splat add zeros
         const double Tjd = T[q] * __builtin_amdgcn_rcp(1.0 - (double)al);
-        T[q] = Tjd;
+        T[q] = take ? Tjd : T[q];
         const float Tj = (float)Tjd;
-        const float at = al * Tj;
+        const float at = take ? al * Tj : 0.f;
         g[6] = fmaf(at, G0[q], g[6]);
         g[7] = fmaf(at, G1[q], g[7]);
         g[8] = fmaf(at, G2[q], g[8]);
-        const float dLda = Tj * ((r2.x - S0[q]) * G0[q] + (r2.y - S1[q]) * G1[q] + (r2.z - S2[q]) * G2[q]);
-        S0[q] = fmaf(al, r2.x - S0[q], S0[q]);
-        S1[q] = fmaf(al, r2.y - S1[q], S1[q]);
-        S2[q] = fmaf(al, r2.z - S2[q], S2[q]);
-        if (!s.clamped) {
-          const float dLdP = dLda * al;
-          g[5] = fmaf(dLda, s.G, g[5]);
-          const float ae = r1.x * s.e;
-          g[0] = fmaf(dLdP, ae, g[0]);
-          g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * s.dy), g[1]);
-          const float hm = -0.5f * dLdP;
-          g[2] = fmaf(hm * s.dx, s.dx, g[2]);
-          g[3] = fmaf(2.f * hm * s.dx, s.dy, g[3]);
-          g[4] = fmaf(hm * s.dy, s.dy, g[4]);
-        }
+        const float d0 = r2.x - S0[q], d1 = r2.y - S1[q], d2 = r2.z - S2[q];
+        const float dLda = take ? Tj * (d0 * G0[q] + d1 * G1[q] + d2 * G2[q]) : 0.f;
+        S0[q] = take ? fmaf(al, d0, S0[q]) : S0[q];
+        S1[q] = take ? fmaf(al, d1, S1[q]) : S1[q];
+        S2[q] = take ? fmaf(al, d2, S2[q]) : S2[q];
+        const float dLda_u = clamped ? 0.f : dLda;   // the clamp cuts alpha off from opacity and power
+        const float dLdP = dLda_u * al;
+        g[5] = fmaf(dLda_u, Gs, g[5]);
+        const float ae = r1.x * sg.e;
+        g[0] = fmaf(dLdP, ae, g[0]);
+        g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * sg.dy), g[1]);
+        const float hm = -0.5f * dLdP;
+        g[2] = fmaf(hm * sg.dx, sg.dx, g[2]);
+        g[3] = fmaf(2.f * hm * sg.dx, sg.dy, g[3]);
+        g[4] = fmaf(hm * sg.dy, sg.dy, g[4]);
       }
       if (__ballot(contrib) == 0ull) continue;
       const float tot8 = reduce8(g, lo8);
