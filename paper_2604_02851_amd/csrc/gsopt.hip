@@ -134,6 +134,8 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   L.vis_b = take(4 * vn);
   L.vkey_a = take(4 * vn);
   L.vkey_b = take(4 * vn);
+  L.vrect_a = take(8 * vn);
+  L.vrect_b = take(8 * vn);
   L.koff = take(4 * (vn + 1));
   L.keys_a = take(4 * cap);
   L.keys_b = take(4 * cap);

@@ -51,6 +51,7 @@ struct WsLayout {
   size_t rec;         // float4x3 [VN] splat record
   size_t g2;          // float x12 [VN] screen-space gradients
   size_t vis_a, vis_b, vkey_a, vkey_b;  // u32 [VN] visible ids / depth keys (sort ping-pong)
+  size_t vrect_a, vrect_b;              // u16x4 [VN] tile rectangles carried through the depth sort
   size_t koff;        // u32 [VN+1] key offsets in depth order
   size_t keys_a, keys_b, vals_a, vals_b;  // u32 [cap]
   size_t hist;        // u32 [256 * max_blocks + 1]

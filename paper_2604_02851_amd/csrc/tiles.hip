@@ -54,7 +54,13 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wave
   return pre + inc - x;
 }
 
-// Value source of a scan: a[k], (a[k] != 0), or a[idx[k]].
+__device__ __forceinline__ uint32_t rect_area(uint2 r) {
+  // (tx0 | ty0 << 16, tx1 | ty1 << 16): inclusive tile rectangle
+  return ((r.y & 0xffffu) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.x >> 16) + 1u);
+}
+
+// Value source of a scan: a[k], (a[k] != 0), a[idx[k]], or the area of
+// tile rectangle k (mode 3, a = rectangles as uint2).
 struct ScanSrc {
   const uint32_t* a;
   const uint32_t* idx;
@@ -62,11 +68,19 @@ struct ScanSrc {
   __device__ __forceinline__ uint32_t operator()(uint32_t k) const {
     if (mode == 0) return a[k];
     if (mode == 1) return a[k] != 0u ? 1u : 0u;
+    if (mode == 3) return rect_area(reinterpret_cast<const uint2*>(a)[k]);
     return a[idx[k]];
   }
   // Four consecutive values from k (a multiple of 4) with one 16-byte load of
   // the directly indexed array.
   __device__ __forceinline__ void four(uint32_t k, uint32_t v[4]) const {
+    if (mode == 3) {
+      const uint4 x = *reinterpret_cast<const uint4*>(a + 2 * (size_t)k);
+      const uint4 y = *reinterpret_cast<const uint4*>(a + 2 * (size_t)k + 4);
+      v[0] = rect_area(make_uint2(x.x, x.y)), v[1] = rect_area(make_uint2(x.z, x.w));
+      v[2] = rect_area(make_uint2(y.x, y.y)), v[3] = rect_area(make_uint2(y.z, y.w));
+      return;
+    }
     const uint4 x = *reinterpret_cast<const uint4*>((mode == 2 ? idx : a) + k);
     if (mode == 0) {
       v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
@@ -205,14 +219,16 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
 
 // ---- visible compaction -----------------------------------------------------
 __global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* count, const uint32_t* depth,
-                                                         const uint32_t* pos, int64_t base, int64_t len,
-                                                         uint32_t* vis_ids, uint32_t* vis_keys) {
+                                                         const uint2* rect, const uint32_t* pos, int64_t base,
+                                                         int64_t len, uint32_t* vis_ids, uint32_t* vis_keys,
+                                                         uint2* vis_rect) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= len) return;
   if (count[base + k] != 0u) {
     const uint32_t p = pos[k];
     vis_ids[p] = (uint32_t)(base + k);
     vis_keys[p] = depth[base + k];
+    vis_rect[p] = rect[base + k];
   }
 }
 
@@ -247,18 +263,23 @@ __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, int64_t 
 // are placed in LDS in digit order (stable), 4) then written out with
 // consecutive threads taking consecutive local positions, so each digit's run
 // is stored contiguously: global position = scanned histogram of (digit,
-// chunk) + position within the digit's run.
+// chunk) + position within the digit's run.  With kPay, a 64-bit payload per
+// key follows the same permutation through the same LDS space afterwards.
 constexpr int kWaveKeys = kSortChunk / NW;
 constexpr int kWaveRounds = kWaveKeys / 64;
+constexpr int kOutRounds = kSortChunk / B;
 
+template <bool kPay>
 __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
-                                                     uint32_t* vout, int64_t max_count, const uint32_t* dcount,
-                                                     int shift, int64_t nblocks, const uint32_t* hist_scanned) {
-  __shared__ uint32_t s_key[kSortChunk];
-  __shared__ uint32_t s_val[kSortChunk];
+                                                     uint32_t* vout, const uint2* pin, uint2* pout,
+                                                     int64_t max_count, const uint32_t* dcount, int shift,
+                                                     int64_t nblocks, const uint32_t* hist_scanned) {
+  __shared__ __align__(16) uint32_t s_kv[2 * kSortChunk];   // keys | values, later the payload
   __shared__ uint32_t s_wc[NW][256];
   __shared__ uint32_t s_gbase[256];
   __shared__ uint32_t s_tmp[NW];
+  uint32_t* s_key = s_kv;
+  uint32_t* s_val = s_kv + kSortChunk;
   const uint32_t n = dev_count(dcount, max_count);
   const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
   if (begin >= n) return;
@@ -268,11 +289,13 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
 #pragma unroll
   for (int q = 0; q < NW; ++q) s_wc[q][threadIdx.x] = 0;
   uint32_t key[kWaveRounds], val[kWaveRounds], lr[kWaveRounds];
+  uint2 pay[kPay ? kWaveRounds : 1];
 #pragma unroll
   for (int r = 0; r < kWaveRounds; ++r) {
     const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
     key[r] = li < cnt ? kin[begin + li] : 0u;
     val[r] = li < cnt ? vin[begin + li] : 0u;
+    if constexpr (kPay) pay[r] = li < cnt ? pin[begin + li] : make_uint2(0u, 0u);
   }
   __syncthreads();
   // 1. stable ranks within (wavefront, digit)
@@ -317,22 +340,44 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
   }
   __syncthreads();
   // 3. local placement in digit order
+  uint32_t pos[kWaveRounds];
 #pragma unroll
   for (int r = 0; r < kWaveRounds; ++r) {
     const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
+    pos[r] = s_wc[w][(key[r] >> shift) & 255u] + lr[r];
     if (li < cnt) {
-      const uint32_t pos = s_wc[w][(key[r] >> shift) & 255u] + lr[r];
-      s_key[pos] = key[r];
-      s_val[pos] = val[r];
+      s_key[pos[r]] = key[r];
+      s_val[pos[r]] = val[r];
     }
   }
   __syncthreads();
   // 4. coalesced write-out
-  for (uint32_t i = threadIdx.x; i < cnt; i += B) {
-    const uint32_t k = s_key[i];
-    const uint32_t dst = s_gbase[(k >> shift) & 255u] + i;
-    kout[dst] = k;
-    vout[dst] = s_val[i];
+  uint32_t dst[kPay ? kOutRounds : 1];
+#pragma unroll
+  for (int r = 0; r < kOutRounds; ++r) {
+    const uint32_t i = (uint32_t)r * B + threadIdx.x;
+    if (i < cnt) {
+      const uint32_t k = s_key[i];
+      const uint32_t d = s_gbase[(k >> shift) & 255u] + i;
+      kout[d] = k;
+      vout[d] = s_val[i];
+      if constexpr (kPay) dst[r] = d;
+    }
+  }
+  if constexpr (kPay) {
+    uint2* s_pay = reinterpret_cast<uint2*>(s_kv);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kWaveRounds; ++r) {
+      const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
+      if (li < cnt) s_pay[pos[r]] = pay[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kOutRounds; ++r) {
+      const uint32_t i = (uint32_t)r * B + threadIdx.x;
+      if (i < cnt) pout[dst[r]] = s_pay[i];
+    }
   }
 }
 
@@ -342,7 +387,8 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
 // and finds the pair owning a slot by binary search over the 64 start
 // offsets, so a pair touching many tiles does not serialise its wavefront.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const uint32_t* koff, const uint32_t* nvis_p,
-                                              const uint32_t* total_keys, const ushort4* rect, const ViewInfo* views,
+                                              const uint32_t* total_keys, const ushort4* sorted_rect,
+                                              const ViewInfo* views,
                                               int64_t n_gauss, int32_t tile_begin, uint32_t cap, uint32_t* keys,
                                               uint32_t* vals) {
   __shared__ uint32_t s_off[4][64];
@@ -362,7 +408,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const 
     end = k0 + lane + 1 < nvis ? koff[k0 + lane + 1] : *total_keys;
     const int v = (int)(vi / (uint64_t)n_gauss);
     s_vi[w][lane] = vi;
-    s_rect[w][lane] = rect[vi];
+    s_rect[w][lane] = sorted_rect[k0 + lane];
     s_row[w][lane] = views[v].tile_base - tile_begin;
     s_tx[w][lane] = views[v].tiles_x;
   }
@@ -399,13 +445,34 @@ __global__ void k_key_total(Counters* c, const uint32_t* total_keys, uint32_t ca
   }
 }
 
+// Per-tile [start, end) of the sorted keys; thread q looks at keys 4q..4q+3
+// (one 16-byte load) and their two outer neighbours.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys, const uint32_t* count_p, uint32_t cap,
                                                 int32_t tile_begin, uint2* ranges) {
+  constexpr uint32_t kNone = 0xffffffffu;   // no tile id reaches this
   const uint32_t n = min(*count_p, cap);
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const uint32_t t = keys[k];
-    if (k == 0 || keys[k - 1] != t) ranges[tile_begin + t].x = k;
-    if (k == n - 1 || keys[k + 1] != t) ranges[tile_begin + t].y = k + 1;
+  const uint32_t nq = (n + 3u) / 4u;
+  const bool aligned = (reinterpret_cast<uintptr_t>(keys) & 15u) == 0;
+  for (uint32_t qd = blockIdx.x * blockDim.x + threadIdx.x; qd < nq; qd += gridDim.x * blockDim.x) {
+    const uint32_t k0 = qd * 4u;
+    uint32_t t[6];
+    if (aligned && k0 + 4u <= n) {
+      const uint4 x = *reinterpret_cast<const uint4*>(keys + k0);
+      t[1] = x.x, t[2] = x.y, t[3] = x.z, t[4] = x.w;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[1 + c] = k0 + c < n ? keys[k0 + c] : kNone;
+    }
+    t[0] = k0 > 0u ? keys[k0 - 1u] : kNone;
+    t[5] = k0 + 4u < n ? keys[k0 + 4u] : kNone;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t k = k0 + c;
+      if (k < n) {
+        if (t[c] != t[c + 1]) ranges[tile_begin + t[c + 1]].x = k;
+        if (t[c + 2] != t[c + 1]) ranges[tile_begin + t[c + 1]].y = k + 1u;
+      }
+    }
   }
 }
 
@@ -440,7 +507,8 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t max_count, con
 // Sorts (key, value) pairs on key bits [0, bits) in ping-pong buffers; returns
 // through *in_b whether the result landed in the second buffer.
 static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
-                             int64_t max_count, const uint32_t* dcount, int bits, bool* in_b, hipStream_t st) {
+                             uint2* pa, uint2* pb, int64_t max_count, const uint32_t* dcount, int bits, bool* in_b,
+                             hipStream_t st) {
   const int64_t nb = cdiv(max_count, kSortChunk);
   uint32_t* hist = seg<uint32_t>(ws, pl.ws.hist);
   uint32_t* partial = seg<uint32_t>(ws, pl.ws.partial);
@@ -451,13 +519,19 @@ static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* v
     uint32_t* vi = flip ? vb : va;
     uint32_t* ko = flip ? ka : kb;
     uint32_t* vo = flip ? va : vb;
+    uint2* pi = flip ? pb : pa;
+    uint2* po = flip ? pa : pb;
     if (nb > 0) {
       hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(B), 0, st, ki, max_count, dcount, shift, nb, hist);
       hipError_t e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * nb, nullptr, partial, pl.ws.partial_len,
                               nullptr, st);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, max_count, dcount,
-                         shift, nb, hist);
+      if (pa)
+        hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi, po,
+                           max_count, dcount, shift, nb, hist);
+      else
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi, po,
+                           max_count, dcount, shift, nb, hist);
     }
     flip = !flip;
   }
@@ -476,6 +550,8 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   uint32_t* vkey_a = seg<uint32_t>(ws, pl.ws.vkey_a);
   uint32_t* vkey_b = seg<uint32_t>(ws, pl.ws.vkey_b);
   uint32_t* koff = seg<uint32_t>(ws, pl.ws.koff);
+  uint2* vrect_a = seg<uint2>(ws, pl.ws.vrect_a);
+  uint2* vrect_b = seg<uint2>(ws, pl.ws.vrect_b);
   uint32_t* partial = seg<uint32_t>(ws, pl.ws.partial);
   uint32_t* keys_a = seg<uint32_t>(ws, pl.ws.keys_a);
   uint32_t* keys_b = seg<uint32_t>(ws, pl.ws.keys_b);
@@ -488,15 +564,17 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   // 1. visible compaction in (view, Gaussian) order: positions -> koff (scratch)
   e = scan_src(ScanSrc{count + base, nullptr, 1}, koff, len, nullptr, partial, pl.ws.partial_len, &ctr->nvis, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compact_visible, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, count, depth, koff, base,
-                     len, vis_a, vkey_a);
+  hipLaunchKernelGGL(k_compact_visible, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, count, depth,
+                     seg<uint2>(ws, pl.ws.rect), koff, base, len, vis_a, vkey_a, vrect_a);
   // 2. stable depth sort of the visible pairs (ties keep (view, Gaussian) order)
   bool in_b = false;
-  e = radix_sort(pl, ws, vkey_a, vis_a, vkey_b, vis_b, len, &ctr->nvis, 32, &in_b, st);
+  e = radix_sort(pl, ws, vkey_a, vis_a, vkey_b, vis_b, vrect_a, vrect_b, len, &ctr->nvis, 32, &in_b, st);
   if (e != hipSuccess) return e;
   const uint32_t* sorted_vis = in_b ? vis_b : vis_a;
+  const uint2* sorted_rect = in_b ? vrect_b : vrect_a;
   // 3. key offsets in depth order
-  e = scan_src(ScanSrc{count, sorted_vis, 2}, koff, len, &ctr->nvis, partial, pl.ws.partial_len, &ctr->keys, st);
+  e = scan_src(ScanSrc{reinterpret_cast<const uint32_t*>(sorted_rect), nullptr, 3}, koff, len, &ctr->nvis, partial,
+               pl.ws.partial_len, &ctr->keys, st);
   if (e != hipSuccess) return e;
   // ctr->keys holds the total; record it and the overflow flag
   hipLaunchKernelGGL(k_key_total, dim3(1), dim3(64), 0, st, ctr, &ctr->keys, cap);
@@ -504,19 +582,19 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   const int32_t tile_begin = pl.views[v0].tile_base;
   const int32_t tile_end = (v0 + nv < pl.n_views) ? pl.views[v0 + nv].tile_base : pl.total_tiles;
   hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, sorted_vis, koff, &ctr->nvis, &ctr->keys,
-                     seg<ushort4>(ws, pl.ws.rect), pl.d_views, N, tile_begin, cap, keys_a, vals_a);
+                     reinterpret_cast<const ushort4*>(sorted_rect), pl.d_views, N, tile_begin, cap, keys_a, vals_a);
   // 5. stable sort by tile (relative to the first tile of the call)
   const int64_t ntiles = tile_end - tile_begin;
   int bits = 0;
   while ((1ll << bits) < ntiles) ++bits;
   bits = bits == 0 ? 8 : ((bits + 7) / 8) * 8;
-  e = radix_sort(pl, ws, keys_a, vals_a, keys_b, vals_b, pl.cap, &ctr->keys, bits, &in_b, st);
+  e = radix_sort(pl, ws, keys_a, vals_a, keys_b, vals_b, nullptr, nullptr, pl.cap, &ctr->keys, bits, &in_b, st);
   if (e != hipSuccess) return e;
   // 6. ranges
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges + tile_begin), 0u, 2 * ntiles, st);
   if (e != hipSuccess) return e;
   const uint32_t* sk = in_b ? keys_b : keys_a;
-  const int64_t rblocks = cdiv(pl.cap, 256) < 8192 ? cdiv(pl.cap, 256) : 8192;
+  const int64_t rblocks = cdiv(pl.cap, 1024) < 8192 ? cdiv(pl.cap, 1024) : 8192;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)rblocks), dim3(256), 0, st, sk, &ctr->keys, cap, tile_begin, ranges);
   return hipGetLastError();
 }

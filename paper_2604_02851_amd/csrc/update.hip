@@ -17,26 +17,65 @@ struct AdamSeg {
 
 struct AdamArgs {
   AdamSeg seg[6];
+  int64_t chunk0[7];   // first chunk of each segment (exclusive prefix), chunk0[6] = total
   const int32_t* step;
   float beta1, beta2, eps;
 };
 
+constexpr int kAdamVec = 4;                    // elements per thread
+constexpr int kAdamChunk = 256 * kAdamVec;     // elements per workgroup
+
+__device__ __forceinline__ void adam_one(float& th, float g, float& m, float& v, float b1, float b2, float c1,
+                                         float c2, float step, float rbc2, float eps) {
+  m = fmaf(b1, m, c1 * g);
+  v = fmaf(b2, v, c2 * g * g);
+  th -= step * m / (sqrtf(v) * rbc2 + eps);
+}
+
+// One workgroup per chunk of kAdamChunk elements of one segment; thread t
+// updates 4 consecutive elements (one 16-byte access per array when the
+// segment is aligned, scalar otherwise and in the segment's tail).  The bias
+// corrections are computed once per workgroup in FP64.
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
-  const AdamSeg s = a.seg[blockIdx.y];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int t = *a.step + 1;
-  const double b1 = a.beta1, b2 = a.beta2;
-  const float bc1 = (float)(1.0 - pow(b1, (double)t));
-  const float rbc2 = (float)(1.0 / sqrt(1.0 - pow(b2, (double)t)));
-  const float c1 = 1.f - a.beta1, c2 = 1.f - a.beta2;
-  const float step = s.lr / bc1;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < s.count; k += stride) {
-    const float g = s.g[k];
-    const float m = fmaf(a.beta1, s.m[k], c1 * g);
-    const float v = fmaf(a.beta2, s.v[k], c2 * g * g);
-    s.m[k] = m;
-    s.v[k] = v;
-    s.theta[k] -= step * m / (sqrtf(v) * rbc2 + a.eps);
+  __shared__ float s_corr[2];
+  int si = 0;
+#pragma unroll
+  for (int q = 1; q < 6; ++q) si += (int64_t)blockIdx.x >= a.chunk0[q] ? 1 : 0;
+  const AdamSeg s = a.seg[si];
+  if (threadIdx.x == 0) {
+    const int t = *a.step + 1;
+    const double bc1 = 1.0 - pow((double)a.beta1, (double)t);
+    s_corr[0] = (float)bc1;
+    s_corr[1] = (float)(1.0 / sqrt(1.0 - pow((double)a.beta2, (double)t)));
+  }
+  __syncthreads();
+  const float step = s.lr / s_corr[0], rbc2 = s_corr[1];
+  const float b1 = a.beta1, b2 = a.beta2, c1 = 1.f - a.beta1, c2 = 1.f - a.beta2, eps = a.eps;
+  const int64_t k0 = ((int64_t)blockIdx.x - a.chunk0[si]) * kAdamChunk + (int64_t)threadIdx.x * kAdamVec;
+  if (k0 >= s.count) return;
+  const bool vec = k0 + kAdamVec <= s.count &&
+                   ((reinterpret_cast<uintptr_t>(s.theta) | reinterpret_cast<uintptr_t>(s.g) |
+                     reinterpret_cast<uintptr_t>(s.m) | reinterpret_cast<uintptr_t>(s.v)) & 15u) == 0;
+  if (vec) {
+    float4 th = *reinterpret_cast<const float4*>(s.theta + k0);
+    const float4 g = *reinterpret_cast<const float4*>(s.g + k0);
+    float4 m = *reinterpret_cast<const float4*>(s.m + k0);
+    float4 v = *reinterpret_cast<const float4*>(s.v + k0);
+    adam_one(th.x, g.x, m.x, v.x, b1, b2, c1, c2, step, rbc2, eps);
+    adam_one(th.y, g.y, m.y, v.y, b1, b2, c1, c2, step, rbc2, eps);
+    adam_one(th.z, g.z, m.z, v.z, b1, b2, c1, c2, step, rbc2, eps);
+    adam_one(th.w, g.w, m.w, v.w, b1, b2, c1, c2, step, rbc2, eps);
+    *reinterpret_cast<float4*>(s.m + k0) = m;
+    *reinterpret_cast<float4*>(s.v + k0) = v;
+    *reinterpret_cast<float4*>(s.theta + k0) = th;
+  } else {
+    for (int64_t k = k0; k < k0 + kAdamVec && k < s.count; ++k) {
+      float th = s.theta[k], m = s.m[k], v = s.v[k];
+      adam_one(th, s.g[k], m, v, b1, b2, c1, c2, step, rbc2, eps);
+      s.m[k] = m;
+      s.v[k] = v;
+      s.theta[k] = th;
+    }
   }
 }
 
@@ -163,12 +202,10 @@ hipError_t launch_adam(const gs_params& p, const gs_params& g, const gs_params& 
   a.beta1 = hp.beta1;
   a.beta2 = hp.beta2;
   a.eps = hp.eps;
-  const int64_t per_block = 256 * 4;
-  int64_t mx = 4 * n > (nk - 1) * 3 * n ? 4 * n : (nk - 1) * 3 * n;
-  int64_t blocks = (mx + per_block - 1) / per_block;
-  if (blocks < 1) blocks = 1;
-  if (blocks > 65535) blocks = 65535;
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks, 6), dim3(256), 0, st, a);
+  a.chunk0[0] = 0;
+  for (int q = 0; q < 6; ++q) a.chunk0[q + 1] = a.chunk0[q] + (a.seg[q].count + kAdamChunk - 1) / kAdamChunk;
+  if (a.chunk0[6] > 0x7fffffffll) return hipErrorInvalidValue;
+  if (a.chunk0[6] > 0) hipLaunchKernelGGL(k_adam, dim3((unsigned)a.chunk0[6]), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, st, step);
   return hipGetLastError();
 }
