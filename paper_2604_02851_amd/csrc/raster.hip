@@ -47,20 +47,53 @@ __device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t ntiles, i
   return xcd * (ntiles >> 3) + min(xcd, ntiles & 7u) + k;
 }
 
-// 3-sigma box of a splat in pixel-centre coordinates: (xmin, xmax, ymin, ymax).
-// With Q = [[a, a r], [a r, s + a r^2]], Sigma2_00 = 1/a + r^2/s and
-// Sigma2_11 = 1/s; the box is widened by 0.1% + 0.01 px for FP32 rounding.
-__device__ __forceinline__ float4 splat_box(const float4& r0, const float4& r1) {
-  const float sxx = 1.f / r1.x + r1.y * r1.y / r1.z;
-  const float syy = 1.f / r1.z;
-  const float hx = 3.003f * sqrtf(sxx) + 0.01f;
-  const float hy = 3.003f * sqrtf(syy) + 0.01f;
-  const float u = r0.x + r0.z, w = r0.y + r0.w;
-  return make_float4(u - hx, u + hx, w - hy, w + hy);
+// Culling of a splat against the pixel-centre rectangle [x0, x1] x [y0, y1]:
+// a lower bound of q = a (dx + r dy)^2 + s dy^2 (P = -q/2) over the
+// rectangle.  q is convex, so its minimum is 0 at the centre when the centre
+// lies inside, else it lies on an edge: along a horizontal edge (dy fixed) at
+// dx = -r dy, along a vertical edge (dx fixed) at dy = -a r dx / (a r^2 + s),
+// each clamped to the edge.  A pixel of the rectangle can pass the 3-sigma
+// test (q <= 9) only if this minimum is <= 9; the threshold is widened by
+// 0.1% + 0.01 for FP32 rounding of both evaluations, so culling never
+// changes a result.
+constexpr float kCullQ = 9.0f * 1.001f + 0.01f;
+
+__device__ __forceinline__ float rect_qmin(float a, float r, float s, float inv, float cu, float cw, float x0,
+                                           float x1, float y0, float y1) {
+  if (cu >= x0 && cu <= x1 && cw >= y0 && cw <= y1) return 0.f;
+  float best = INFINITY;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float dy = (k ? y1 : y0) - cw;
+    const float xs = fminf(fmaxf(cu - r * dy, x0), x1);
+    const float e = (xs - cu) + r * dy;
+    best = fminf(best, a * e * e + s * dy * dy);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float dx = (k ? x1 : x0) - cu;
+    const float dys = fminf(fmaxf(-a * r * dx * inv, y0 - cw), y1 - cw);
+    const float e = dx + r * dys;
+    best = fminf(best, a * e * e + s * dys * dys);
+  }
+  return best;
 }
 
-__device__ __forceinline__ bool box_misses(const float4& b, float xlo, float xhi, float ylo, float yhi) {
-  return b.x > xhi || b.y < xlo || b.z > yhi || b.w < ylo;
+// Bit w set when the splat may reach a pixel of wavefront w's sub-tile of the
+// tile whose top-left pixel is (tx0, ty0).
+template <class G, int SW>
+__device__ __forceinline__ uint32_t splat_wave_mask(const float4& r0, const float4& r1, int tx0, int ty0) {
+  const float cu = r0.x + r0.z, cw = r0.y + r0.w;
+  const float a = r1.x, r = r1.y, s = r1.z;
+  const float inv = 1.f / fmaf(a * r, r, s);
+  uint32_t m = 0;
+#pragma unroll
+  for (int w = 0; w < G::NWAVES; ++w) {
+    const float x0 = (float)(tx0 + (w % G::WPR) * SW) + 0.5f, x1 = x0 + (float)(SW - 1);
+    const float y0 = (float)(ty0 + (w / G::WPR) * G::WROWS) + 0.5f, y1 = y0 + (float)(G::WROWS - 1);
+    if (!(rect_qmin(a, r, s, inv, cu, cw, x0, x1, y0, y1) > kCullQ)) m |= 1u << w;
+  }
+  return m;
 }
 
 // Ranges are clamped to the key capacity so that a workspace whose lists were
@@ -161,17 +194,15 @@ template <int TW, int TH, int PPT, int SW, int BATCH>
 __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
   using G = Geom<TW, TH, PPT, SW>;
   __shared__ float4 s_rec[BATCH * 3];
-  __shared__ float4 s_box[BATCH];
+  __shared__ uint32_t s_mask[BATCH];
   const uint32_t slot = tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule);
   const int t = a.tile_begin + (int)slot;
   const ViewInfo view = a.views[a.tile_view[t]];
   const int local = t - view.tile_base;
   const int ty = local / view.tiles_x, tx = local - ty * view.tiles_x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x0 = tx * TW + (wave % G::WPR) * SW, y0 = ty * TH + (wave / G::WPR) * G::WROWS;
   const int px = x0 + lane % SW, py0 = y0 + lane / SW;
-  const float xlo = (float)x0 + 0.5f, xhi = (float)(x0 + SW) - 0.5f;
-  const float ylo = (float)y0 + 0.5f, yhi = (float)(y0 + G::WROWS) - 0.5f;
   const uint2 rg = clamp_range(a.ranges[t], a.cap);
   const float pxc = (float)px + 0.5f;
   float T[PPT], c0[PPT], c1[PPT], c2[PPT];
@@ -196,12 +227,12 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
       s_rec[j * 3 + 0] = r0;
       s_rec[j * 3 + 1] = r1;
       s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
-      s_box[j] = splat_box(r0, r1);
+      s_mask[j] = splat_wave_mask<G, SW>(r0, r1, tx * TW, ty * TH);
     }
     __syncthreads();
     if (live) {
       for (uint32_t j = 0; j < cnt; ++j) {
-        if (box_misses(s_box[j], xlo, xhi, ylo, yhi)) continue;
+        if (!((__builtin_amdgcn_readfirstlane(s_mask[j]) >> wave) & 1u)) continue;
         const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1], r2 = s_rec[j * 3 + 2];
         const uint32_t pos1 = b0 + j + 1;
 #pragma unroll
@@ -283,7 +314,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   using G = Geom<TW, TH, PPT, SW>;
   constexpr bool kMultiWave = G::NWAVES > 1;
   __shared__ float4 s_rec[BATCH * 3];
-  __shared__ float4 s_box[BATCH];
+  __shared__ uint32_t s_mask[BATCH];
   __shared__ uint32_t s_id[BATCH];
   __shared__ float s_g[kMultiWave ? G::NWAVES * BATCH * 9 : 1];   // per-wavefront splat sums of a batch
   __shared__ uint32_t s_max;
@@ -292,11 +323,9 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   const ViewInfo view = a.views[a.tile_view[t]];
   const int local = t - view.tile_base;
   const int ty = local / view.tiles_x, tx = local - ty * view.tiles_x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x0 = tx * TW + (wave % G::WPR) * SW, y0 = ty * TH + (wave / G::WPR) * G::WROWS;
   const int px = x0 + lane % SW, py0 = y0 + lane / SW;
-  const float xlo = (float)x0 + 0.5f, xhi = (float)(x0 + SW) - 0.5f;
-  const float ylo = (float)y0 + 0.5f, yhi = (float)(y0 + G::WROWS) - 0.5f;
   const uint2 rg = clamp_range(a.ranges[t], a.cap);
   const float pxc = (float)px + 0.5f;
   const int64_t HW = (int64_t)view.width * view.height;
@@ -354,13 +383,13 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       s_rec[j * 3 + 0] = r0;
       s_rec[j * 3 + 1] = r1;
       s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
-      s_box[j] = splat_box(r0, r1);
+      s_mask[j] = splat_wave_mask<G, SW>(r0, r1, tx * TW, ty * TH);
     }
     if (kMultiWave)
       for (uint32_t q = threadIdx.x; q < G::NWAVES * BATCH * 9; q += G::NT) s_g[q] = 0.f;
     __syncthreads();
     for (int j = (int)cnt - 1; j >= 0; --j) {
-      if (box_misses(s_box[j], xlo, xhi, ylo, yhi)) continue;
+      if (!((__builtin_amdgcn_readfirstlane(s_mask[j]) >> wave) & 1u)) continue;
       const uint32_t pos = b_begin + (uint32_t)j;
       const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1];
       const float4 r2 = s_rec[j * 3 + 2];
