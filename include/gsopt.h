@@ -134,6 +134,14 @@ gs_status gs_plan(gs_ctx ctx, int32_t n, int32_t sh_degree, int32_t n_views,
                   const gs_camera* host_cams, const gs_render_opts* opts,
                   int64_t key_capacity, size_t* workspace_bytes);
 
+/* Prepares a freshly allocated workspace of the current plan (enqueued on
+ * stream): clears the per-(view, Gaussian) screen-space gradient slots and
+ * the counters.  Call once after allocating the workspace and before its
+ * first use; later steps keep the slots cleared themselves (the projection
+ * adjoint clears every slot it has consumed).  GS_ERR_INVALID without a plan
+ * or with a NULL workspace. */
+gs_status gs_workspace_init(gs_ctx ctx, void* workspace, hipStream_t stream);
+
 /* Layout of the current plan: pixel_offsets[n_views+1] (pixel index of each
  * view's first pixel; images are planar CHW per view at 3*pixel_offsets[v])
  * and tile_offsets[n_views+1].  Either pointer may be NULL. */

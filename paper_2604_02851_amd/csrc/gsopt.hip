@@ -314,6 +314,16 @@ gs_status gs_frame_layout(gs_ctx c, int64_t* pix, int32_t* tiles) {
   return GS_OK;
 }
 
+gs_status gs_workspace_init(gs_ctx c, void* ws, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_workspace_init: no plan");
+  if (!ws) return fail(c, GS_ERR_INVALID, "gs_workspace_init: null workspace");
+  const Plan& pl = c->plan;
+  GS_HIP(c, launch_fill_u32(seg<uint32_t>(ws, pl.ws.g2), 0u, (int64_t)kG2Stride * pl.ws.vn, st));
+  GS_HIP(c, launch_fill_u32(seg<uint32_t>(ws, pl.ws.counters), 0u, (int64_t)(sizeof(Counters) / 4), st));
+  return GS_OK;
+}
+
 gs_status gs_project(gs_ctx c, const gs_params* params, const gs_camera* cams, int32_t v0, int32_t nv, void* ws,
                      hipStream_t st) {
   if (!c) return GS_ERR_INVALID;

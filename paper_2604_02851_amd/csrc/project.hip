@@ -1,8 +1,17 @@
 // Project/cull (forward) and the projection chain rule (backward).
 //
-// One thread per Gaussian loops over the views of the call, so the
-// parameters are read from HBM once per call, however many views it covers
-// (batched mode: all views of the step).  Geometry (camera-space mean,
+// A workgroup takes 64 Gaussians (one per lane) and its kViewWaves
+// wavefronts split the views of the call between them (view v goes to
+// wavefront v mod kViewWaves), so the parameters are read from HBM once per
+// call however many views it covers; the backward sums a Gaussian's views
+// over the wavefronts through LDS.  One wavefront measured fastest: the
+// FP64 per-Gaussian set-up is then not repeated.
+//
+// The screen-space gradient slots are all zero between steps: the
+// workspace is cleared once (gs_workspace_init), the compositing adjoint
+// adds into the slots of visible pairs only, and the colour part of the
+// projection adjoint, which reads each visible pair's slots last, clears
+// them again.  Geometry (camera-space mean,
 // covariance, screen-space conic, projected mean, tile rectangle) is
 // evaluated in FP64: the projected mean feeds every pixel test at up to
 // 1920 px, where FP32 leaves ~1e-4 px of error; FP64 costs little here
@@ -201,18 +210,21 @@ struct ProjArgs {
   uint32_t* count;
   ushort4* rect;
   float4* rec;
-  float4* g2;
 };
 
+constexpr int kViewWaves = 1;
+
 template <int DEG>
-__global__ __launch_bounds__(256) void k_project(ProjArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int wave = threadIdx.x >> 6;
   const int64_t n = a.p.n;
-  if (i >= n) return;
+  if (i >= n || wave >= a.nv) return;
   Gauss g;
   load_gauss<DEG>(a.p, i, g);
   constexpr int nk = (DEG + 1) * (DEG + 1);
-  for (int v = a.v0; v < a.v0 + a.nv; ++v) {
+#pragma unroll 1
+  for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) {
     const int64_t o = (int64_t)v * n + i;
     const gs_camera cam = a.cams[v];
     uint32_t cnt = 0;
@@ -253,10 +265,6 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
           a.rec[o * 3 + 0] = make_float4(uh, wh, ul, wl);
           a.rec[o * 3 + 1] = make_float4(qa, qr, qs, g.o);
           a.rec[o * 3 + 2] = make_float4(col[0], col[1], col[2], 0.f);
-          const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-          a.g2[o * 3 + 0] = zero;
-          a.g2[o * 3 + 1] = zero;
-          a.g2[o * 3 + 2] = zero;
         }
       }
     }
@@ -270,57 +278,36 @@ struct ProjBwdArgs {
   int v0, nv;
   const uint32_t* count;
   const float4* g2;
+  float4* g2z;   // the same slots, cleared by k_color_bwd after reading
   float* gmean; float* glsc; float* gquat; float* gopac; float* gsh;
   int accumulate;
 };
 
+// Geometric part of the projection adjoint (mean, log-scale, quaternion,
+// opacity); the SH coefficients and the view-direction term of the mean
+// gradient come from k_color_bwd, which runs after it.
 template <int DEG>
-__global__ __launch_bounds__(128) void k_project_bwd(ProjBwdArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) {
+  constexpr int kOut = 11;   // mean 3, log-scale 3, quaternion 4, opacity 1
+  __shared__ float s_part[kViewWaves > 1 ? kViewWaves - 1 : 1][kOut][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const int64_t n = a.p.n;
-  if (i >= n) return;
   Gauss g;
-  load_gauss<DEG>(a.p, i, g);
-  constexpr int nk = (DEG + 1) * (DEG + 1);
+  g.ok = false;
+  if (i < n && wave < a.nv) load_gauss<DEG>(a.p, i, g);
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
-  float gsh[3 * nk];
-#pragma unroll
-  for (int k = 0; k < 3 * nk; ++k) gsh[k] = 0.f;
-  for (int v = a.v0; v < a.v0 + a.nv && g.ok; ++v) {
+#pragma unroll 1
+  for (int v = a.v0 + wave; v < a.v0 + a.nv && g.ok; v += kViewWaves) {
     const int64_t o = (int64_t)v * n + i;
     if (a.count[o] == 0) continue;
-    const float4 t0 = a.g2[o * 3 + 0], t1 = a.g2[o * 3 + 1], t2 = a.g2[o * 3 + 2];
+    const float4 t0 = a.g2[o * 3 + 0], t1 = a.g2[o * 3 + 1];
     const double gu = t0.x, gw = t0.y, ga = t0.z, gb = t0.w, gc = t1.x, gop = t1.y;
-    const float gcol[3] = {t1.z, t1.w, t2.x};
     const gs_camera cam = a.cams[v];
     ViewGeom vg;
     view_geom(g, cam, vg);
     // opacity
     go += gop * (double)g.o * (1.0 - (double)g.o);
-    // colour -> SH coefficients and view direction
-    float d[3], len;
-    view_dir(cam, g.mu, d, &len);
-    float Y[16];
-    sh_basis(DEG, d[0], d[1], d[2], Y);
-    float wk[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) wk[k] = 0.f;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      float s = 0.5f;
-#pragma unroll
-      for (int k = 0; k < nk; ++k) s = fmaf(a.p.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], s);
-      const float gcc = s > 0.f ? gcol[ch] : 0.f;
-#pragma unroll
-      for (int k = 0; k < nk; ++k) {
-        gsh[k * 3 + ch] += Y[k] * gcc;
-        wk[k] += gcc * a.p.sh[(int64_t)(k * 3 + ch) * n + i];
-      }
-    }
-    float gd[3] = {0.f, 0.f, 0.f};
-    sh_grad_accum(DEG, d[0], d[1], d[2], wk, gd);
-    const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
-    for (int k = 0; k < 3; ++k) gm[k] += (double)((gd[k] - d[k] * dd) / len);
     // conic -> screen covariance: dL/dSigma2 = -Q G_Q Q
     const double qa = vg.C / vg.det, qb = -vg.B / vg.det, qc = vg.A / vg.det;
     const double S00 = -(qa * qa * ga + qa * qb * gb + qb * qb * gc);
@@ -386,15 +373,103 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjBwdArgs a) {
     const double dot = w_ * gr[0] + x_ * gr[1] + y_ * gr[2] + z_ * gr[3];
     for (int k = 0; k < 4; ++k) gq[k] += (gr[k] - g.rho[k] * dot) / g.qn;
   }
-  auto put = [&](float* dst, double val) {
-    if (a.accumulate) *dst += (float)val; else *dst = (float)val;
-  };
-  for (int k = 0; k < 3; ++k) put(&a.gmean[k * n + i], gm[k]);
-  for (int k = 0; k < 3; ++k) put(&a.glsc[k * n + i], gs[k]);
-  for (int k = 0; k < 4; ++k) put(&a.gquat[k * n + i], gq[k]);
-  put(&a.gopac[i], go);
+  // sum over the wavefronts: waves 1.. park their partial sums in LDS
+  float part[kOut];
 #pragma unroll
-  for (int k = 0; k < nk * 3; ++k) put(&a.gsh[(int64_t)k * n + i], gsh[k]);
+  for (int k = 0; k < 3; ++k) part[k] = (float)gm[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) part[3 + k] = (float)gs[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) part[6 + k] = (float)gq[k];
+  part[10] = (float)go;
+  if (wave > 0) {
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) s_part[wave - 1][k][lane] = part[k];
+  }
+  __syncthreads();
+  if (wave > 0 || i >= n) return;
+#pragma unroll
+  for (int w = 0; w < kViewWaves - 1; ++w)
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) part[k] += s_part[w][k][lane];
+  auto put = [&](float* dst, float val) {
+    if (a.accumulate) *dst += val; else *dst = val;
+  };
+  for (int k = 0; k < 3; ++k) put(&a.gmean[k * n + i], part[k]);
+  for (int k = 0; k < 3; ++k) put(&a.glsc[k * n + i], part[3 + k]);
+  for (int k = 0; k < 4; ++k) put(&a.gquat[k * n + i], part[6 + k]);
+  put(&a.gopac[i], part[10]);
+}
+
+// Colour part of the projection adjoint: SH coefficients, and the term of
+// the mean gradient that comes through the view direction (added to the mean
+// gradient written by k_project_bwd).
+template <int DEG>
+__global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
+  constexpr int nk = (DEG + 1) * (DEG + 1);
+  constexpr int kOut = 3 + 3 * nk;   // mean (direction term) 3, SH
+  __shared__ float s_part[kViewWaves > 1 ? kViewWaves - 1 : 1][kOut][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t n = a.p.n;
+  float part[kOut];
+#pragma unroll
+  for (int k = 0; k < kOut; ++k) part[k] = 0.f;
+  if (i < n && wave < a.nv) {
+    float sh[3 * nk];
+#pragma unroll
+    for (int k = 0; k < 3 * nk; ++k) sh[k] = a.p.sh[(int64_t)k * n + i];
+    const float mu[3] = {a.p.mean[i], a.p.mean[n + i], a.p.mean[2 * n + i]};
+#pragma unroll 1
+    for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) {
+      const int64_t o = (int64_t)v * n + i;
+      if (a.count[o] == 0) continue;
+      const float* g2 = reinterpret_cast<const float*>(a.g2) + o * kG2Stride;
+      const float gcol[3] = {g2[6], g2[7], g2[8]};
+      static_assert(kG2Stride == 12, "three float4 slots per pair");
+      float4* slot = a.g2z + o * 3;
+      slot[0] = slot[1] = slot[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+      float d[3], len;
+      view_dir(a.cams[v], mu, d, &len);
+      float Y[16];
+      sh_basis(DEG, d[0], d[1], d[2], Y);
+      float wk[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) wk[k] = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float s = 0.5f;
+#pragma unroll
+        for (int k = 0; k < nk; ++k) s = fmaf(sh[k * 3 + ch], Y[k], s);
+        const float gcc = s > 0.f ? gcol[ch] : 0.f;
+#pragma unroll
+        for (int k = 0; k < nk; ++k) {
+          part[3 + k * 3 + ch] += Y[k] * gcc;
+          wk[k] += gcc * sh[k * 3 + ch];
+        }
+      }
+      float gd[3] = {0.f, 0.f, 0.f};
+      sh_grad_accum(DEG, d[0], d[1], d[2], wk, gd);
+      const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+      for (int k = 0; k < 3; ++k) part[k] += (gd[k] - d[k] * dd) / len;
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) s_part[wave - 1][k][lane] = part[k];
+  }
+  __syncthreads();
+  if (wave > 0 || i >= n) return;
+#pragma unroll
+  for (int w = 0; w < kViewWaves - 1; ++w)
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) part[k] += s_part[w][k][lane];
+  for (int k = 0; k < 3; ++k) a.gmean[k * n + i] += part[k];
+#pragma unroll
+  for (int k = 0; k < nk * 3; ++k) {
+    float* dst = &a.gsh[(int64_t)k * n + i];
+    *dst = a.accumulate ? *dst + part[3 + k] : part[3 + k];
+  }
 }
 
 }  // namespace
@@ -413,14 +488,14 @@ hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* c
   a.count = seg<uint32_t>(ws, pl.ws.count);
   a.rect = seg<ushort4>(ws, pl.ws.rect);
   a.rec = seg<float4>(ws, pl.ws.rec);
-  a.g2 = seg<float4>(ws, pl.ws.g2);
-  const int blocks = (p.n + 255) / 256;
+  const int blocks = (p.n + 63) / 64;
   if (blocks == 0) return hipSuccess;
+  const dim3 block(64 * kViewWaves);
   switch (p.deg) {
-    case 0: hipLaunchKernelGGL(k_project<0>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 3: hipLaunchKernelGGL(k_project<3>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 0: hipLaunchKernelGGL(k_project<0>, dim3(blocks), block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, dim3(blocks), block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, dim3(blocks), block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_project<3>, dim3(blocks), block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -435,20 +510,28 @@ hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camer
   a.nv = nv;
   a.count = seg<uint32_t>(ws, pl.ws.count);
   a.g2 = seg<float4>(ws, pl.ws.g2);
+  a.g2z = seg<float4>(ws, pl.ws.g2);
   a.gmean = grads.mean;
   a.glsc = grads.log_scale;
   a.gquat = grads.quat;
   a.gopac = grads.opacity_logit;
   a.gsh = grads.sh;
   a.accumulate = accumulate;
-  const int blocks = (p.n + 127) / 128;
+  const int blocks = (p.n + 63) / 64;
   if (blocks == 0) return hipSuccess;
+  const dim3 block(64 * kViewWaves);
   switch (p.deg) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(blocks), dim3(128), 0, st, a); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(blocks), dim3(128), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(blocks), dim3(128), 0, st, a); break;
-    case 3: hipLaunchKernelGGL(k_project_bwd<3>, dim3(blocks), dim3(128), 0, st, a); break;
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(blocks), block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(blocks), block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(blocks), block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_project_bwd<3>, dim3(blocks), block, 0, st, a); break;
     default: return hipErrorInvalidValue;
+  }
+  switch (p.deg) {
+    case 0: hipLaunchKernelGGL(k_color_bwd<0>, dim3(blocks), block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_color_bwd<1>, dim3(blocks), block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_color_bwd<2>, dim3(blocks), block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_color_bwd<3>, dim3(blocks), block, 0, st, a); break;
   }
   return hipGetLastError();
 }

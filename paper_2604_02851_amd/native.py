@@ -20,7 +20,7 @@ GS_OK, GS_ERR_INVALID, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED, GS_ERR_S
 STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP",
                 -4: "GS_ERR_UNSUPPORTED", -5: "GS_ERR_STALE"}
 
-EXPORTED = ("gs_create", "gs_destroy", "gs_last_error", "gs_plan", "gs_frame_layout", "gs_project",
+EXPORTED = ("gs_create", "gs_destroy", "gs_last_error", "gs_plan", "gs_frame_layout", "gs_workspace_init", "gs_project",
             "gs_build_tile_lists", "gs_composite", "gs_backward", "gs_adam_step", "gs_delta_extract",
             "gs_delta_reset_baseline", "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
             "gs_step_launch", "gs_profile_enable", "gs_profile_read", "gs_profile_reset")
@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
         L.gs_plan.argtypes = [ctx, c_int32, c_int32, c_int32, c_void_p, POINTER(GsRenderOpts), c_int64,
                               POINTER(c_size_t)]
         L.gs_frame_layout.argtypes = [ctx, c_void_p, c_void_p]
+        L.gs_workspace_init.argtypes = [ctx, c_void_p, c_void_p]
         L.gs_project.argtypes = [ctx, POINTER(GsParams), c_void_p, c_int32, c_int32, c_void_p, c_void_p]
         L.gs_build_tile_lists.argtypes = [ctx, c_int32, c_int32, c_void_p, c_void_p]
         L.gs_composite.argtypes = [ctx, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
@@ -199,6 +200,9 @@ class Context:
         til = np.zeros(self.n_views + 1, np.int32)
         self._chk(self.L.gs_frame_layout(self.h, pix.ctypes.data_as(c_void_p), til.ctypes.data_as(c_void_p)))
         return pix, til
+
+    def workspace_init(self, ws, stream=None):
+        self._chk(self.L.gs_workspace_init(self.h, ptr(ws), stream_handle(stream)))
 
     def project(self, params: DeviceParams, dev_cams, v0, nv, ws, stream=None):
         p = params.struct()

@@ -47,6 +47,7 @@ class Renderer:
         nbytes = self.ctx.plan(self.n, self.sh_degree, self.cams, self.tile, self.batch_depth, self.bg,
                                self.loss_mode, self.key_capacity, self.ppt, self.wave_w, self.schedule)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ctx.workspace_init(self.ws)
         self.pix_off, self.tile_off = self.ctx.frame_layout()
 
     def replan(self, key_capacity: int):
