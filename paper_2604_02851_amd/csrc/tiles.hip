@@ -233,26 +233,46 @@ __global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* count, 
 }
 
 // ---- radix sort (LSD, 8-bit digits, stable) ---------------------------------
+// Digit counts of kHistChunks consecutive chunks per workgroup, one chunk
+// after the other; each thread loads its kSortItems keys of a chunk with
+// 16-byte loads (the scan chunk layout) and counts them with LDS atomics
+// into its wavefront's own sub-histogram, which bounds the contention of
+// skewed digits (the exponent byte of depth keys) to one wavefront.  Counts
+// are stored digit-major, hist[d * nblocks + chunk]; a workgroup writes each
+// digit's kHistChunks counts as one contiguous run.
+constexpr int kHistChunks = 4;
+
 __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, int64_t max_count, const uint32_t* dcount,
                                                   int shift, int64_t nblocks, uint32_t* hist) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  __shared__ uint32_t h[NW][kHistChunks][256];
+#pragma unroll
+  for (int q = 0; q < NW * kHistChunks; ++q) (&h[0][0][0])[q * 256 + threadIdx.x] = 0;
   __syncthreads();
   const uint32_t n = dev_count(dcount, max_count);
-  const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
-  if (begin < n) {
+  const int w = threadIdx.x >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * kHistChunks;
+  const ScanSrc src{keys, nullptr, 0};
+  for (int cc = 0; cc < kHistChunks; ++cc) {
+    const uint64_t begin = (uint64_t)(c0 + cc) * kSortChunk;
+    if (c0 + cc >= nblocks || begin >= n) break;
     uint32_t v[kRounds][4];
-    load_chunk(ScanSrc{keys, nullptr, 0}, begin, n, v);
+    load_chunk(src, begin, n, v);
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-      const uint64_t k = begin + (uint64_t)r * 4 * B + 4u * threadIdx.x;
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        if (k + c < n) atomicAdd(&h[(v[r][c] >> shift) & 255u], 1u);
+        if (begin + (uint64_t)r * 4 * B + 4u * threadIdx.x + c < n) atomicAdd(&h[w][cc][(v[r][c] >> shift) & 255u], 1u);
     }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  uint32_t* dst = hist + (int64_t)threadIdx.x * nblocks + c0;
+#pragma unroll
+  for (int c = 0; c < kHistChunks; ++c) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) t += h[q][c][threadIdx.x];
+    if (c0 + c < nblocks) dst[c] = t;
+  }
 }
 
 // Scatter of one chunk (kSortChunk keys, split into NW contiguous wavefront
@@ -383,9 +403,29 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
 
 // ---- key emission in depth order -----------------------------------------
 // One wavefront writes the keys of 64 consecutive depth-sorted visible pairs:
-// lane l produces output slots start + l, start + l + 64, ... (coalesced),
-// and finds the pair owning a slot by binary search over the 64 start
-// offsets, so a pair touching many tiles does not serialise its wavefront.
+// in each round lane l produces output slot S + l (coalesced stores).  The
+// pair owning a slot is found without searching: each pair whose first slot
+// falls in the round marks that slot with its index, and an inclusive max-scan
+// over the lanes (carried from the previous round) hands every slot the last
+// pair that started at or before it.  The slot's tile within the pair's
+// rectangle comes from a float-reciprocal quotient corrected to the exact
+// integer one.
+
+// Inclusive max-scan over the 64 lanes (values >= -1).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_max(int v) {
+  return max(v, __builtin_amdgcn_update_dpp(-1, v, CTRL, ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ int wave_incl_max(int v) {
+  v = dpp_max<0x111, 0xf>(v);   // row_shr:1
+  v = dpp_max<0x112, 0xf>(v);   // row_shr:2
+  v = dpp_max<0x114, 0xf>(v);   // row_shr:4
+  v = dpp_max<0x118, 0xf>(v);   // row_shr:8
+  v = dpp_max<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_max<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const uint32_t* koff, const uint32_t* nvis_p,
                                               const uint32_t* total_keys, const ushort4* sorted_rect,
                                               const ViewInfo* views,
@@ -394,8 +434,10 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const 
   __shared__ uint32_t s_off[4][64];
   __shared__ uint32_t s_vi[4][64];
   __shared__ ushort4 s_rect[4][64];
+  __shared__ float s_rw[4][64];      // 1 / rectangle width
   __shared__ int32_t s_row[4][64];   // first tile of the pair's view, relative to the call's first tile
   __shared__ int32_t s_tx[4][64];    // tiles per row in the pair's view
+  __shared__ int32_t s_mark[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t nvis = *nvis_p;
   const uint32_t k0 = (blockIdx.x * 4u + (uint32_t)w) * 64u;
@@ -407,8 +449,10 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const 
     off = koff[k0 + lane];
     end = k0 + lane + 1 < nvis ? koff[k0 + lane + 1] : *total_keys;
     const int v = (int)(vi / (uint64_t)n_gauss);
+    const ushort4 r = sorted_rect[k0 + lane];
     s_vi[w][lane] = vi;
-    s_rect[w][lane] = sorted_rect[k0 + lane];
+    s_rect[w][lane] = r;
+    s_rw[w][lane] = __builtin_amdgcn_rcpf((float)((uint32_t)r.z - r.x + 1u));
     s_row[w][lane] = views[v].tile_base - tile_begin;
     s_tx[w][lane] = views[v].tiles_x;
   }
@@ -419,19 +463,32 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const 
   uint32_t stop = end;
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) stop = max(stop, (uint32_t)__shfl_xor((int)stop, d, 64));
-  for (uint32_t slot = start + (uint32_t)lane; slot < stop; slot += 64) {
-    int lo = 0, hi = (int)nent - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[w][mid] <= slot) lo = mid; else hi = mid - 1;
-    }
-    const ushort4 r = s_rect[w][lo];
-    const uint32_t m = slot - s_off[w][lo];
-    const uint32_t width = (uint32_t)r.z - r.x + 1u;
-    const uint32_t ty = r.y + m / width, tx = r.x + m % width;
-    if (slot < cap) {
-      keys[slot] = (uint32_t)(s_row[w][lo] + (int32_t)(ty * (uint32_t)s_tx[w][lo] + tx));
-      vals[slot] = s_vi[w][lo];
+  int carry = -1;
+  for (uint32_t S = start; S < stop; S += 64) {
+    s_mark[w][lane] = -1;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && off >= S && off - S < 64u) s_mark[w][off - S] = lane;
+    __builtin_amdgcn_wave_barrier();
+    const int own = wave_incl_max(max(s_mark[w][lane], carry));
+    carry = __builtin_amdgcn_readlane(own, 63);
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t slot = S + (uint32_t)lane;
+    if (slot < stop && slot < cap) {
+      const ushort4 r = s_rect[w][own];
+      const uint32_t m = slot - s_off[w][own];
+      const uint32_t width = (uint32_t)r.z - r.x + 1u;
+      uint32_t q = (uint32_t)((float)m * s_rw[w][own]);
+      int32_t rem = (int32_t)(m - q * width);
+      if (rem < 0) {
+        q -= 1u;
+        rem += (int32_t)width;
+      } else if (rem >= (int32_t)width) {
+        q += 1u;
+        rem -= (int32_t)width;
+      }
+      const uint32_t ty = r.y + q, tx = r.x + (uint32_t)rem;
+      keys[slot] = (uint32_t)(s_row[w][own] + (int32_t)(ty * (uint32_t)s_tx[w][own] + tx));
+      vals[slot] = s_vi[w][own];
     }
   }
 }
@@ -522,7 +579,8 @@ static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* v
     uint2* pi = flip ? pb : pa;
     uint2* po = flip ? pa : pb;
     if (nb > 0) {
-      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(B), 0, st, ki, max_count, dcount, shift, nb, hist);
+      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)cdiv(nb, kHistChunks)), dim3(B), 0, st, ki, max_count, dcount,
+                         shift, nb, hist);
       hipError_t e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * nb, nullptr, partial, pl.ws.partial_len,
                               nullptr, st);
       if (e != hipSuccess) return e;
