@@ -14,7 +14,7 @@
 // the workgroup once every pixel has stopped; saves T_final, the contributor
 // count and the last composited list position.
 // Backward: walks the list back to front from each pixel's last position,
-// rebuilding the transmittance by division (in FP64); a splat's screen-space
+// rebuilding the transmittance by division (FP32 reciprocal); a splat's screen-space
 // gradient is summed over the thread's pixels in registers, then over the
 // wavefront with DPP row operations, then over the wavefronts of the tile in
 // LDS, and finally added once per (tile, splat, field) to the global
@@ -307,8 +307,10 @@ struct BwdArgs {
 //   T_j = T_{j+1} / (1 - alpha_j)
 //   d out / d col_j   = alpha_j T_j
 //   d out / d alpha_j = T_j (col_j - S_j),   S_{j-1} = alpha_j col_j + (1 - alpha_j) S_j
-// The division chain runs in FP64, so the rebuilt T_j carry only the FP32
-// rounding of the forward product they start from.
+// The division chain runs in FP32 with the hardware reciprocal: each step adds
+// at most about 4 units of 2^-24 to T_j's relative error (reciprocal, product,
+// and 1 - alpha), which stays inside the same E_p = sum 1/(1 - alpha) bound
+// as the forward product's own rounding.
 template <int TW, int TH, int PPT, int SW, int BATCH>
 __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   using G = Geom<TW, TH, PPT, SW>;
@@ -336,14 +338,14 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   if (threadIdx.x == 0) s_max = rg.x;
   __syncthreads();
   float G0[PPT], G1[PPT], G2[PPT], S0[PPT], S1[PPT], S2[PPT];
-  double T[PPT];
+  float T[PPT];
   uint32_t last[PPT];
   float lossv = 0.f;
   uint32_t my_max = rg.x;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     G0[q] = G1[q] = G2[q] = 0.f;
-    T[q] = 1.0;
+    T[q] = 1.f;
     S0[q] = a.bg0;
     S1[q] = a.bg1;
     S2[q] = a.bg2;
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         G2[q] = wv * (float)((d2 > 0.f) - (d2 < 0.f));
         lossv += wv * (fabsf(d0) + fabsf(d1) + fabsf(d2));
       }
-      T[q] = (double)a.T[view.pix_off + p];
+      T[q] = a.T[view.pix_off + p];
       last[q] = min(max(a.last[view.pix_off + p], rg.x), rg.y);
       my_max = max(my_max, last[q]);
     }
@@ -408,9 +410,8 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         const bool take = splat_alpha(sg.P, r1.w, Gs, al, clamped) && cand;
         contrib = contrib || take;
         // predicated from here on; lanes that do not take the splat add zeros
-        const double Tjd = T[q] * __builtin_amdgcn_rcp(1.0 - (double)al);
-        T[q] = take ? Tjd : T[q];
-        const float Tj = (float)Tjd;
+        const float Tj = T[q] * __builtin_amdgcn_rcpf(1.f - al);
+        T[q] = take ? Tj : T[q];
         const float at = take ? al * Tj : 0.f;
         g[6] = fmaf(at, G0[q], g[6]);
         g[7] = fmaf(at, G1[q], g[7]);
