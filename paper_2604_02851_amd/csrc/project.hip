@@ -105,8 +105,10 @@ struct Gauss {
   bool ok;
 };
 
-template <int DEG>
-__device__ __forceinline__ void load_gauss(const ParamPtrs& p, int64_t i, Gauss& g) {
+// sh_finite: whether the Gaussian's SH coefficients are all finite (the
+// caller checks them where it loads them, or passes true where only pairs
+// already found visible are visited).
+__device__ __forceinline__ void load_gauss(const ParamPtrs& p, int64_t i, Gauss& g, bool sh_finite) {
   const int64_t n = p.n;
   bool fin = true;
   for (int k = 0; k < 3; ++k) {
@@ -117,10 +119,7 @@ __device__ __forceinline__ void load_gauss(const ParamPtrs& p, int64_t i, Gauss&
   for (int k = 0; k < 3; ++k) { ls[k] = p.lsc[k * n + i]; fin &= isfinite(ls[k]); }
   for (int k = 0; k < 4; ++k) { q[k] = p.quat[k * n + i]; fin &= isfinite(q[k]); }
   const float w = p.opac[i];
-  fin &= isfinite(w);
-  constexpr int nsh = 3 * (DEG + 1) * (DEG + 1);
-#pragma unroll
-  for (int k = 0; k < nsh; ++k) fin &= isfinite(p.sh[k * n + i]);
+  fin &= isfinite(w) && sh_finite;
   const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
   g.qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   g.ok = fin && g.qn > 0.0;
@@ -220,9 +219,20 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
   const int wave = threadIdx.x >> 6;
   const int64_t n = a.p.n;
   if (i >= n || wave >= a.nv) return;
-  Gauss g;
-  load_gauss<DEG>(a.p, i, g);
   constexpr int nk = (DEG + 1) * (DEG + 1);
+  // SH coefficients parked in this wavefront's own LDS columns (each lane
+  // reads back only what it wrote, so no barrier is needed)
+  __shared__ float s_sh[kViewWaves][3 * nk][64];
+  const int lane = threadIdx.x & 63;
+  bool sh_ok = true;
+#pragma unroll
+  for (int k = 0; k < 3 * nk; ++k) {
+    const float c = a.p.sh[(int64_t)k * n + i];
+    sh_ok &= isfinite(c);
+    s_sh[wave][k][lane] = c;
+  }
+  Gauss g;
+  load_gauss(a.p, i, g, sh_ok);
 #pragma unroll 1
   for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) {
     const int64_t o = (int64_t)v * n + i;
@@ -259,7 +269,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
           for (int ch = 0; ch < 3; ++ch) {
             float s = 0.5f;
 #pragma unroll
-            for (int k = 0; k < nk; ++k) s = fmaf(a.p.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], s);
+            for (int k = 0; k < nk; ++k) s = fmaf(s_sh[wave][k * 3 + ch][lane], Y[k], s);
             col[ch] = fmaxf(s, 0.f);
           }
           a.rec[o * 3 + 0] = make_float4(uh, wh, ul, wl);
@@ -295,7 +305,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
   const int64_t n = a.p.n;
   Gauss g;
   g.ok = false;
-  if (i < n && wave < a.nv) load_gauss<DEG>(a.p, i, g);
+  if (i < n && wave < a.nv) load_gauss(a.p, i, g, true);
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
 #pragma unroll 1
   for (int v = a.v0 + wave; v < a.v0 + a.nv && g.ok; v += kViewWaves) {
@@ -415,10 +425,12 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
   float part[kOut];
 #pragma unroll
   for (int k = 0; k < kOut; ++k) part[k] = 0.f;
+  __shared__ float s_sh[kViewWaves][3 * nk][64];   // per-lane columns: no barrier needed
   if (i < n && wave < a.nv) {
-    float sh[3 * nk];
+    float* sh_col = &s_sh[wave][0][lane];
 #pragma unroll
-    for (int k = 0; k < 3 * nk; ++k) sh[k] = a.p.sh[(int64_t)k * n + i];
+    for (int k = 0; k < 3 * nk; ++k) sh_col[k * 64] = a.p.sh[(int64_t)k * n + i];
+#define SH(k) sh_col[(k) * 64]
     const float mu[3] = {a.p.mean[i], a.p.mean[n + i], a.p.mean[2 * n + i]};
 #pragma unroll 1
     for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) {
@@ -440,12 +452,12 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
       for (int ch = 0; ch < 3; ++ch) {
         float s = 0.5f;
 #pragma unroll
-        for (int k = 0; k < nk; ++k) s = fmaf(sh[k * 3 + ch], Y[k], s);
+        for (int k = 0; k < nk; ++k) s = fmaf(SH(k * 3 + ch), Y[k], s);
         const float gcc = s > 0.f ? gcol[ch] : 0.f;
 #pragma unroll
         for (int k = 0; k < nk; ++k) {
           part[3 + k * 3 + ch] += Y[k] * gcc;
-          wk[k] += gcc * sh[k * 3 + ch];
+          wk[k] += gcc * SH(k * 3 + ch);
         }
       }
       float gd[3] = {0.f, 0.f, 0.f};
@@ -453,6 +465,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
       const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
       for (int k = 0; k < 3; ++k) part[k] += (gd[k] - d[k] * dd) / len;
     }
+#undef SH
   }
   if (wave > 0) {
 #pragma unroll
