@@ -99,6 +99,57 @@ def cpu_baseline(w, min_seconds: float):
                        f"by pixel count to {t_step:.1f} s per step")}
 
 
+def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log) -> dict:
+    """Steps/s of one synthetic workload (graph replay of the batched step, the
+    given launch shape; cfg5 also extracts the delta of all six attribute
+    groups after each step, on the scene after one round of object motion and
+    relighting)."""
+    from paper_2604_02851_amd import scenes as S
+    from paper_2604_02851_amd.native import DeviceParams
+    from paper_2604_02851_amd.renderer import Optimizer, Renderer
+    import numpy as np
+    w = S.workload(cfg)
+    stream = torch.cuda.current_stream()
+    pert = w.extra.get("perturbed")
+    if cfg == 5:
+        S.Dynamics(w.extra["rng_dyn"], w.scene).step([w.scene, pert])
+    params = DeviceParams.from_scene(w.scene)
+    r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, loss_mode=1, **shape)
+    r.fit_capacity(params)
+    if pert is not None:            # targets: render of the perturbed copy
+        pdev = DeviceParams.from_scene(pert)
+        r.fit_capacity(pdev)
+        targets = r.forward(pdev)[0].clone()
+        del pdev
+    else:                           # the workload's own target image
+        targets = torch.from_numpy(np.ascontiguousarray(w.extra["target"], np.float32).reshape(-1)).to(r.device)
+    opt = Optimizer(r, params, targets, stream=stream)
+    if cfg == 5:
+        opt.enable_delta(params.clone(), 0x3F, 1e-3)
+    opt.step()
+    torch.cuda.synchronize()
+    opt.capture()
+    for _ in range(warmup):
+        opt.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        opt.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    if r.counters().overflow:
+        raise SystemExit(f"cfg{cfg}: key capacity overflowed during the timed steps")
+    out = {"steps_per_s": round(1000.0 / ms, 3), "ms_per_step": round(ms, 4), "views": len(w.cams),
+           "views_per_s": round(len(w.cams) * 1000.0 / ms, 2), "gaussians": w.scene.n, "pixels": w.n_pixels,
+           "keys": int(r.counters().keys), "delta": cfg == 5}
+    log(f"[bench] {w.name}: {ms:.3f} ms/step ({1000 / ms:.2f} steps/s)")
+    del opt, r, params, targets
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +165,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time of the CPU baseline sample")
+    ap.add_argument("--no-configs", action="store_true", help="skip the steps/s of the other workloads")
     ap.add_argument("--calib-copy", action="store_true", help="run only a plain 1 GiB device copy (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -241,6 +293,13 @@ def main():
         cpu = cpu_baseline(w, args.cpu_seconds)
         log(f"[bench] cpu baseline {cpu['value']:.3g} steps/s ({time.perf_counter() - t:.1f} s)")
 
+    wave_w, schedule = r.wave_w, r.schedule
+    configs = None
+    if not args.no_configs:
+        del opt, r, targets, params, pert
+        torch.cuda.empty_cache()
+        configs = {f"cfg{k}": config_rate(k, shape, 10, 2, torch, log) for k in (1, 2, 3, 5)}
+
     out = {
         "metric": METRIC, "value": round(1000.0 / ms_batched, 3), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batched, 4),
@@ -251,7 +310,7 @@ def main():
                                "replayed from a HIP graph",
                    "gaussians": w.scene.n, "views": len(w.cams), "pixels": w.n_pixels,
                    "tile": f"{tile[0]}x{tile[1]}", "batch_depth": batch, "pixels_per_thread": ppt,
-                   "wave_w": r.wave_w, "schedule": r.schedule,
+                   "wave_w": wave_w, "schedule": schedule,
                    "autotuned": tuned is not None,
                    "keys": int(c.keys), "visible_pairs": int(c.visible), "parallelism": "1 GPU"},
         "views_per_s": round(len(w.cams) * 1000.0 / ms_batched, 2),
@@ -261,6 +320,7 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "other_workloads": configs,
     }
     print(json.dumps(out), flush=True)
 
