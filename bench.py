@@ -99,11 +99,12 @@ def cpu_baseline(w, min_seconds: float):
                        f"by pixel count to {t_step:.1f} s per step")}
 
 
-def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log) -> dict:
+def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log, frozen: float = 0.0) -> dict:
     """Steps/s of one synthetic workload (graph replay of the batched step, the
     given launch shape; cfg5 also extracts the delta of all six attribute
     groups after each step, on the scene after one round of object motion and
-    relighting)."""
+    relighting).  frozen: fraction of the Gaussians in the frozen pool
+    (rendered, not optimised; the last ones)."""
     from paper_2604_02851_amd import scenes as S
     from paper_2604_02851_amd.native import DeviceParams
     from paper_2604_02851_amd.renderer import Optimizer, Renderer
@@ -123,7 +124,8 @@ def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log) -> d
         del pdev
     else:                           # the workload's own target image
         targets = torch.from_numpy(np.ascontiguousarray(w.extra["target"], np.float32).reshape(-1)).to(r.device)
-    opt = Optimizer(r, params, targets, stream=stream)
+    n_active = w.scene.n - int(round(frozen * w.scene.n))
+    opt = Optimizer(r, params, targets, stream=stream, n_active=n_active)
     if cfg == 5:
         opt.enable_delta(params.clone(), 0x3F, 1e-3)
     opt.step()
@@ -143,8 +145,8 @@ def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log) -> d
         raise SystemExit(f"cfg{cfg}: key capacity overflowed during the timed steps")
     out = {"steps_per_s": round(1000.0 / ms, 3), "ms_per_step": round(ms, 4), "views": len(w.cams),
            "views_per_s": round(len(w.cams) * 1000.0 / ms, 2), "gaussians": w.scene.n, "pixels": w.n_pixels,
-           "keys": int(r.counters().keys), "delta": cfg == 5}
-    log(f"[bench] {w.name}: {ms:.3f} ms/step ({1000 / ms:.2f} steps/s)")
+           "keys": int(r.counters().keys), "delta": cfg == 5, "active_gaussians": n_active}
+    log(f"[bench] {w.name} ({n_active} active): {ms:.3f} ms/step ({1000 / ms:.2f} steps/s)")
     del opt, r, params, targets
     torch.cuda.empty_cache()
     return out
@@ -299,6 +301,8 @@ def main():
         del opt, r, targets, params, pert
         torch.cuda.empty_cache()
         configs = {f"cfg{k}": config_rate(k, shape, 10, 2, torch, log) for k in (1, 2, 3, 5)}
+        # Gaussian freezing: cfg4 with half of the model in the frozen pool
+        configs["cfg4_half_frozen"] = config_rate(4, shape, 10, 2, torch, log, frozen=0.5)
 
     out = {
         "metric": METRIC, "value": round(1000.0 / ms_batched, 3), "unit": "steps/s", "n_gpus": 1,

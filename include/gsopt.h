@@ -180,7 +180,12 @@ gs_status gs_composite(gs_ctx ctx, int32_t view_begin, int32_t view_count, void*
  *  mode 0: dev_upstream is dL/dimage (image layout);
  *  mode 1: dev_upstream is the target image; L1 loss with the plan's
  *          loss_mode; *dev_loss (device FP32) receives the loss of these views.
- *  accumulate 0 writes grads, 1 adds to them.  dev_loss may be NULL in mode 0. */
+ *  accumulate 0 writes grads, 1 adds to them.  dev_loss may be NULL in mode 0.
+ * Active and frozen pools (Sec. 3.3, Gaussian freezing): grads->n may be
+ * smaller than params->n.  Then only the first grads->n Gaussians (the
+ * active pool) are differentiated, and grads rows are strided by grads->n;
+ * the others (the frozen pool) are rendered and shape every pixel's
+ * transmittance and colour as before but receive no gradient work. */
 gs_status gs_backward(gs_ctx ctx, const gs_params* params, const gs_camera* dev_cams,
                       int32_t view_begin, int32_t view_count, void* dev_workspace,
                       const float* dev_images, const float* dev_T_final, const float* dev_upstream,
@@ -189,10 +194,30 @@ gs_status gs_backward(gs_ctx ctx, const gs_params* params, const gs_camera* dev_
 
 /* Fused Adam over all parameter tensors (configured learning rates,
  * Sec. 3.1).  *dev_step holds the number of steps taken so far; the update
- * uses t = *dev_step + 1 and a following kernel stores t. */
+ * uses t = *dev_step + 1 and a following kernel stores t.  grads, m and v
+ * describe the active pool (n <= params->n, rows strided by their n): only
+ * the first grads->n Gaussians of each parameter row are updated; frozen
+ * Gaussians keep their values and need no moments (Sec. 3.3). */
 gs_status gs_adam_step(gs_ctx ctx, const gs_params* params, const gs_params* grads,
                        const gs_params* m, const gs_params* v, int32_t* dev_step,
                        const gs_adam_hparams* hp, hipStream_t stream);
+
+/* Moves active Gaussians into the frozen pool (Sec. 3.3: as regions become
+ * stable their Gaussians leave the trainable set but stay renderable).
+ * flags[i] != 0 (device bytes, i < m->n) marks active Gaussian i for
+ * freezing.  In place, as a stable partition of the active prefix: the
+ * Gaussians that stay active keep their order at the front, followed by the
+ * newly frozen ones in their order, followed by the Gaussians frozen before
+ * (unchanged).  The same permutation is applied to every row of params
+ * (n = planned n), to baseline (optional, n = planned n) and to ids
+ * (optional, uint32 per Gaussian, e.g. stable Gaussian IDs for the delta
+ * stream).  m and v (n = current active count) are compacted to the new
+ * active count n' (rows strided by n').  *new_active (device int32)
+ * receives n'; after synchronising the caller describes grads, m and v with
+ * n = n' (the same storage).  Enqueued on stream; uses the workspace. */
+gs_status gs_freeze(gs_ctx ctx, gs_params* params, gs_params* m, gs_params* v, const uint8_t* flags,
+                    uint32_t* ids, gs_params* baseline, void* dev_workspace, int32_t* new_active,
+                    hipStream_t stream);
 
 /* Changed-Gaussian delta (Sec. 3.5: per-attribute tensor deltas relative to
  * the previously transmitted state, Gaussian-ID ordering).  Groups, in this

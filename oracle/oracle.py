@@ -239,3 +239,24 @@ def delta(cur_scene, base_scene, mask: int = 0x3F, tau: float = 1e-3):
     out = np.zeros(delta_capacity_words(n, cur_scene.sh_degree, mask), np.uint32)
     w = lib().or_delta(cp, bp, _p(widths), n, mask, float(np.float32(tau)), _p(out))
     return out[:w]
+
+
+def freeze_partition(rows_all, rows_active, flags, n_active):
+    """Gaussian freezing (active and frozen pools): the stable partition that
+    moves the active Gaussians flagged for freezing behind the ones that stay
+    active, ahead of the previously frozen ones.
+
+    rows_all: list of [r, N] arrays (parameters, baselines, ids) permuted along
+    the Gaussian axis; rows_active: list of [r, n_active] arrays (optimizer
+    moments) restricted to the Gaussians that stay active.  Returns
+    (permuted rows_all, compacted rows_active, new active count, order) where
+    order[j] is the old index of the Gaussian now at j."""
+    flags = np.asarray(flags).astype(bool)
+    assert flags.shape == (n_active,)
+    keep = np.nonzero(~flags)[0]
+    moved = np.nonzero(flags)[0]
+    n = rows_all[0].shape[-1] if rows_all else n_active
+    order = np.concatenate([keep, moved, np.arange(n_active, n)]).astype(np.int64)
+    out_all = [np.ascontiguousarray(a[..., order]) for a in rows_all]
+    out_act = [np.ascontiguousarray(a[..., keep]) for a in rows_active]
+    return out_all, out_act, len(keep), order

@@ -162,6 +162,18 @@ gs_status check_params(gs_ctx c, const gs_params* p, const char* what) {
   return GS_OK;
 }
 
+// Trainable tensors (gradients, Adam moments) describe the active pool: the
+// first t->n Gaussians of the plan's n, rows strided by t->n.
+gs_status check_trainable(gs_ctx c, const gs_params* t, const char* what) {
+  if (!t) return fail(c, GS_ERR_INVALID, "%s: null gs_params", what);
+  if (t->n < 0 || t->n > c->plan.n || t->sh_degree != c->plan.sh_degree)
+    return fail(c, GS_ERR_INVALID, "%s: n=%d (active pool) must lie in [0, %d] with sh_degree %d", what, t->n,
+                c->plan.n, c->plan.sh_degree);
+  if (t->n > 0 && (!t->mean || !t->log_scale || !t->quat || !t->opacity_logit || !t->sh))
+    return fail(c, GS_ERR_INVALID, "%s: null tensor pointer", what);
+  return GS_OK;
+}
+
 gs_status check_range(gs_ctx c, int v0, int nv, const void* ws, const char* what) {
   if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "%s: no plan (call gs_plan first)", what);
   if (v0 < 0 || nv < 1 || v0 + nv > c->plan.n_views)
@@ -365,14 +377,14 @@ gs_status gs_backward(gs_ctx c, const gs_params* params, const gs_camera* cams, 
   gs_status s = check_range(c, v0, nv, ws, "gs_backward");
   if (s != GS_OK) return s;
   if ((s = check_params(c, params, "gs_backward")) != GS_OK) return s;
-  if ((s = check_params(c, grads, "gs_backward(grads)")) != GS_OK) return s;
+  if ((s = check_trainable(c, grads, "gs_backward(grads)")) != GS_OK) return s;
   if (!cams || !img || !T || !up) return fail(c, GS_ERR_INVALID, "gs_backward: null input");
   if (mode != 0 && mode != 1) return fail(c, GS_ERR_INVALID, "gs_backward: mode=%d", mode);
   if (mode == 1 && !loss) return fail(c, GS_ERR_INVALID, "gs_backward: mode 1 needs a loss pointer");
   if (accumulate != 0 && accumulate != 1) return fail(c, GS_ERR_INVALID, "gs_backward: accumulate=%d", accumulate);
   const Plan& pl = c->plan;
   GS_HIP(c, timed(c, ST_COMPOSITE_BWD, st,
-                  [&] { return launch_composite_bwd(pl, v0, nv, ws, img, T, up, mode, loss, st); }));
+                  [&] { return launch_composite_bwd(pl, v0, nv, ws, img, T, up, mode, loss, grads->n, st); }));
   GS_HIP(c, timed(c, ST_PROJECT_BWD, st, [&] {
     return launch_project_bwd(pl, ptrs(params), cams, v0, nv, ws, *grads, accumulate, st);
   }));
@@ -386,16 +398,36 @@ gs_status gs_adam_step(gs_ctx c, const gs_params* p, const gs_params* g, const g
   if (!p || !g || !m || !v || !step || !hp) return fail(c, GS_ERR_INVALID, "gs_adam_step: null argument");
   const gs_params* all[4] = {p, g, m, v};
   for (int k = 0; k < 4; ++k) {
-    if (all[k]->n != p->n || all[k]->sh_degree != p->sh_degree)
-      return fail(c, GS_ERR_INVALID, "gs_adam_step: tensors disagree on n / sh_degree");
-    if (p->n > 0 && (!all[k]->mean || !all[k]->log_scale || !all[k]->quat || !all[k]->opacity_logit || !all[k]->sh))
+    if (all[k]->n != (k == 0 ? p->n : g->n) || all[k]->sh_degree != p->sh_degree || all[k]->n < 0)
+      return fail(c, GS_ERR_INVALID, "gs_adam_step: gradients and moments must share n (the active pool) and "
+                                     "sh_degree with the parameters");
+    if (all[k]->n > 0 && (!all[k]->mean || !all[k]->log_scale || !all[k]->quat || !all[k]->opacity_logit ||
+                          !all[k]->sh))
       return fail(c, GS_ERR_INVALID, "gs_adam_step: null tensor pointer");
   }
+  if (g->n > p->n) return fail(c, GS_ERR_INVALID, "gs_adam_step: active pool %d larger than n=%d", g->n, p->n);
   if (p->sh_degree < 0 || p->sh_degree > 3) return fail(c, GS_ERR_INVALID, "gs_adam_step: sh_degree");
   if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f && hp->eps >= 0.f))
     return fail(c, GS_ERR_INVALID, "gs_adam_step: betas must lie in [0,1) and eps >= 0");
-  if (p->n == 0) return GS_OK;
+  if (g->n == 0) return GS_OK;
   GS_HIP(c, timed(c, ST_ADAM, st, [&] { return launch_adam(*p, *g, *m, *v, step, *hp, st); }));
+  return GS_OK;
+}
+
+gs_status gs_freeze(gs_ctx c, gs_params* params, gs_params* m, gs_params* v, const uint8_t* flags, uint32_t* ids,
+                    gs_params* baseline, void* ws, int32_t* new_active, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_freeze: no plan");
+  gs_status s;
+  if ((s = check_params(c, params, "gs_freeze(params)")) != GS_OK) return s;
+  if ((s = check_trainable(c, m, "gs_freeze(m)")) != GS_OK) return s;
+  if ((s = check_trainable(c, v, "gs_freeze(v)")) != GS_OK) return s;
+  if (m->n != v->n) return fail(c, GS_ERR_INVALID, "gs_freeze: m and v describe different active pools");
+  if (baseline && (s = check_params(c, baseline, "gs_freeze(baseline)")) != GS_OK) return s;
+  if (!ws || !new_active || (m->n > 0 && !flags))
+    return fail(c, GS_ERR_INVALID, "gs_freeze: null workspace, flags or new_active");
+  GS_HIP(c, launch_freeze(c->plan, *params, *m, *v, flags, ids, baseline, ws, new_active, st));
   return GS_OK;
 }
 

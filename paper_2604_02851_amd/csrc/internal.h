@@ -39,7 +39,7 @@ struct Counters {
   uint32_t keys;          // keys needed by the last tile-list build
   uint32_t overflow;      // set when keys > capacity
   uint32_t key_cap;
-  uint32_t pad[4];
+  uint32_t pad[4];        // pad[0]: kept count of the last freeze
 };
 
 // Byte offsets of the workspace segments (computed by the host at plan time).
@@ -147,10 +147,13 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
 hipError_t launch_composite(const Plan& pl, int v0, int nv, void* ws, float* img, float* T, uint32_t* nc,
                             hipStream_t st);
 hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const float* img, const float* T,
-                                const float* up, int mode, float* loss, hipStream_t st);
+                                const float* up, int mode, float* loss, int32_t n_active, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
 hipError_t launch_adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v,
                        int32_t* step, const gs_adam_hparams& hp, hipStream_t st);
+hipError_t launch_freeze(const Plan& pl, const gs_params& p, const gs_params& m, const gs_params& v,
+                         const uint8_t* flags, uint32_t* ids, const gs_params* base, void* ws, int32_t* new_active,
+                         hipStream_t st);
 hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& base, uint32_t mask, float tau,
                         uint32_t* out, void* ws, hipStream_t st);
 hipError_t launch_epoch_bump(uint32_t* epoch, hipStream_t st);

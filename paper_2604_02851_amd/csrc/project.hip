@@ -290,6 +290,7 @@ struct ProjBwdArgs {
   const float4* g2;
   float4* g2z;   // the same slots, cleared by k_color_bwd after reading
   float* gmean; float* glsc; float* gquat; float* gopac; float* gsh;
+  int64_t n_active;   // gradients for Gaussians i < n_active, rows strided by n_active
   int accumulate;
 };
 
@@ -302,10 +303,10 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
   __shared__ float s_part[kViewWaves > 1 ? kViewWaves - 1 : 1][kOut][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t n = a.p.n;
+  const int64_t n = a.p.n, na = a.n_active;
   Gauss g;
   g.ok = false;
-  if (i < n && wave < a.nv) load_gauss(a.p, i, g, true);
+  if (i < na && wave < a.nv) load_gauss(a.p, i, g, true);
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
 #pragma unroll 1
   for (int v = a.v0 + wave; v < a.v0 + a.nv && g.ok; v += kViewWaves) {
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
     for (int k = 0; k < kOut; ++k) s_part[wave - 1][k][lane] = part[k];
   }
   __syncthreads();
-  if (wave > 0 || i >= n) return;
+  if (wave > 0 || i >= na) return;
 #pragma unroll
   for (int w = 0; w < kViewWaves - 1; ++w)
 #pragma unroll
@@ -405,9 +406,9 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
   auto put = [&](float* dst, float val) {
     if (a.accumulate) *dst += val; else *dst = val;
   };
-  for (int k = 0; k < 3; ++k) put(&a.gmean[k * n + i], part[k]);
-  for (int k = 0; k < 3; ++k) put(&a.glsc[k * n + i], part[3 + k]);
-  for (int k = 0; k < 4; ++k) put(&a.gquat[k * n + i], part[6 + k]);
+  for (int k = 0; k < 3; ++k) put(&a.gmean[k * na + i], part[k]);
+  for (int k = 0; k < 3; ++k) put(&a.glsc[k * na + i], part[3 + k]);
+  for (int k = 0; k < 4; ++k) put(&a.gquat[k * na + i], part[6 + k]);
   put(&a.gopac[i], part[10]);
 }
 
@@ -421,12 +422,12 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
   __shared__ float s_part[kViewWaves > 1 ? kViewWaves - 1 : 1][kOut][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t n = a.p.n;
+  const int64_t n = a.p.n, na = a.n_active;
   float part[kOut];
 #pragma unroll
   for (int k = 0; k < kOut; ++k) part[k] = 0.f;
   __shared__ float s_sh[kViewWaves][3 * nk][64];   // per-lane columns: no barrier needed
-  if (i < n && wave < a.nv) {
+  if (i < na && wave < a.nv) {
     float* sh_col = &s_sh[wave][0][lane];
 #pragma unroll
     for (int k = 0; k < 3 * nk; ++k) sh_col[k * 64] = a.p.sh[(int64_t)k * n + i];
@@ -472,15 +473,15 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
     for (int k = 0; k < kOut; ++k) s_part[wave - 1][k][lane] = part[k];
   }
   __syncthreads();
-  if (wave > 0 || i >= n) return;
+  if (wave > 0 || i >= na) return;
 #pragma unroll
   for (int w = 0; w < kViewWaves - 1; ++w)
 #pragma unroll
     for (int k = 0; k < kOut; ++k) part[k] += s_part[w][k][lane];
-  for (int k = 0; k < 3; ++k) a.gmean[k * n + i] += part[k];
+  for (int k = 0; k < 3; ++k) a.gmean[k * na + i] += part[k];
 #pragma unroll
   for (int k = 0; k < nk * 3; ++k) {
-    float* dst = &a.gsh[(int64_t)k * n + i];
+    float* dst = &a.gsh[(int64_t)k * na + i];
     *dst = a.accumulate ? *dst + part[3 + k] : part[3 + k];
   }
 }
@@ -529,8 +530,9 @@ hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camer
   a.gquat = grads.quat;
   a.gopac = grads.opacity_logit;
   a.gsh = grads.sh;
+  a.n_active = grads.n;
   a.accumulate = accumulate;
-  const int blocks = (p.n + 63) / 64;
+  const int blocks = (grads.n + 63) / 64;
   if (blocks == 0) return hipSuccess;
   const dim3 block(64 * kViewWaves);
   switch (p.deg) {

@@ -57,6 +57,7 @@ __device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t ntiles, i
 // 0.1% + 0.01 for FP32 rounding of both evaluations, so culling never
 // changes a result.
 constexpr float kCullQ = 9.0f * 1.001f + 0.01f;
+constexpr uint32_t kActiveBit = 0x80000000u;   // in the per-splat wavefront mask (at most 16 wavefronts)
 
 __device__ __forceinline__ float rect_qmin(float a, float r, float s, float inv, float cu, float cw, float x0,
                                            float x1, float y0, float y1) {
@@ -299,6 +300,8 @@ struct BwdArgs {
   float* loss;
   uint32_t cap;
   float bg0, bg1, bg2;
+  uint32_t n_gauss;    // Gaussians per view in the value index v * n_gauss + i
+  uint32_t n_active;   // Gaussians i < n_active are trainable; the rest are frozen
 };
 
 // Adjoint of the compositing of one pixel, walked back to front from the
@@ -385,13 +388,16 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       s_rec[j * 3 + 0] = r0;
       s_rec[j * 3 + 1] = r1;
       s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
-      s_mask[j] = splat_wave_mask<G, SW>(r0, r1, tx * TW, ty * TH);
+      // bit 31: the splat's Gaussian is trainable (frozen ones still shape T and S)
+      s_mask[j] = splat_wave_mask<G, SW>(r0, r1, tx * TW, ty * TH) | (id % a.n_gauss < a.n_active ? kActiveBit : 0u);
     }
     if (kMultiWave)
       for (uint32_t q = threadIdx.x; q < G::NWAVES * BATCH * 9; q += G::NT) s_g[q] = 0.f;
     __syncthreads();
     for (int j = (int)cnt - 1; j >= 0; --j) {
-      if (!((__builtin_amdgcn_readfirstlane(s_mask[j]) >> wave) & 1u)) continue;
+      const uint32_t mword = __builtin_amdgcn_readfirstlane(s_mask[j]);
+      if (!((mword >> wave) & 1u)) continue;
+      const bool act = (mword & kActiveBit) != 0u;
       const uint32_t pos = b_begin + (uint32_t)j;
       const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1];
       const float4 r2 = s_rec[j * 3 + 2];
@@ -412,27 +418,29 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         // predicated from here on; lanes that do not take the splat add zeros
         const float Tj = T[q] * __builtin_amdgcn_rcpf(1.f - al);
         T[q] = take ? Tj : T[q];
-        const float at = take ? al * Tj : 0.f;
-        g[6] = fmaf(at, G0[q], g[6]);
-        g[7] = fmaf(at, G1[q], g[7]);
-        g[8] = fmaf(at, G2[q], g[8]);
         const float d0 = r2.x - S0[q], d1 = r2.y - S1[q], d2 = r2.z - S2[q];
-        const float dLda = take ? Tj * (d0 * G0[q] + d1 * G1[q] + d2 * G2[q]) : 0.f;
+        if (act) {   // uniform: gradients only for trainable Gaussians
+          const float at = take ? al * Tj : 0.f;
+          g[6] = fmaf(at, G0[q], g[6]);
+          g[7] = fmaf(at, G1[q], g[7]);
+          g[8] = fmaf(at, G2[q], g[8]);
+          const float dLda = take ? Tj * (d0 * G0[q] + d1 * G1[q] + d2 * G2[q]) : 0.f;
+          const float dLda_u = clamped ? 0.f : dLda;   // the clamp cuts alpha off from opacity and power
+          const float dLdP = dLda_u * al;
+          g[5] = fmaf(dLda_u, Gs, g[5]);
+          const float ae = r1.x * sg.e;
+          g[0] = fmaf(dLdP, ae, g[0]);
+          g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * sg.dy), g[1]);
+          const float hm = -0.5f * dLdP;
+          g[2] = fmaf(hm * sg.dx, sg.dx, g[2]);
+          g[3] = fmaf(2.f * hm * sg.dx, sg.dy, g[3]);
+          g[4] = fmaf(hm * sg.dy, sg.dy, g[4]);
+        }
         S0[q] = take ? fmaf(al, d0, S0[q]) : S0[q];
         S1[q] = take ? fmaf(al, d1, S1[q]) : S1[q];
         S2[q] = take ? fmaf(al, d2, S2[q]) : S2[q];
-        const float dLda_u = clamped ? 0.f : dLda;   // the clamp cuts alpha off from opacity and power
-        const float dLdP = dLda_u * al;
-        g[5] = fmaf(dLda_u, Gs, g[5]);
-        const float ae = r1.x * sg.e;
-        g[0] = fmaf(dLdP, ae, g[0]);
-        g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * sg.dy), g[1]);
-        const float hm = -0.5f * dLdP;
-        g[2] = fmaf(hm * sg.dx, sg.dx, g[2]);
-        g[3] = fmaf(2.f * hm * sg.dx, sg.dy, g[3]);
-        g[4] = fmaf(hm * sg.dy, sg.dy, g[4]);
       }
-      if (__ballot(contrib) == 0ull) continue;
+      if (!act || __ballot(contrib) == 0ull) continue;
       const float tot8 = reduce8(g, lo8);
       const float tot9 = wave_total_lane63(g[8]);
       if (kMultiWave) {
@@ -562,8 +570,10 @@ hipError_t launch_composite(const Plan& pl, int v0, int nv, void* ws, float* img
 }
 
 hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const float* img, const float* T,
-                                const float* up, int mode, float* loss, hipStream_t st) {
+                                const float* up, int mode, float* loss, int32_t n_active, hipStream_t st) {
   BwdArgs a;
+  a.n_gauss = (uint32_t)pl.n;
+  a.n_active = (uint32_t)n_active;
   a.views = pl.d_views;
   a.tile_view = pl.d_tile_view;
   a.schedule = pl.schedule;

@@ -7,17 +7,20 @@ namespace gs {
 namespace {
 
 struct AdamSeg {
-  float* theta;
-  const float* g;
+  float* theta;      // row r of the group at theta + r * n_total
+  const float* g;    // gradient and moments: row r at + r * n_active
   float* m;
   float* v;
-  int64_t count;
+  int32_t rows;
   float lr;
 };
 
 struct AdamArgs {
   AdamSeg seg[6];
-  int64_t chunk0[7];   // first chunk of each segment (exclusive prefix), chunk0[6] = total
+  int64_t chunk0[7];   // first chunk of each group (exclusive prefix), chunk0[6] = total
+  int64_t n_total;     // parameter row stride
+  int64_t n_active;    // trainable Gaussians (a prefix): elements per row and moment row stride
+  int64_t row_chunks;  // chunks per row
   const int32_t* step;
   float beta1, beta2, eps;
 };
@@ -32,10 +35,11 @@ __device__ __forceinline__ void adam_one(float& th, float g, float& m, float& v,
   th -= step * m / (sqrtf(v) * rbc2 + eps);
 }
 
-// One workgroup per chunk of kAdamChunk elements of one segment; thread t
-// updates 4 consecutive elements (one 16-byte access per array when the
-// segment is aligned, scalar otherwise and in the segment's tail).  The bias
-// corrections are computed once per workgroup in FP64.
+// One workgroup per chunk of kAdamChunk elements of one row of one group;
+// thread t updates 4 consecutive elements (one 16-byte access per array when
+// aligned, scalar otherwise and in the row's tail).  Only the first n_active
+// Gaussians of each row are trainable; frozen ones are left untouched.  The
+// bias corrections are computed once per workgroup in FP64.
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   __shared__ float s_corr[2];
   int si = 0;
@@ -51,30 +55,36 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   __syncthreads();
   const float step = s.lr / s_corr[0], rbc2 = s_corr[1];
   const float b1 = a.beta1, b2 = a.beta2, c1 = 1.f - a.beta1, c2 = 1.f - a.beta2, eps = a.eps;
-  const int64_t k0 = ((int64_t)blockIdx.x - a.chunk0[si]) * kAdamChunk + (int64_t)threadIdx.x * kAdamVec;
-  if (k0 >= s.count) return;
-  const bool vec = k0 + kAdamVec <= s.count &&
-                   ((reinterpret_cast<uintptr_t>(s.theta) | reinterpret_cast<uintptr_t>(s.g) |
-                     reinterpret_cast<uintptr_t>(s.m) | reinterpret_cast<uintptr_t>(s.v)) & 15u) == 0;
+  const int64_t local = (int64_t)blockIdx.x - a.chunk0[si];
+  const int64_t row = local / a.row_chunks, chunk = local - row * a.row_chunks;
+  const int64_t k0 = chunk * kAdamChunk + (int64_t)threadIdx.x * kAdamVec;
+  if (k0 >= a.n_active) return;
+  float* th_p = s.theta + row * a.n_total + k0;
+  const float* g_p = s.g + row * a.n_active + k0;
+  float* m_p = s.m + row * a.n_active + k0;
+  float* v_p = s.v + row * a.n_active + k0;
+  const bool vec = k0 + kAdamVec <= a.n_active &&
+                   ((reinterpret_cast<uintptr_t>(th_p) | reinterpret_cast<uintptr_t>(g_p) |
+                     reinterpret_cast<uintptr_t>(m_p) | reinterpret_cast<uintptr_t>(v_p)) & 15u) == 0;
   if (vec) {
-    float4 th = *reinterpret_cast<const float4*>(s.theta + k0);
-    const float4 g = *reinterpret_cast<const float4*>(s.g + k0);
-    float4 m = *reinterpret_cast<const float4*>(s.m + k0);
-    float4 v = *reinterpret_cast<const float4*>(s.v + k0);
+    float4 th = *reinterpret_cast<const float4*>(th_p);
+    const float4 g = *reinterpret_cast<const float4*>(g_p);
+    float4 m = *reinterpret_cast<const float4*>(m_p);
+    float4 v = *reinterpret_cast<const float4*>(v_p);
     adam_one(th.x, g.x, m.x, v.x, b1, b2, c1, c2, step, rbc2, eps);
     adam_one(th.y, g.y, m.y, v.y, b1, b2, c1, c2, step, rbc2, eps);
     adam_one(th.z, g.z, m.z, v.z, b1, b2, c1, c2, step, rbc2, eps);
     adam_one(th.w, g.w, m.w, v.w, b1, b2, c1, c2, step, rbc2, eps);
-    *reinterpret_cast<float4*>(s.m + k0) = m;
-    *reinterpret_cast<float4*>(s.v + k0) = v;
-    *reinterpret_cast<float4*>(s.theta + k0) = th;
+    *reinterpret_cast<float4*>(m_p) = m;
+    *reinterpret_cast<float4*>(v_p) = v;
+    *reinterpret_cast<float4*>(th_p) = th;
   } else {
-    for (int64_t k = k0; k < k0 + kAdamVec && k < s.count; ++k) {
-      float th = s.theta[k], m = s.m[k], v = s.v[k];
-      adam_one(th, s.g[k], m, v, b1, b2, c1, c2, step, rbc2, eps);
-      s.m[k] = m;
-      s.v[k] = v;
-      s.theta[k] = th;
+    for (int c = 0; c < kAdamVec && k0 + c < a.n_active; ++c) {
+      float th = th_p[c], m = m_p[c], v = v_p[c];
+      adam_one(th, g_p[c], m, v, b1, b2, c1, c2, step, rbc2, eps);
+      m_p[c] = m;
+      v_p[c] = v;
+      th_p[c] = th;
     }
   }
 }
@@ -182,31 +192,126 @@ __global__ __launch_bounds__(256) void k_delta_write(DeltaArgs a) {
   }
 }
 
+// ---- freezing: stable partition of the active pool ----------------------------
+// Active Gaussians flagged for freezing move behind the ones that stay
+// active (both in their old order), ahead of the Gaussians frozen before;
+// the moments of the Gaussians that stay active are compacted to the new
+// active count.  Rows are moved one at a time through a scratch copy.
+__global__ void k_fill_i32_zero(int32_t* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+__global__ void k_keep_flags(const uint8_t* flags, int64_t n_active, uint32_t* keep) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_active) keep[i] = flags[i] ? 0u : 1u;
+}
+
+__global__ void k_freeze_dst(const uint32_t* pos, const uint32_t* kept, const uint8_t* flags, int64_t n_active,
+                             uint32_t* dst, int32_t* new_active) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nk = *kept;
+  if (i == 0) *new_active = (int32_t)nk;
+  if (i < n_active) dst[i] = flags[i] ? nk + (uint32_t)i - pos[i] : pos[i];
+}
+
+__global__ void k_copy_words(const uint32_t* src, uint32_t* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// row[dst[i]] = scratch[i] for i < n_active (a permutation of the prefix)
+__global__ void k_scatter_words(const uint32_t* scratch, const uint32_t* dst, int64_t n_active, uint32_t* row) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_active) row[dst[i]] = scratch[i];
+}
+
+// moment row r, compacted: (base + r * kept)[pos[i]] = scratch[i] for kept i
+__global__ void k_compact_words(const uint32_t* scratch, const uint32_t* pos, const uint8_t* flags, int64_t n_active,
+                                const uint32_t* kept, uint32_t* base, int64_t r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_active && !flags[i]) base[r * (int64_t)*kept + pos[i]] = scratch[i];
+}
+
 }  // namespace
 
 hipError_t launch_adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v, int32_t* step,
                        const gs_adam_hparams& hp, hipStream_t st) {
-  const int64_t n = p.n;
-  const int64_t nk = (int64_t)(p.sh_degree + 1) * (p.sh_degree + 1);
+  const int64_t n = p.n, na = g.n;
+  const int nk = (p.sh_degree + 1) * (p.sh_degree + 1);
   AdamArgs a;
-  auto setseg = [&](int s, float* th, float* gr, float* mm, float* vv, int64_t cnt) {
-    a.seg[s] = AdamSeg{th, gr, mm, vv, cnt, hp.lr[s]};
+  auto setseg = [&](int s, float* th, const float* gr, float* mm, float* vv, int rows, int64_t row0) {
+    a.seg[s] = AdamSeg{th + row0 * n, gr + row0 * na, mm + row0 * na, vv + row0 * na, rows, hp.lr[s]};
   };
-  setseg(0, p.mean, g.mean, m.mean, v.mean, 3 * n);
-  setseg(1, p.log_scale, g.log_scale, m.log_scale, v.log_scale, 3 * n);
-  setseg(2, p.quat, g.quat, m.quat, v.quat, 4 * n);
-  setseg(3, p.opacity_logit, g.opacity_logit, m.opacity_logit, v.opacity_logit, n);
-  setseg(4, p.sh, g.sh, m.sh, v.sh, 3 * n);
-  setseg(5, p.sh + 3 * n, g.sh + 3 * n, m.sh + 3 * n, v.sh + 3 * n, (nk - 1) * 3 * n);
+  setseg(0, p.mean, g.mean, m.mean, v.mean, 3, 0);
+  setseg(1, p.log_scale, g.log_scale, m.log_scale, v.log_scale, 3, 0);
+  setseg(2, p.quat, g.quat, m.quat, v.quat, 4, 0);
+  setseg(3, p.opacity_logit, g.opacity_logit, m.opacity_logit, v.opacity_logit, 1, 0);
+  setseg(4, p.sh, g.sh, m.sh, v.sh, 3, 0);
+  setseg(5, p.sh, g.sh, m.sh, v.sh, 3 * (nk - 1), 3);
+  a.n_total = n;
+  a.n_active = na;
+  a.row_chunks = (na + kAdamChunk - 1) / kAdamChunk;
   a.step = step;
   a.beta1 = hp.beta1;
   a.beta2 = hp.beta2;
   a.eps = hp.eps;
   a.chunk0[0] = 0;
-  for (int q = 0; q < 6; ++q) a.chunk0[q + 1] = a.chunk0[q] + (a.seg[q].count + kAdamChunk - 1) / kAdamChunk;
+  for (int q = 0; q < 6; ++q) a.chunk0[q + 1] = a.chunk0[q] + (int64_t)a.seg[q].rows * a.row_chunks;
   if (a.chunk0[6] > 0x7fffffffll) return hipErrorInvalidValue;
   if (a.chunk0[6] > 0) hipLaunchKernelGGL(k_adam, dim3((unsigned)a.chunk0[6]), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, st, step);
+  return hipGetLastError();
+}
+
+static inline unsigned blocks256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_freeze(const Plan& pl, const gs_params& p, const gs_params& m, const gs_params& v,
+                         const uint8_t* flags, uint32_t* ids, const gs_params* base, void* ws, int32_t* new_active,
+                         hipStream_t st) {
+  const int64_t n = p.n, na = m.n;
+  if (na == 0) {
+    hipLaunchKernelGGL(k_fill_i32_zero, dim3(1), dim3(64), 0, st, new_active);
+    return hipGetLastError();
+  }
+  uint32_t* keep = seg<uint32_t>(ws, pl.ws.depth);
+  uint32_t* pos = seg<uint32_t>(ws, pl.ws.koff);
+  uint32_t* dst = seg<uint32_t>(ws, pl.ws.vkey_a);
+  uint32_t* scratch = seg<uint32_t>(ws, pl.ws.vkey_b);
+  uint32_t* kept = &seg<Counters>(ws, pl.ws.counters)->pad[0];
+  hipLaunchKernelGGL(k_keep_flags, dim3(blocks256(na)), dim3(256), 0, st, flags, na, keep);
+  hipError_t e = launch_scan(keep, pos, na, nullptr, seg<uint32_t>(ws, pl.ws.partial), pl.ws.partial_len, kept, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_freeze_dst, dim3(blocks256(na)), dim3(256), 0, st, pos, kept, flags, na, dst, new_active);
+  const int nk = (p.sh_degree + 1) * (p.sh_degree + 1);
+  auto permute_rows = [&](const gs_params& t) {
+    float* rows_of[5] = {t.mean, t.log_scale, t.quat, t.opacity_logit, t.sh};
+    const int count[5] = {3, 3, 4, 1, 3 * nk};
+    for (int g = 0; g < 5; ++g)
+      for (int r = 0; r < count[g]; ++r) {
+        uint32_t* row = reinterpret_cast<uint32_t*>(rows_of[g] + (int64_t)r * n);
+        hipLaunchKernelGGL(k_copy_words, dim3(blocks256(na)), dim3(256), 0, st, row, scratch, na);
+        hipLaunchKernelGGL(k_scatter_words, dim3(blocks256(na)), dim3(256), 0, st, scratch, dst, na, row);
+      }
+  };
+  auto compact_rows = [&](const gs_params& t) {
+    float* rows_of[5] = {t.mean, t.log_scale, t.quat, t.opacity_logit, t.sh};
+    const int count[5] = {3, 3, 4, 1, 3 * nk};
+    for (int g = 0; g < 5; ++g)
+      for (int r = 0; r < count[g]; ++r) {
+        uint32_t* base = reinterpret_cast<uint32_t*>(rows_of[g]);
+        hipLaunchKernelGGL(k_copy_words, dim3(blocks256(na)), dim3(256), 0, st, base + (int64_t)r * na, scratch, na);
+        hipLaunchKernelGGL(k_compact_words, dim3(blocks256(na)), dim3(256), 0, st, scratch, pos, flags, na, kept,
+                           base, (int64_t)r);
+      }
+  };
+  permute_rows(p);
+  if (base) permute_rows(*base);
+  if (ids) {
+    hipLaunchKernelGGL(k_copy_words, dim3(blocks256(na)), dim3(256), 0, st, ids, scratch, na);
+    hipLaunchKernelGGL(k_scatter_words, dim3(blocks256(na)), dim3(256), 0, st, scratch, dst, na, ids);
+  }
+  compact_rows(m);
+  compact_rows(v);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS
 
 EXPORTED = ("gs_create", "gs_destroy", "gs_last_error", "gs_plan", "gs_frame_layout", "gs_workspace_init", "gs_project",
             "gs_build_tile_lists", "gs_composite", "gs_backward", "gs_adam_step", "gs_delta_extract",
-            "gs_delta_reset_baseline", "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
+            "gs_delta_reset_baseline", "gs_freeze", "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
             "gs_step_launch", "gs_profile_enable", "gs_profile_read", "gs_profile_reset")
 STAGES = ("project", "tile_lists", "composite", "composite_bwd", "project_bwd", "adam", "delta")
 SEG = {"depth": 0, "count": 1, "rect": 2, "record": 3, "grad2d": 4, "sorted_values": 5, "ranges": 6, "last": 7}
@@ -93,6 +93,8 @@ def lib() -> ctypes.CDLL:
         L.gs_delta_extract.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), c_uint32, c_float, c_void_p,
                                        c_int64, c_void_p, c_void_p]
         L.gs_delta_reset_baseline.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), c_void_p, c_void_p]
+        L.gs_freeze.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), POINTER(GsParams), c_void_p, c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_void_p]
         L.gs_read_counters.argtypes = [ctx, c_void_p, c_void_p, POINTER(GsCounters)]
         L.gs_workspace_segment.argtypes = [ctx, c_int32, c_int32, c_int32, POINTER(c_size_t), POINTER(c_size_t)]
         L.gs_profile_enable.argtypes = [ctx, c_int32]
@@ -148,6 +150,25 @@ class DeviceParams:
 
     def clone(self):
         return DeviceParams(*[t.clone() for t in self.tensors()], self.sh_degree)
+
+    @classmethod
+    def zeros(cls, n: int, sh_degree: int, device="cuda"):
+        nk = (sh_degree + 1) ** 2
+        f = dict(dtype=torch.float32, device=device)
+        return cls(torch.zeros(3, n, **f), torch.zeros(3, n, **f), torch.zeros(4, n, **f), torch.zeros(n, **f),
+                   torch.zeros(3 * nk, n, **f), sh_degree)
+
+    def narrowed(self, n: int) -> "DeviceParams":
+        """The same storage described with n Gaussians per row (rows packed at
+        stride n), as left by an in-place compaction to n."""
+        assert 0 <= n <= self.n
+        out = []
+        for t in self.tensors():
+            rows = 1 if t.dim() == 1 else t.shape[0]
+            flat = t.view(-1) if t.is_contiguous() else t.reshape(-1)
+            v = flat[:rows * n]
+            out.append(v if t.dim() == 1 else v.view(rows, n))
+        return DeviceParams(*out, self.sh_degree)
 
     def struct(self) -> GsParams:
         return GsParams(*[ptr(t) for t in self.tensors()], self.n, self.sh_degree)
@@ -237,6 +258,13 @@ class Context:
         c, b = cur.struct(), baseline.struct()
         self._chk(self.L.gs_delta_reset_baseline(self.h, ctypes.byref(c), ctypes.byref(b), ptr(dev_epoch),
                                                  stream_handle(stream)))
+
+    def freeze(self, params, m, v, flags, ws, new_active, ids=None, baseline=None, stream=None):
+        p, mm, vv = params.struct(), m.struct(), v.struct()
+        b = baseline.struct() if baseline is not None else None
+        self._chk(self.L.gs_freeze(self.h, ctypes.byref(p), ctypes.byref(mm), ctypes.byref(vv), ptr(flags), ptr(ids),
+                                   ctypes.byref(b) if b is not None else None, ptr(ws), ptr(new_active),
+                                   stream_handle(stream)))
 
     def read_counters(self, ws, stream=None) -> GsCounters:
         out = GsCounters()

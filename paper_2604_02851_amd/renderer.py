@@ -128,14 +128,18 @@ class Optimizer:
     backward, Adam), batched or plain, eager or replayed from a HIP graph."""
 
     def __init__(self, renderer: Renderer, params: DeviceParams, targets: torch.Tensor, lr=DEFAULT_LR,
-                 betas=(0.9, 0.999), eps=1e-15, stream: torch.cuda.Stream | None = None):
+                 betas=(0.9, 0.999), eps=1e-15, stream: torch.cuda.Stream | None = None, n_active: int | None = None):
+        """n_active: the first n_active Gaussians form the active (trainable)
+        pool, the rest the frozen pool (rendered, not optimised)."""
         self.r = renderer
         self.params = params
         self.targets = targets.contiguous()
-        self.grads = DeviceParams.zeros_like(params)
-        self.m = DeviceParams.zeros_like(params)
-        self.v = DeviceParams.zeros_like(params)
+        na = params.n if n_active is None else int(n_active)
         dev = renderer.device
+        self.grads = DeviceParams.zeros(na, params.sh_degree, dev)
+        self.m = DeviceParams.zeros(na, params.sh_degree, dev)
+        self.v = DeviceParams.zeros(na, params.sh_degree, dev)
+        self.ids = None
         self.step_count = torch.zeros(1, dtype=torch.int32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.lr, self.betas, self.eps = tuple(lr), tuple(betas), eps
@@ -177,6 +181,26 @@ class Optimizer:
 
     def invalidate(self):
         self._args_cache.clear()
+
+    @property
+    def n_active(self) -> int:
+        return self.grads.n
+
+    def freeze(self, flags: torch.Tensor) -> int:
+        """Moves the active Gaussians with flags[i] != 0 (uint8, one per active
+        Gaussian) into the frozen pool; parameters, delta baseline and ids are
+        permuted in place, moments compacted.  Synchronises; returns the new
+        active count.  A captured graph must be captured again afterwards."""
+        assert flags.dtype == torch.uint8 and flags.numel() == self.n_active and flags.is_contiguous()
+        out = torch.zeros(1, dtype=torch.int32, device=self.r.device)
+        base = self.delta["baseline"] if self.delta is not None else None
+        self.r.ctx.freeze(self.params, self.m, self.v, flags, self.r.ws, out, ids=self.ids, baseline=base,
+                          stream=self.stream)
+        (self.stream or torch.cuda.current_stream()).synchronize()
+        na = int(out.item())
+        self.grads, self.m, self.v = (x.narrowed(na) for x in (self.grads, self.m, self.v))
+        self._args_cache.clear()
+        return na
 
     def step(self, plain: bool = False):
         self.r.ctx.step(self.args(plain), self.stream)
