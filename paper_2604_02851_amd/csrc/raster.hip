@@ -415,30 +415,31 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         bool clamped;
         const bool take = splat_alpha(sg.P, r1.w, Gs, al, clamped) && cand;
         contrib = contrib || take;
-        // predicated from here on; lanes that do not take the splat add zeros
+        // predicated from here on; lanes that do not take the splat add zeros.
+        // A frozen splat runs the same arithmetic (its sums are dropped below):
+        // a second, gradient-free copy of this loop costs more registers
+        // than the work it would save.
         const float Tj = T[q] * __builtin_amdgcn_rcpf(1.f - al);
         T[q] = take ? Tj : T[q];
+        const float at = take ? al * Tj : 0.f;
+        g[6] = fmaf(at, G0[q], g[6]);
+        g[7] = fmaf(at, G1[q], g[7]);
+        g[8] = fmaf(at, G2[q], g[8]);
         const float d0 = r2.x - S0[q], d1 = r2.y - S1[q], d2 = r2.z - S2[q];
-        if (act) {   // uniform: gradients only for trainable Gaussians
-          const float at = take ? al * Tj : 0.f;
-          g[6] = fmaf(at, G0[q], g[6]);
-          g[7] = fmaf(at, G1[q], g[7]);
-          g[8] = fmaf(at, G2[q], g[8]);
-          const float dLda = take ? Tj * (d0 * G0[q] + d1 * G1[q] + d2 * G2[q]) : 0.f;
-          const float dLda_u = clamped ? 0.f : dLda;   // the clamp cuts alpha off from opacity and power
-          const float dLdP = dLda_u * al;
-          g[5] = fmaf(dLda_u, Gs, g[5]);
-          const float ae = r1.x * sg.e;
-          g[0] = fmaf(dLdP, ae, g[0]);
-          g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * sg.dy), g[1]);
-          const float hm = -0.5f * dLdP;
-          g[2] = fmaf(hm * sg.dx, sg.dx, g[2]);
-          g[3] = fmaf(2.f * hm * sg.dx, sg.dy, g[3]);
-          g[4] = fmaf(hm * sg.dy, sg.dy, g[4]);
-        }
+        const float dLda = take ? Tj * (d0 * G0[q] + d1 * G1[q] + d2 * G2[q]) : 0.f;
         S0[q] = take ? fmaf(al, d0, S0[q]) : S0[q];
         S1[q] = take ? fmaf(al, d1, S1[q]) : S1[q];
         S2[q] = take ? fmaf(al, d2, S2[q]) : S2[q];
+        const float dLda_u = clamped ? 0.f : dLda;   // the clamp cuts alpha off from opacity and power
+        const float dLdP = dLda_u * al;
+        g[5] = fmaf(dLda_u, Gs, g[5]);
+        const float ae = r1.x * sg.e;
+        g[0] = fmaf(dLdP, ae, g[0]);
+        g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * sg.dy), g[1]);
+        const float hm = -0.5f * dLdP;
+        g[2] = fmaf(hm * sg.dx, sg.dx, g[2]);
+        g[3] = fmaf(2.f * hm * sg.dx, sg.dy, g[3]);
+        g[4] = fmaf(hm * sg.dy, sg.dy, g[4]);
       }
       if (!act || __ballot(contrib) == 0ull) continue;
       const float tot8 = reduce8(g, lo8);
