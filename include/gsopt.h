@@ -202,6 +202,41 @@ gs_status gs_adam_step(gs_ctx ctx, const gs_params* params, const gs_params* gra
                        const gs_params* m, const gs_params* v, int32_t* dev_step,
                        const gs_adam_hparams* hp, hipStream_t stream);
 
+/* ---- preculling by grid cells (Sec. 3.3) ---------------------------------
+ * A regular world grid of dims[0] x dims[1] x dims[2] cubic cells of edge
+ * cell_size starting at origin; cell index = cx + dims[0] (cy + dims[1] cz).
+ * Gaussians whose mean lies outside the grid belong to an extra cell,
+ * index dims[0] dims[1] dims[2], which is never culled. */
+typedef struct {
+  float origin[3];
+  float cell_size;
+  int32_t dims[3];
+  int32_t reserved;
+} gs_grid;
+
+/* Assigns every Gaussian (params->n) to its cell: cell_of[n] (device uint32)
+ * and cell_sigma[n_cells + 1] (device uint32 holding FP32 bits: the largest
+ * exp(log-scale) among the cell's Gaussians), both caller-owned. */
+gs_status gs_assign_cells(gs_ctx ctx, const gs_params* params, const gs_grid* grid, uint32_t* cell_of,
+                          uint32_t* cell_sigma, hipStream_t stream);
+
+/* Per-view cell visibility for views [view_begin, view_begin + view_count):
+ * mask[(v - view_begin) * (n_cells + 1) + c] = 1 unless no Gaussian of cell c
+ * can be visible in view v (conservative: derived from the projection's own
+ * visibility rule with the cell's largest scale, so culling never changes a
+ * result).  Engines with their own visibility (a depth test) may write the
+ * mask themselves instead. */
+gs_status gs_visible_cells(gs_ctx ctx, const gs_grid* grid, const gs_camera* dev_cams, int32_t view_begin,
+                           int32_t view_count, const uint32_t* cell_sigma, uint8_t* mask, hipStream_t stream);
+
+/* Turns preculling on for later gs_project calls (and steps): Gaussian i is
+ * skipped for view v when mask[v * (n_cells + 1) + cell_of[i]] == 0 (rows
+ * for every view of the plan).  NULL pointers turn it off.  The pointers are
+ * recorded, not their contents: the caller may rewrite the mask between
+ * steps; changing the pointers invalidates a captured step graph, and a new
+ * gs_plan turns preculling off. */
+gs_status gs_set_precull(gs_ctx ctx, const uint32_t* cell_of, const uint8_t* mask, int32_t n_cells);
+
 /* Moves active Gaussians into the frozen pool (Sec. 3.3: as regions become
  * stable their Gaussians leave the trainable set but stay renderable).
  * flags[i] != 0 (device bytes, i < m->n) marks active Gaussian i for

@@ -260,3 +260,17 @@ def freeze_partition(rows_all, rows_active, flags, n_active):
     out_all = [np.ascontiguousarray(a[..., order]) for a in rows_all]
     out_act = [np.ascontiguousarray(a[..., keep]) for a in rows_active]
     return out_all, out_act, len(keep), order
+
+
+def cell_of(mean, origin, cell_size, dims):
+    """Preculling grid (Sec. 3.3): the cell of each mean, evaluated in FP32 as
+    t = (p - origin) / cell_size per axis, cell = cx + dims0 (cy + dims1 cz);
+    means outside the grid (or NaN) get the extra index dims0 dims1 dims2."""
+    m = np.asarray(mean, np.float32)
+    o = np.asarray(origin, np.float32).reshape(3, 1)
+    t = (m - o) / np.float32(cell_size)
+    d = np.asarray(dims, np.int64).reshape(3, 1)
+    inside = np.all((t >= 0) & (t < d.astype(np.float32)), axis=0)
+    idx = np.floor(np.where(inside, t, 0)).astype(np.int64)
+    c = idx[0] + d[0, 0] * (idx[1] + d[1, 0] * idx[2])
+    return np.where(inside, c, int(np.prod(dims))).astype(np.int64)

@@ -414,6 +414,59 @@ gs_status gs_adam_step(gs_ctx c, const gs_params* p, const gs_params* g, const g
   return GS_OK;
 }
 
+static gs_status check_grid(gs_ctx c, const gs_grid* g, const char* what) {
+  if (!g) return fail(c, GS_ERR_INVALID, "%s: null grid", what);
+  const int64_t nc = (int64_t)g->dims[0] * g->dims[1] * g->dims[2];
+  if (g->dims[0] < 1 || g->dims[1] < 1 || g->dims[2] < 1 || nc >= (1ll << 31) || !(g->cell_size > 0.f) ||
+      !std::isfinite(g->cell_size) || !std::isfinite(g->origin[0]) || !std::isfinite(g->origin[1]) ||
+      !std::isfinite(g->origin[2]))
+    return fail(c, GS_ERR_INVALID, "%s: grid needs dims >= 1 (fewer than 2^31 cells), a finite origin and a "
+                                   "positive cell size", what);
+  return GS_OK;
+}
+
+gs_status gs_assign_cells(gs_ctx c, const gs_params* params, const gs_grid* grid, uint32_t* cell_of,
+                          uint32_t* cell_sigma, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  gs_status s;
+  if ((s = check_grid(c, grid, "gs_assign_cells")) != GS_OK) return s;
+  if (!params || params->n < 0 || (params->n > 0 && (!params->mean || !params->log_scale)))
+    return fail(c, GS_ERR_INVALID, "gs_assign_cells: bad params");
+  if ((params->n > 0 && !cell_of) || !cell_sigma) return fail(c, GS_ERR_INVALID, "gs_assign_cells: null output");
+  GS_HIP(c, launch_assign_cells(ptrs(params), *grid, cell_of, cell_sigma, st));
+  return GS_OK;
+}
+
+gs_status gs_visible_cells(gs_ctx c, const gs_grid* grid, const gs_camera* cams, int32_t v0, int32_t nv,
+                           const uint32_t* cell_sigma, uint8_t* mask, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  gs_status s;
+  if ((s = check_grid(c, grid, "gs_visible_cells")) != GS_OK) return s;
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_visible_cells: no plan");
+  if (v0 < 0 || nv < 1 || v0 + nv > c->plan.n_views)
+    return fail(c, GS_ERR_INVALID, "gs_visible_cells: view range [%d, %d) outside [0, %d)", v0, v0 + nv,
+                c->plan.n_views);
+  if (!cams || !cell_sigma || !mask) return fail(c, GS_ERR_INVALID, "gs_visible_cells: null pointer");
+  GS_HIP(c, launch_visible_cells(*grid, cams, v0, nv, cell_sigma, mask, st));
+  return GS_OK;
+}
+
+gs_status gs_set_precull(gs_ctx c, const uint32_t* cell_of, const uint8_t* mask, int32_t n_cells) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_set_precull: no plan");
+  if ((cell_of == nullptr) != (mask == nullptr))
+    return fail(c, GS_ERR_INVALID, "gs_set_precull: give both cell_of and mask, or neither");
+  if (mask && n_cells < 1) return fail(c, GS_ERR_INVALID, "gs_set_precull: n_cells=%d", n_cells);
+  c->plan.cell_of = cell_of;
+  c->plan.cell_mask = mask;
+  c->plan.cell_row = mask ? n_cells + 1 : 0;
+  ++c->plan_gen;   // a captured step used the previous setting
+  return GS_OK;
+}
+
 gs_status gs_freeze(gs_ctx c, gs_params* params, gs_params* m, gs_params* v, const uint8_t* flags, uint32_t* ids,
                     gs_params* baseline, void* ws, int32_t* new_active, hipStream_t st) {
   if (!c) return GS_ERR_INVALID;

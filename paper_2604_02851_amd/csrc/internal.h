@@ -79,6 +79,10 @@ struct Plan {
   int64_t cap = 0;
   ViewInfo views[kMaxViews];
   WsLayout ws;
+  // preculling (caller-owned device arrays; null = off)
+  const uint32_t* cell_of = nullptr;
+  const uint8_t* cell_mask = nullptr;
+  int32_t cell_row = 0;   // n_cells + 1
   // library-owned device copies
   ViewInfo* d_views = nullptr;
   int32_t* d_tile_view = nullptr;
@@ -151,6 +155,10 @@ hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
 hipError_t launch_adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v,
                        int32_t* step, const gs_adam_hparams& hp, hipStream_t st);
+hipError_t launch_assign_cells(const ParamPtrs& p, const gs_grid& g, uint32_t* cell_of, uint32_t* cell_sigma,
+                               hipStream_t st);
+hipError_t launch_visible_cells(const gs_grid& g, const gs_camera* cams, int v0, int nv, const uint32_t* cell_sigma,
+                                uint8_t* mask, hipStream_t st);
 hipError_t launch_freeze(const Plan& pl, const gs_params& p, const gs_params& m, const gs_params& v,
                          const uint8_t* flags, uint32_t* ids, const gs_params* base, void* ws, int32_t* new_active,
                          hipStream_t st);

@@ -209,6 +209,9 @@ struct ProjArgs {
   uint32_t* count;
   ushort4* rect;
   float4* rec;
+  const uint32_t* cell_of;   // preculling (null = off)
+  const uint8_t* cell_mask;
+  int32_t cell_row;
 };
 
 constexpr int kViewWaves = 1;
@@ -233,12 +236,13 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
   }
   Gauss g;
   load_gauss(a.p, i, g, sh_ok);
+  const uint32_t cell = a.cell_mask ? a.cell_of[i] : 0u;
 #pragma unroll 1
   for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) {
     const int64_t o = (int64_t)v * n + i;
     const gs_camera cam = a.cams[v];
     uint32_t cnt = 0;
-    if (g.ok) {
+    if (g.ok && (!a.cell_mask || a.cell_mask[(int64_t)v * a.cell_row + cell])) {
       const float z32 = depth_key(cam.R[6], cam.R[7], cam.R[8], cam.t[2], g.mu[0], g.mu[1], g.mu[2]);
       ViewGeom vg;
       if (z32 >= kNear && view_geom(g, cam, vg)) {
@@ -502,6 +506,9 @@ hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* c
   a.count = seg<uint32_t>(ws, pl.ws.count);
   a.rect = seg<ushort4>(ws, pl.ws.rect);
   a.rec = seg<float4>(ws, pl.ws.rec);
+  a.cell_of = pl.cell_of;
+  a.cell_mask = pl.cell_mask;
+  a.cell_row = pl.cell_row;
   const int blocks = (p.n + 63) / 64;
   if (blocks == 0) return hipSuccess;
   const dim3 block(64 * kViewWaves);

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS
 
 EXPORTED = ("gs_create", "gs_destroy", "gs_last_error", "gs_plan", "gs_frame_layout", "gs_workspace_init", "gs_project",
             "gs_build_tile_lists", "gs_composite", "gs_backward", "gs_adam_step", "gs_delta_extract",
-            "gs_delta_reset_baseline", "gs_freeze", "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
+            "gs_delta_reset_baseline", "gs_freeze", "gs_assign_cells", "gs_visible_cells", "gs_set_precull",
+            "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
             "gs_step_launch", "gs_profile_enable", "gs_profile_read", "gs_profile_reset")
 STAGES = ("project", "tile_lists", "composite", "composite_bwd", "project_bwd", "adam", "delta")
 SEG = {"depth": 0, "count": 1, "rect": 2, "record": 3, "grad2d": 4, "sorted_values": 5, "ranges": 6, "last": 7}
@@ -46,6 +47,10 @@ class GsRenderOpts(ctypes.Structure):
 
 class GsAdamHparams(ctypes.Structure):
     _fields_ = [("lr", c_float * 6), ("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
+
+
+class GsGrid(ctypes.Structure):
+    _fields_ = [("origin", c_float * 3), ("cell_size", c_float), ("dims", c_int32 * 3), ("reserved", c_int32)]
 
 
 class GsCounters(ctypes.Structure):
@@ -93,6 +98,9 @@ def lib() -> ctypes.CDLL:
         L.gs_delta_extract.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), c_uint32, c_float, c_void_p,
                                        c_int64, c_void_p, c_void_p]
         L.gs_delta_reset_baseline.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), c_void_p, c_void_p]
+        L.gs_assign_cells.argtypes = [ctx, POINTER(GsParams), POINTER(GsGrid), c_void_p, c_void_p, c_void_p]
+        L.gs_visible_cells.argtypes = [ctx, POINTER(GsGrid), c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]
+        L.gs_set_precull.argtypes = [ctx, c_void_p, c_void_p, c_int32]
         L.gs_freeze.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), POINTER(GsParams), c_void_p, c_void_p,
                                 c_void_p, c_void_p, c_void_p, c_void_p]
         L.gs_read_counters.argtypes = [ctx, c_void_p, c_void_p, POINTER(GsCounters)]
@@ -258,6 +266,18 @@ class Context:
         c, b = cur.struct(), baseline.struct()
         self._chk(self.L.gs_delta_reset_baseline(self.h, ctypes.byref(c), ctypes.byref(b), ptr(dev_epoch),
                                                  stream_handle(stream)))
+
+    def assign_cells(self, params, grid: "GsGrid", cell_of, cell_sigma, stream=None):
+        p = params.struct()
+        self._chk(self.L.gs_assign_cells(self.h, ctypes.byref(p), ctypes.byref(grid), ptr(cell_of), ptr(cell_sigma),
+                                         stream_handle(stream)))
+
+    def visible_cells(self, grid: "GsGrid", dev_cams, v0, nv, cell_sigma, mask, stream=None):
+        self._chk(self.L.gs_visible_cells(self.h, ctypes.byref(grid), ptr(dev_cams), v0, nv, ptr(cell_sigma),
+                                          ptr(mask), stream_handle(stream)))
+
+    def set_precull(self, cell_of, mask, n_cells: int):
+        self._chk(self.L.gs_set_precull(self.h, ptr(cell_of), ptr(mask), int(n_cells)))
 
     def freeze(self, params, m, v, flags, ws, new_active, ids=None, baseline=None, stream=None):
         p, mm, vv = params.struct(), m.struct(), v.struct()

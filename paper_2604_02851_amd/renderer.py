@@ -49,6 +49,33 @@ class Renderer:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.ctx.workspace_init(self.ws)
         self.pix_off, self.tile_off = self.ctx.frame_layout()
+        if getattr(self, "precull", None) is not None:   # a new plan turns preculling off: restore it
+            self.ctx.set_precull(*self.precull)
+
+    def enable_precull(self, params: DeviceParams, origin, cell_size: float, dims, update_mask: bool = True):
+        """Preculling by grid cells (Sec. 3.3): assigns the Gaussians to the
+        cells of the grid and lets the projection skip, per view, the cells
+        that view cannot see (conservative: results do not change).  Returns
+        (cell_of, mask); call update_precull() after the cameras or the model
+        move."""
+        g = N.GsGrid((N.c_float * 3)(*origin), float(cell_size), (N.c_int32 * 3)(*dims), 0)
+        n_cells = int(dims[0]) * int(dims[1]) * int(dims[2])
+        self.grid, self.n_cells = g, n_cells
+        self.cell_of = torch.zeros(max(params.n, 1), dtype=torch.int32, device=self.device)
+        self.cell_sigma = torch.zeros(n_cells + 1, dtype=torch.int32, device=self.device)
+        self.cell_mask = torch.ones(self.n_views * (n_cells + 1), dtype=torch.uint8, device=self.device)
+        self.update_precull(params)
+        self.precull = (self.cell_of, self.cell_mask, n_cells)
+        self.ctx.set_precull(*self.precull)
+        return self.cell_of, self.cell_mask
+
+    def update_precull(self, params: DeviceParams):
+        self.ctx.assign_cells(params, self.grid, self.cell_of, self.cell_sigma)
+        self.ctx.visible_cells(self.grid, self.dev_cams, 0, self.n_views, self.cell_sigma, self.cell_mask)
+
+    def disable_precull(self):
+        self.precull = None
+        self.ctx.set_precull(None, None, 0)
 
     def replan(self, key_capacity: int):
         self.key_capacity = int(key_capacity)

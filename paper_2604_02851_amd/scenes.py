@@ -221,6 +221,24 @@ def small_workload(seed: int, n: int, extent: float, sh_degree: int, sizes, dist
 # Applied on the host in float32 to the model and the target copy alike.
 # ---------------------------------------------------------------------------
 
+def rig_workload(seed: int, n: int, half: float = 20.0, height: float = 2.0, views: int = 4,
+                 size=(320, 180), sh_degree: int = 3) -> Workload:
+    """A wide, flat scene (means uniform in [-half, half] x [-height, height] x
+    [-half, half]) seen from a rig of cameras at the origin looking outward at
+    evenly spaced headings, as around a player in a large world: each view
+    sees only part of the model (the preculling workload)."""
+    rng = np.random.default_rng(np.random.SeedSequence(260402851 + 1000 + seed))
+    scene = draw_scene(rng, n, 1.0, sh_degree)
+    scene.mean[0] *= np.float32(half)
+    scene.mean[1] *= np.float32(height)
+    scene.mean[2] *= np.float32(half)
+    w, h = size
+    recs = [look_at((0.0, 0.0, 0.0), w, h, 60.0,
+                    target=(math.cos(2 * math.pi * k / views), 0.0, math.sin(2 * math.pi * k / views)))
+            for k in range(views)]
+    return Workload(f"rig{seed}", scene, cams_array(recs), 16, {"perturbed": perturb(rng, scene)})
+
+
 def _quat_mul(a, b):
     aw, ax, ay, az = a
     bw, bx, by, bz = b
