@@ -185,7 +185,10 @@ gs_status gs_composite(gs_ctx ctx, int32_t view_begin, int32_t view_count, void*
  * smaller than params->n.  Then only the first grads->n Gaussians (the
  * active pool) are differentiated, and grads rows are strided by grads->n;
  * the others (the frozen pool) are rendered and shape every pixel's
- * transmittance and colour as before but receive no gradient work. */
+ * transmittance and colour as before but receive no gradient work.
+ * The views of the call must have been projected by the latest gs_project
+ * call (whose per-Gaussian visibility lets the adjoint skip Gaussians seen
+ * in none of them). */
 gs_status gs_backward(gs_ctx ctx, const gs_params* params, const gs_camera* dev_cams,
                       int32_t view_begin, int32_t view_count, void* dev_workspace,
                       const float* dev_images, const float* dev_T_final, const float* dev_upstream,

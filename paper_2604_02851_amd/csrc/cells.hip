@@ -51,6 +51,32 @@ __global__ __launch_bounds__(256) void k_assign_cells(ParamPtrs p, gs_grid g, ui
   else atomicMax(&cell_sigma[c], 0x7f800000u);   // NaN scale: never cull its cell
 }
 
+// The same with the per-cell maxima first taken in LDS over a chunk of
+// kCellChunk Gaussians (for grids of at most kLdsCells cells), so that each
+// workgroup sends one global atomic per cell it touched.
+constexpr int kLdsCells = 8192;
+constexpr int kCellChunk = 8192;
+
+__global__ __launch_bounds__(256) void k_assign_cells_lds(ParamPtrs p, gs_grid g, uint32_t n_cells,
+                                                           uint32_t* cell_of, uint32_t* cell_sigma) {
+  __shared__ uint32_t s_max[kLdsCells];
+  for (uint32_t c = threadIdx.x; c <= n_cells; c += blockDim.x) s_max[c] = 0u;
+  __syncthreads();
+  const int64_t n = p.n;
+  const int64_t i0 = (int64_t)blockIdx.x * kCellChunk;
+  const int64_t i1 = i0 + kCellChunk < n ? i0 + kCellChunk : n;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    uint32_t c = cell_of_point(g, p.mean[i], p.mean[n + i], p.mean[2 * n + i]);
+    if (c == 0xffffffffu) c = n_cells;
+    cell_of[i] = c;
+    const float sig = expf(fmaxf(fmaxf(p.lsc[i], p.lsc[n + i]), p.lsc[2 * n + i]));
+    atomicMax(&s_max[c], sig >= 0.f ? __float_as_uint(sig) : 0x7f800000u);
+  }
+  __syncthreads();
+  for (uint32_t c = threadIdx.x; c <= n_cells; c += blockDim.x)
+    if (s_max[c] != 0u) atomicMax(&cell_sigma[c], s_max[c]);
+}
+
 __global__ void k_zero_words(uint32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -110,7 +136,10 @@ hipError_t launch_assign_cells(const ParamPtrs& p, const gs_grid& g, uint32_t* c
                                hipStream_t st) {
   const int64_t nc = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
   hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((nc + 1 + 255) / 256)), dim3(256), 0, st, cell_sigma, nc + 1);
-  if (p.n > 0)
+  if (p.n > 0 && nc + 1 <= kLdsCells)
+    hipLaunchKernelGGL(k_assign_cells_lds, dim3((unsigned)((p.n + kCellChunk - 1) / kCellChunk)), dim3(256), 0, st,
+                       p, g, (uint32_t)nc, cell_of, cell_sigma);
+  else if (p.n > 0)
     hipLaunchKernelGGL(k_assign_cells, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, st, p, g, (uint32_t)nc,
                        cell_of, cell_sigma);
   return hipGetLastError();

@@ -209,12 +209,14 @@ struct ProjArgs {
   uint32_t* count;
   ushort4* rect;
   float4* rec;
+  uint8_t* seen;             // per Gaussian: visible in some view of this call
   const uint32_t* cell_of;   // preculling (null = off)
   const uint8_t* cell_mask;
   int32_t cell_row;
 };
 
-constexpr int kViewWaves = 1;
+constexpr int kViewWaves = 1;   // (the per-Gaussian "seen" flag assumes a single wavefront per Gaussian)
+static_assert(kViewWaves == 1, "one wavefront writes a Gaussian's seen flag");
 
 template <int DEG>
 __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
@@ -223,6 +225,18 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
   const int64_t n = a.p.n;
   if (i >= n || wave >= a.nv) return;
   constexpr int nk = (DEG + 1) * (DEG + 1);
+  const uint32_t cell = a.cell_mask ? a.cell_of[i] : 0u;
+  if (a.cell_mask) {
+    // a Gaussian whose cell no view of the call can see is culled everywhere
+    // without touching its parameters
+    bool any = false;
+    for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) any |= a.cell_mask[(int64_t)v * a.cell_row + cell] != 0;
+    if (!any) {
+      for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) a.count[(int64_t)v * n + i] = 0u;
+      a.seen[i] = 0;
+      return;
+    }
+  }
   // SH coefficients parked in this wavefront's own LDS columns (each lane
   // reads back only what it wrote, so no barrier is needed)
   __shared__ float s_sh[kViewWaves][3 * nk][64];
@@ -236,7 +250,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
   }
   Gauss g;
   load_gauss(a.p, i, g, sh_ok);
-  const uint32_t cell = a.cell_mask ? a.cell_of[i] : 0u;
+  bool seen = false;
 #pragma unroll 1
   for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) {
     const int64_t o = (int64_t)v * n + i;
@@ -283,7 +297,9 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
       }
     }
     a.count[o] = cnt;
+    seen |= cnt != 0u;
   }
+  a.seen[i] = seen ? 1 : 0;
 }
 
 struct ProjBwdArgs {
@@ -291,6 +307,7 @@ struct ProjBwdArgs {
   const gs_camera* cams;
   int v0, nv;
   const uint32_t* count;
+  const uint8_t* seen;
   const float4* g2;
   float4* g2z;   // the same slots, cleared by k_color_bwd after reading
   float* gmean; float* glsc; float* gquat; float* gopac; float* gsh;
@@ -310,7 +327,8 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
   const int64_t n = a.p.n, na = a.n_active;
   Gauss g;
   g.ok = false;
-  if (i < na && wave < a.nv) load_gauss(a.p, i, g, true);
+  // Gaussians visible in no view of the last projection need no set-up
+  if (i < na && wave < a.nv && a.seen[i]) load_gauss(a.p, i, g, true);
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
 #pragma unroll 1
   for (int v = a.v0 + wave; v < a.v0 + a.nv && g.ok; v += kViewWaves) {
@@ -431,7 +449,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
 #pragma unroll
   for (int k = 0; k < kOut; ++k) part[k] = 0.f;
   __shared__ float s_sh[kViewWaves][3 * nk][64];   // per-lane columns: no barrier needed
-  if (i < na && wave < a.nv) {
+  if (i < na && wave < a.nv && a.seen[i]) {
     float* sh_col = &s_sh[wave][0][lane];
 #pragma unroll
     for (int k = 0; k < 3 * nk; ++k) sh_col[k * 64] = a.p.sh[(int64_t)k * n + i];
@@ -506,6 +524,7 @@ hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* c
   a.count = seg<uint32_t>(ws, pl.ws.count);
   a.rect = seg<ushort4>(ws, pl.ws.rect);
   a.rec = seg<float4>(ws, pl.ws.rec);
+  a.seen = seg<uint8_t>(ws, pl.ws.seen);
   a.cell_of = pl.cell_of;
   a.cell_mask = pl.cell_mask;
   a.cell_row = pl.cell_row;
@@ -530,6 +549,7 @@ hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camer
   a.v0 = v0;
   a.nv = nv;
   a.count = seg<uint32_t>(ws, pl.ws.count);
+  a.seen = seg<uint8_t>(ws, pl.ws.seen);
   a.g2 = seg<float4>(ws, pl.ws.g2);
   a.g2z = seg<float4>(ws, pl.ws.g2);
   a.gmean = grads.mean;
