@@ -274,3 +274,25 @@ def cell_of(mean, origin, cell_size, dims):
     idx = np.floor(np.where(inside, t, 0)).astype(np.int64)
     c = idx[0] + d[0, 0] * (idx[1] + d[1, 0] * idx[2])
     return np.where(inside, c, int(np.prod(dims))).astype(np.int64)
+
+
+def cell_order(cells, n_active, n_cells):
+    """Grouping the model by preculling cell (Sec. 3.3: Gaussians belong to
+    grid cells): within the active prefix and within the frozen suffix
+    separately, Gaussians ordered by cell, equal cells in their old order;
+    cell values of n_cells or more count as n_cells (outside the grid).
+
+    Written as the rank definition of a stable sort: the new position of
+    Gaussian i in its pool [lo, hi) is lo + #{j in pool: key_j < key_i} +
+    #{j in pool, j < i: key_j == key_i}.  Returns order, order[k] = old index
+    of the Gaussian now at k."""
+    key = [min(int(c), int(n_cells)) for c in np.asarray(cells).reshape(-1)]
+    n = len(key)
+    order = np.empty(n, np.int64)
+    for lo, hi in ((0, int(n_active)), (int(n_active), n)):
+        for i in range(lo, hi):
+            less = sum(1 for j in range(lo, hi) if key[j] < key[i])
+            tie = sum(1 for j in range(lo, i) if key[j] == key[i])
+            order[lo + less + tie] = i
+    return order
+
