@@ -152,22 +152,28 @@ def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log, froz
     return out
 
 
-def rig_rate(precull: bool, shape: dict, steps: int, warmup: int, torch, log) -> dict:
+def rig_rate(precull: bool, grouped: bool, shape: dict, steps: int, warmup: int, torch, log) -> dict:
     """Steps/s of a large-world workload: 2M Gaussians over an 80 x 8 x 80
     region seen from a rig of 8 outward-looking 1280x720 cameras at its
-    centre, with or without preculling by 4-unit grid cells (the cell
-    assignment and per-view visibility are recomputed every step, inside the
-    timed region)."""
+    centre spread over a 60-degree arc, with or without preculling by 4-unit
+    grid cells (the cell assignment and per-view visibility are recomputed
+    every step, inside the timed region), with the model in its generated
+    order or grouped by cell once before the timed steps."""
     from paper_2604_02851_amd import scenes as S
     from paper_2604_02851_amd.native import DeviceParams
     from paper_2604_02851_amd.renderer import Optimizer, Renderer
-    w = S.rig_workload(7, 2_000_000, half=40.0, height=4.0, views=8, size=(1280, 720))
+    w = S.rig_workload(7, 2_000_000, half=40.0, height=4.0, views=8, size=(1280, 720), arc=60.0)
     stream = torch.cuda.current_stream()
     params = DeviceParams.from_scene(w.scene)
     pdev = DeviceParams.from_scene(w.extra["perturbed"])
     r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, loss_mode=1, **shape)
-    if precull:
+    if precull or grouped:
         r.enable_precull(params, origin=(-40.0, -4.0, -40.0), cell_size=4.0, dims=(20, 2, 20))
+    if grouped:
+        r.sort_cells(pdev)      # targets come from the perturbed model: its own order does not matter
+        r.sort_cells(params)
+    if grouped and not precull:
+        r.disable_precull()
     r.fit_capacity(pdev)
     r.fit_capacity(params)
     targets = r.forward(pdev)[0].clone()
@@ -198,10 +204,11 @@ def rig_rate(precull: bool, shape: dict, steps: int, warmup: int, torch, log) ->
     if r.counters().overflow:
         raise SystemExit("rig workload: key capacity overflowed during the timed steps")
     c = r.counters()
-    log(f"[bench] rig 2M/8 views, precull={precull}: {ms:.3f} ms/step ({1000 / ms:.2f} steps/s), "
-        f"visible pairs {int(c.visible)}")
+    log(f"[bench] rig 2M/8 views/60deg, precull={precull}, grouped={grouped}: {ms:.3f} ms/step "
+        f"({1000 / ms:.2f} steps/s), visible pairs {int(c.visible)}")
     out = {"steps_per_s": round(1000.0 / ms, 3), "ms_per_step": round(ms, 4), "views": len(w.cams),
-           "gaussians": w.scene.n, "precull": precull, "visible_pairs": int(c.visible), "keys": int(c.keys)}
+           "gaussians": w.scene.n, "precull": precull, "grouped_by_cell": grouped, "visible_pairs": int(c.visible),
+           "keys": int(c.keys)}
     del opt, r, params, targets
     torch.cuda.empty_cache()
     return out
@@ -359,8 +366,9 @@ def main():
         # Gaussian freezing: cfg4 with half of the model in the frozen pool
         configs["cfg4_half_frozen"] = config_rate(4, shape, 10, 2, torch, log, frozen=0.5)
         # preculling by grid cells: a large world seen from a camera rig
-        configs["rig2M_no_precull"] = rig_rate(False, shape, 10, 2, torch, log)
-        configs["rig2M_precull"] = rig_rate(True, shape, 10, 2, torch, log)
+        configs["rig2M"] = rig_rate(False, False, shape, 10, 2, torch, log)
+        configs["rig2M_grouped"] = rig_rate(False, True, shape, 10, 2, torch, log)
+        configs["rig2M_grouped_precull"] = rig_rate(True, True, shape, 10, 2, torch, log)
 
     out = {
         "metric": METRIC, "value": round(1000.0 / ms_batched, 3), "unit": "steps/s", "n_gpus": 1,

@@ -257,6 +257,23 @@ gs_status gs_freeze(gs_ctx ctx, gs_params* params, gs_params* m, gs_params* v, c
                     uint32_t* ids, gs_params* baseline, void* dev_workspace, int32_t* new_active,
                     hipStream_t stream);
 
+/* Reorders the model in place so that Gaussians are grouped by grid cell
+ * (Sec. 3.3: Gaussians are assigned to cells and visibility is decided per
+ * cell; keeping each cell's Gaussians together lets whole wavefronts of the
+ * projection and its adjoints skip a culled cell).  A stable sort by
+ * cell_of[i] (device uint32 per Gaussian, from gs_assign_cells; values of
+ * n_cells or more sort as the outside cell n_cells), done separately within
+ * the active prefix [0, m->n) and the frozen suffix, so the pools stay where
+ * they are.  The permutation is applied to every row of params (n = planned
+ * n), to baseline (optional), ids (optional, uint32 per Gaussian) and
+ * cell_of itself, and to the first m->n entries of every row of m and v
+ * (rows strided by m->n).  m and v may both be NULL (no optimizer state: the
+ * whole model is one pool).  Results of later calls are unchanged except for
+ * the order of Gaussians with equal depth keys.  Enqueued on stream; uses
+ * the workspace (the projection's buffers: project again afterwards). */
+gs_status gs_sort_cells(gs_ctx ctx, gs_params* params, gs_params* m, gs_params* v, uint32_t* cell_of,
+                        int32_t n_cells, uint32_t* ids, gs_params* baseline, void* ws, hipStream_t stream);
+
 /* Changed-Gaussian delta (Sec. 3.5: per-attribute tensor deltas relative to
  * the previously transmitted state, Gaussian-ID ordering).  Groups, in this
  * order and bit position of group_mask: 0 opacity (1 value), 1 SH DC (3),

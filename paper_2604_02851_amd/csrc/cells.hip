@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_assign_cells(ParamPtrs p, gs_grid g, ui
 // kCellChunk Gaussians (for grids of at most kLdsCells cells), so that each
 // workgroup sends one global atomic per cell it touched.
 constexpr int kLdsCells = 8192;
-constexpr int kCellChunk = 8192;
+constexpr int kCellChunk = 2048;
 
 __global__ __launch_bounds__(256) void k_assign_cells_lds(ParamPtrs p, gs_grid g, uint32_t n_cells,
                                                            uint32_t* cell_of, uint32_t* cell_sigma) {
@@ -130,7 +130,80 @@ __global__ __launch_bounds__(256) void k_visible_cells(gs_grid g, const gs_camer
   mask[(int64_t)(t / row) * row + c] = vis;
 }
 
+// ---- spatial order: the model kept grouped by cell ---------------------------
+// With Gaussians stored in index order independent of position, every
+// wavefront of the projection holds Gaussians from all over the scene, so
+// per-view culling (by the frustum or by cells) almost never removes a whole
+// wavefront.  Stored grouped by cell, a wavefront's Gaussians share a cell,
+// and a culled cell costs the projection and its adjoints almost nothing.
+
+// sort key: pool (active 0, frozen 1) above the cell index (out-of-range
+// values count as the outside cell n_cells); the value is the position
+__global__ void k_cell_keys(const uint32_t* cell_of, int64_t n, int64_t n_active, uint32_t n_cells, int cell_bits,
+                            uint32_t* key, uint32_t* val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t c = cell_of[i] < n_cells ? cell_of[i] : n_cells;
+  key[i] = ((i >= n_active ? 1u : 0u) << cell_bits) | c;
+  val[i] = (uint32_t)i;
+}
+
+__global__ void k_copy_row(const uint32_t* src, uint32_t* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// row[k] = old[from[k]], k < n (old parked in scratch)
+__global__ void k_gather_row(const uint32_t* scratch, const uint32_t* from, int64_t n, uint32_t* row) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) row[k] = scratch[from[k]];
+}
+
 }  // namespace
+
+hipError_t launch_sort_cells(const Plan& pl, const gs_params& p, const gs_params* m, const gs_params* v,
+                             uint32_t* cell_of, int32_t n_cells, int64_t n_active, uint32_t* ids, const gs_params* base,
+                             void* ws, hipStream_t st) {
+  const int64_t n = p.n;
+  if (n == 0) return hipSuccess;
+  int cell_bits = 1;
+  while (((int64_t)1 << cell_bits) <= (int64_t)n_cells) ++cell_bits;
+  const int bits = (cell_bits + 1 + 7) / 8 * 8;
+  uint32_t* ka = seg<uint32_t>(ws, pl.ws.vkey_a);
+  uint32_t* kb = seg<uint32_t>(ws, pl.ws.vkey_b);
+  uint32_t* va = seg<uint32_t>(ws, pl.ws.vis_a);
+  uint32_t* vb = seg<uint32_t>(ws, pl.ws.vis_b);
+  uint32_t* scratch = seg<uint32_t>(ws, pl.ws.depth);
+  const unsigned gb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_cell_keys, dim3(gb), dim3(256), 0, st, cell_of, n, n_active, (uint32_t)n_cells, cell_bits, ka,
+                     va);
+  bool in_b = false;
+  hipError_t e = launch_sort_pairs(pl, ws, ka, va, kb, vb, n, bits, &in_b, st);
+  if (e != hipSuccess) return e;
+  const uint32_t* from = in_b ? vb : va;   // from[k] = old position of the Gaussian that lands at k
+  auto permute = [&](uint32_t* row, int64_t len) {
+    if (len == 0) return;
+    const unsigned g = (unsigned)((len + 255) / 256);
+    hipLaunchKernelGGL(k_copy_row, dim3(g), dim3(256), 0, st, row, scratch, len);
+    hipLaunchKernelGGL(k_gather_row, dim3(g), dim3(256), 0, st, scratch, from, len, row);
+  };
+  const int nk = (p.sh_degree + 1) * (p.sh_degree + 1);
+  auto permute_tensor = [&](const gs_params& t, int64_t len) {
+    float* rows_of[5] = {t.mean, t.log_scale, t.quat, t.opacity_logit, t.sh};
+    const int count[5] = {3, 3, 4, 1, 3 * nk};
+    for (int g = 0; g < 5; ++g)
+      for (int r = 0; r < count[g]; ++r) permute(reinterpret_cast<uint32_t*>(rows_of[g] + (int64_t)r * len), len);
+  };
+  permute_tensor(p, n);
+  if (base) permute_tensor(*base, n);
+  if (ids) permute(ids, n);
+  permute(cell_of, n);
+  // the active prefix maps onto itself (pool bit above the cell), so the
+  // moments take the permutation's first n_active entries
+  if (m) permute_tensor(*m, n_active);
+  if (v) permute_tensor(*v, n_active);
+  return hipGetLastError();
+}
 
 hipError_t launch_assign_cells(const ParamPtrs& p, const gs_grid& g, uint32_t* cell_of, uint32_t* cell_sigma,
                                hipStream_t st) {

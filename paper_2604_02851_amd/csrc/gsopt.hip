@@ -485,6 +485,27 @@ gs_status gs_freeze(gs_ctx c, gs_params* params, gs_params* m, gs_params* v, con
   return GS_OK;
 }
 
+gs_status gs_sort_cells(gs_ctx c, gs_params* params, gs_params* m, gs_params* v, uint32_t* cell_of, int32_t n_cells,
+                        uint32_t* ids, gs_params* baseline, void* ws, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_sort_cells: no plan");
+  gs_status s;
+  if ((s = check_params(c, params, "gs_sort_cells(params)")) != GS_OK) return s;
+  if ((m == nullptr) != (v == nullptr)) return fail(c, GS_ERR_INVALID, "gs_sort_cells: give both m and v, or neither");
+  if (m) {
+    if ((s = check_trainable(c, m, "gs_sort_cells(m)")) != GS_OK) return s;
+    if ((s = check_trainable(c, v, "gs_sort_cells(v)")) != GS_OK) return s;
+    if (m->n != v->n) return fail(c, GS_ERR_INVALID, "gs_sort_cells: m and v describe different active pools");
+  }
+  if (baseline && (s = check_params(c, baseline, "gs_sort_cells(baseline)")) != GS_OK) return s;
+  if (!ws || (params->n > 0 && !cell_of)) return fail(c, GS_ERR_INVALID, "gs_sort_cells: null workspace or cell_of");
+  if (n_cells < 1) return fail(c, GS_ERR_INVALID, "gs_sort_cells: n_cells=%d", n_cells);
+  GS_HIP(c, launch_sort_cells(c->plan, *params, m, v, cell_of, n_cells, m ? (int64_t)m->n : (int64_t)params->n, ids,
+                              baseline, ws, st));
+  return GS_OK;
+}
+
 gs_status gs_delta_extract(gs_ctx c, const gs_params* cur, const gs_params* base, uint32_t mask, float tau,
                            uint32_t* out, int64_t cap_words, void* ws, hipStream_t st) {
   if (!c) return GS_ERR_INVALID;

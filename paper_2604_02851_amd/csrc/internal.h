@@ -163,6 +163,9 @@ hipError_t launch_visible_cells(const gs_grid& g, const gs_camera* cams, int v0,
 hipError_t launch_freeze(const Plan& pl, const gs_params& p, const gs_params& m, const gs_params& v,
                          const uint8_t* flags, uint32_t* ids, const gs_params* base, void* ws, int32_t* new_active,
                          hipStream_t st);
+hipError_t launch_sort_cells(const Plan& pl, const gs_params& p, const gs_params* m, const gs_params* v,
+                             uint32_t* cell_of, int32_t n_cells, int64_t n_active, uint32_t* ids, const gs_params* base,
+                             void* ws, hipStream_t st);
 hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& base, uint32_t mask, float tau,
                         uint32_t* out, void* ws, hipStream_t st);
 hipError_t launch_epoch_bump(uint32_t* epoch, hipStream_t st);
@@ -171,6 +174,11 @@ bool sorted_values_in_b(const Plan& pl, int v0, int nv);
 // whether compositing kernels were built for this tile shape / pixels per thread
 bool raster_variant_built(int tile_w, int tile_h, int ppt, int wave_w);
 
+// stable radix sort of `count` (key, value) pairs on key bits [0, bits) in the
+// sort scratch of the workspace (histograms and partials); ping-pong buffers,
+// *in_b tells whether the result landed in (kb, vb)
+hipError_t launch_sort_pairs(const Plan& pl, void* ws, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
+                             int64_t count, int bits, bool* in_b, hipStream_t st);
 // exclusive scan of `count` u32 values (count read from *dcount when non-null,
 // capped at `max_count`); total written to *total when non-null.
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t max_count, const uint32_t* dcount,

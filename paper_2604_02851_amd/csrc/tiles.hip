@@ -597,6 +597,11 @@ static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* v
   return hipGetLastError();
 }
 
+hipError_t launch_sort_pairs(const Plan& pl, void* ws, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
+                             int64_t count, int bits, bool* in_b, hipStream_t st) {
+  return radix_sort(pl, ws, ka, va, kb, vb, nullptr, nullptr, count, nullptr, bits, in_b, st);
+}
+
 hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream_t st) {
   Counters* ctr = seg<Counters>(ws, pl.ws.counters);
   const int64_t N = pl.n;

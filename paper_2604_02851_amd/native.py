@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS
 
 EXPORTED = ("gs_create", "gs_destroy", "gs_last_error", "gs_plan", "gs_frame_layout", "gs_workspace_init", "gs_project",
             "gs_build_tile_lists", "gs_composite", "gs_backward", "gs_adam_step", "gs_delta_extract",
-            "gs_delta_reset_baseline", "gs_freeze", "gs_assign_cells", "gs_visible_cells", "gs_set_precull",
+            "gs_delta_reset_baseline", "gs_freeze", "gs_sort_cells", "gs_assign_cells", "gs_visible_cells", "gs_set_precull",
             "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
             "gs_step_launch", "gs_profile_enable", "gs_profile_read", "gs_profile_reset")
 STAGES = ("project", "tile_lists", "composite", "composite_bwd", "project_bwd", "adam", "delta")
@@ -103,6 +103,8 @@ def lib() -> ctypes.CDLL:
         L.gs_set_precull.argtypes = [ctx, c_void_p, c_void_p, c_int32]
         L.gs_freeze.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), POINTER(GsParams), c_void_p, c_void_p,
                                 c_void_p, c_void_p, c_void_p, c_void_p]
+        L.gs_sort_cells.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), POINTER(GsParams), c_void_p, c_int32,
+                                    c_void_p, c_void_p, c_void_p, c_void_p]
         L.gs_read_counters.argtypes = [ctx, c_void_p, c_void_p, POINTER(GsCounters)]
         L.gs_workspace_segment.argtypes = [ctx, c_int32, c_int32, c_int32, POINTER(c_size_t), POINTER(c_size_t)]
         L.gs_profile_enable.argtypes = [ctx, c_int32]
@@ -278,6 +280,15 @@ class Context:
 
     def set_precull(self, cell_of, mask, n_cells: int):
         self._chk(self.L.gs_set_precull(self.h, ptr(cell_of), ptr(mask), int(n_cells)))
+
+    def sort_cells(self, params, cell_of, n_cells: int, ws, m=None, v=None, ids=None, baseline=None, stream=None):
+        p = params.struct()
+        mm = m.struct() if m is not None else None
+        vv = v.struct() if v is not None else None
+        b = baseline.struct() if baseline is not None else None
+        ref = lambda x: ctypes.byref(x) if x is not None else None
+        self._chk(self.L.gs_sort_cells(self.h, ctypes.byref(p), ref(mm), ref(vv), ptr(cell_of), int(n_cells),
+                                       ptr(ids), ref(b), ptr(ws), stream_handle(stream)))
 
     def freeze(self, params, m, v, flags, ws, new_active, ids=None, baseline=None, stream=None):
         p, mm, vv = params.struct(), m.struct(), v.struct()

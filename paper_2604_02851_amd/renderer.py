@@ -69,9 +69,19 @@ class Renderer:
         self.ctx.set_precull(*self.precull)
         return self.cell_of, self.cell_mask
 
-    def update_precull(self, params: DeviceParams):
-        self.ctx.assign_cells(params, self.grid, self.cell_of, self.cell_sigma)
-        self.ctx.visible_cells(self.grid, self.dev_cams, 0, self.n_views, self.cell_sigma, self.cell_mask)
+    def update_precull(self, params: DeviceParams, stream=None):
+        self.ctx.assign_cells(params, self.grid, self.cell_of, self.cell_sigma, stream)
+        self.ctx.visible_cells(self.grid, self.dev_cams, 0, self.n_views, self.cell_sigma, self.cell_mask, stream)
+
+    def sort_cells(self, params: DeviceParams, stream=None, **state):
+        """Reorders the model in place so that Gaussians are grouped by grid
+        cell (stable, within the active and frozen pools), refreshing the cell
+        assignment and the cell mask first; needs enable_precull()'s grid.  `state` passes the
+        optimizer's m, v, ids and baseline, permuted alike.  Results change
+        only in the order of Gaussians with equal depth keys."""
+        assert getattr(self, "grid", None) is not None, "sort_cells needs the grid of enable_precull()"
+        self.update_precull(params, stream)
+        self.ctx.sort_cells(params, self.cell_of, self.n_cells, self.ws, stream=stream, **state)
 
     def disable_precull(self):
         self.precull = None
@@ -228,6 +238,13 @@ class Optimizer:
         self.grads, self.m, self.v = (x.narrowed(na) for x in (self.grads, self.m, self.v))
         self._args_cache.clear()
         return na
+
+    def sort_cells(self):
+        """Groups the model by grid cell (Renderer.sort_cells) together with
+        the moments, ids and delta baseline.  Buffers stay where they are, so
+        a captured graph remains valid."""
+        base = self.delta["baseline"] if self.delta is not None else None
+        self.r.sort_cells(self.params, stream=self.stream, m=self.m, v=self.v, ids=self.ids, baseline=base)
 
     def step(self, plain: bool = False):
         self.r.ctx.step(self.args(plain), self.stream)

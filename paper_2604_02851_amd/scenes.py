@@ -221,12 +221,21 @@ def small_workload(seed: int, n: int, extent: float, sh_degree: int, sizes, dist
 # Applied on the host in float32 to the model and the target copy alike.
 # ---------------------------------------------------------------------------
 
+def _heading(k: int, views: int, arc: float) -> float:
+    """Heading of camera k of a rig spread evenly over `arc` degrees (a full
+    turn places the cameras 360/views apart; a partial arc includes both ends)."""
+    if arc >= 360.0:
+        return 2 * math.pi * k / views
+    return math.radians(arc) * (k / (views - 1) if views > 1 else 0.0)
+
+
 def rig_workload(seed: int, n: int, half: float = 20.0, height: float = 2.0, views: int = 4,
-                 size=(320, 180), sh_degree: int = 3) -> Workload:
+                 size=(320, 180), sh_degree: int = 3, arc: float = 360.0) -> Workload:
     """A wide, flat scene (means uniform in [-half, half] x [-height, height] x
     [-half, half]) seen from a rig of cameras at the origin looking outward at
-    evenly spaced headings, as around a player in a large world: each view
-    sees only part of the model (the preculling workload)."""
+    headings evenly spaced over `arc` degrees, as around a player in a large
+    world: each view sees only part of the model, and with an arc below a
+    full turn part of the model is seen by no view (the preculling workload)."""
     rng = np.random.default_rng(np.random.SeedSequence(260402851 + 1000 + seed))
     scene = draw_scene(rng, n, 1.0, sh_degree)
     scene.mean[0] *= np.float32(half)
@@ -234,7 +243,7 @@ def rig_workload(seed: int, n: int, half: float = 20.0, height: float = 2.0, vie
     scene.mean[2] *= np.float32(half)
     w, h = size
     recs = [look_at((0.0, 0.0, 0.0), w, h, 60.0,
-                    target=(math.cos(2 * math.pi * k / views), 0.0, math.sin(2 * math.pi * k / views)))
+                    target=(math.cos(_heading(k, views, arc)), 0.0, math.sin(_heading(k, views, arc))))
             for k in range(views)]
     return Workload(f"rig{seed}", scene, cams_array(recs), 16, {"perturbed": perturb(rng, scene)})
 
