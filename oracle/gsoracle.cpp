@@ -912,4 +912,165 @@ int64_t or_delta(const float* const* cur, float* const* base, const int32_t* wid
   return pos;
 }
 
+// ---- delta codecs and client replay (Sec. 3.5) -----------------------------
+// The paper codes means and scales as residuals against the previously
+// transmitted state and the other attributes as quantized updates, without
+// giving bit counts, ranges or rounding.  The reading implemented here, per
+// group g with step s_g (inv_g = fl32(1 / s_g)), code width B_g (8 or 16):
+//  mode 0 (raw):      the rule of or_delta; the value is sent as FP32 bits and
+//                     becomes the baseline.
+//  mode 1 (residual): c = clamp(rint(fl32(fl32(p - b) * inv)), -(2^(B-1)-1),
+//                     2^(B-1)-1) (NaN -> 0); the row is sent when some c != 0;
+//                     the baseline (and the receiver) become fl32(b + fl32(c s)),
+//                     so sender and receiver stay bit-identical (closed loop).
+//  mode 2 (quantized): q(x) = clamp(rint(fl32(fl32(x - lo) * inv)), 0, 2^B - 1)
+//                     (NaN -> 0); the row is sent when some q(p) != q(b); the
+//                     baseline and the receiver become fl32(lo + fl32(q(p) s)).
+// rint rounds half to even.  A sent row carries all of its elements; codes
+// of a row are packed little-endian, 32/B per word, a row starting on a word
+// boundary.  Packet words: [0] epoch, [1] group mask, [2..7] row counts,
+// [8] total words, then per masked group in order the ascending indices and
+// the rows' words.
+namespace {
+const int kCodecHeader = 9;
+
+int64_t codec_row_words(int mode, int bits, int width) {
+  if (mode == 0) return width;
+  const int per = 32 / bits;
+  return (width + per - 1) / per;
+}
+
+long codec_code(int mode, int bits, float step, float lo, float p, float b, bool of_base) {
+  const float inv = 1.0f / step;
+  if (mode == 1) {
+    const float r = p - b;
+    const float x = r * inv;
+    double q = std::nearbyint((double)x);
+    if (std::isnan(x)) q = 0.0;
+    const double m = (double)((1L << (bits - 1)) - 1);
+    return (long)std::min(std::max(q, -m), m);
+  }
+  const float v = of_base ? b : p;
+  const float d = v - lo;
+  const float x = d * inv;
+  double q = std::nearbyint((double)x);
+  if (std::isnan(x)) q = 0.0;
+  const double m = (double)((1L << bits) - 1);
+  return (long)std::min(std::max(q, 0.0), m);
+}
+}  // namespace
+
+// Encodes the masked groups of `cur` against `base` (updated in place) into
+// out (capacity checked by the caller); returns the words written.
+int64_t or_codec_encode(const float* const* cur, float* const* base, const int32_t* widths, int64_t n,
+                        uint32_t group_mask, const int32_t* modes, const int32_t* bits, const float* steps,
+                        const float* los, const float* taus, uint32_t epoch, uint32_t* out) {
+  int64_t pos = kCodecHeader;
+  out[0] = epoch;
+  out[1] = group_mask;
+  for (int g = 0; g < 6; ++g) {
+    out[2 + g] = 0;
+    if (!((group_mask >> g) & 1u) || widths[g] == 0) continue;
+    const int W = widths[g], md = modes[g], B = md == 0 ? 32 : bits[g];
+    std::vector<int64_t> rows;
+    for (int64_t i = 0; i < n; ++i) {
+      bool send = false;
+      for (int k = 0; k < W && !send; ++k) {
+        const float p = cur[g][k * n + i], b = base[g][k * n + i];
+        if (md == 0) {
+          const float diff = std::fabs(p - b);
+          const float thr = taus[g] * std::fabs(b);
+          send = diff > thr;
+        } else if (md == 1) {
+          send = codec_code(1, B, steps[g], los[g], p, b, false) != 0;
+        } else {
+          send = codec_code(2, B, steps[g], los[g], p, b, false) != codec_code(2, B, steps[g], los[g], p, b, true);
+        }
+      }
+      if (send) rows.push_back(i);
+    }
+    out[2 + g] = (uint32_t)rows.size();
+    for (int64_t i : rows) out[pos++] = (uint32_t)i;
+    const int64_t wpr = codec_row_words(md, B, W);
+    for (int64_t i : rows) {
+      for (int64_t w = 0; w < wpr; ++w) out[pos + w] = 0u;
+      for (int k = 0; k < W; ++k) {
+        const float p = cur[g][k * n + i];
+        float& b = base[g][k * n + i];
+        if (md == 0) {
+          std::memcpy(&out[pos + k], &p, 4);
+          b = p;
+          continue;
+        }
+        const long c = codec_code(md, B, steps[g], los[g], p, b, false);
+        const float t = (float)c * steps[g];
+        b = md == 1 ? b + t : los[g] + t;
+        const int per = 32 / B;
+        const uint32_t field = (uint32_t)((uint64_t)(int64_t)c & ((1ull << B) - 1));
+        out[pos + k / per] |= field << ((k % per) * B);
+      }
+      pos += wpr;
+    }
+  }
+  out[8] = (uint32_t)pos;
+  return pos;
+}
+
+// Client replay: applies a packet to the receiver's model.  Returns the
+// status bits: 1 epoch differs from `epoch`, 2 malformed (too short, mask bits
+// above 5, rows in unmasked groups, counts above n, a total that disagrees
+// with the header or exceeds packet_words, an index >= n, indices not
+// strictly ascending).  The model is changed only when the status is 0.
+uint32_t or_codec_apply(float* const* model, const int32_t* widths, int64_t n, const uint32_t* pk,
+                        int64_t packet_words, const int32_t* modes, const int32_t* bits, const float* steps,
+                        const float* los, uint32_t epoch) {
+  if (packet_words < kCodecHeader) return 2u;
+  uint32_t status = pk[0] != epoch ? 1u : 0u;
+  const uint32_t mask = pk[1];
+  if (mask & ~0x3Fu) return status | 2u;
+  int64_t total = kCodecHeader;
+  for (int g = 0; g < 6; ++g) {
+    const int64_t c = pk[2 + g];
+    if ((!((mask >> g) & 1u) && c != 0) || c > n) return status | 2u;
+    const int md = modes[g], B = md == 0 ? 32 : bits[g];
+    total += c * (1 + codec_row_words(md, B, widths[g]));
+  }
+  if (total != (int64_t)pk[8] || total > packet_words) return status | 2u;
+  int64_t pos = kCodecHeader;
+  for (int g = 0; g < 6; ++g) {
+    const int64_t c = pk[2 + g];
+    for (int64_t r = 0; r < c; ++r) {
+      const int64_t i = pk[pos + r];
+      if (i >= n || (r > 0 && (int64_t)pk[pos + r - 1] >= i)) return status | 2u;
+    }
+    pos += c * (1 + codec_row_words(modes[g], modes[g] == 0 ? 32 : bits[g], widths[g]));
+  }
+  if (status) return status;
+  pos = kCodecHeader;
+  for (int g = 0; g < 6; ++g) {
+    const int64_t c = pk[2 + g];
+    const int W = widths[g], md = modes[g], B = md == 0 ? 32 : bits[g];
+    const int64_t wpr = codec_row_words(md, B, W);
+    const uint32_t* vals = pk + pos + c;
+    for (int64_t r = 0; r < c; ++r) {
+      const int64_t i = pk[pos + r];
+      for (int k = 0; k < W; ++k) {
+        float& x = model[g][k * n + i];
+        if (md == 0) {
+          std::memcpy(&x, &vals[r * wpr + k], 4);
+          continue;
+        }
+        const int per = 32 / B;
+        const uint32_t field = (vals[r * wpr + k / per] >> ((k % per) * B)) & (uint32_t)((1ull << B) - 1);
+        long code = (long)field;
+        if (md == 1 && (field >> (B - 1)) & 1u) code -= 1L << B;   // two's complement
+        const float t = (float)code * steps[g];
+        x = md == 1 ? x + t : los[g] + t;
+      }
+    }
+    pos += c * (1 + wpr);
+  }
+  return 0u;
+}
+
 }  // extern "C"

@@ -52,6 +52,10 @@ def lib():
         L.or_adam.argtypes = [P, P, P, P, i64, flt, flt, flt, flt, i32, P, P, P]
         L.or_delta.argtypes = [P, P, P, i64, u32, flt, P]
         L.or_delta.restype = i64
+        L.or_codec_encode.argtypes = [P, P, P, i64, u32, P, P, P, P, P, u32, P]
+        L.or_codec_encode.restype = i64
+        L.or_codec_apply.argtypes = [P, P, i64, P, i64, P, P, P, P, u32]
+        L.or_codec_apply.restype = u32
         _lib = L
     return _lib
 
@@ -239,6 +243,66 @@ def delta(cur_scene, base_scene, mask: int = 0x3F, tau: float = 1e-3):
     out = np.zeros(delta_capacity_words(n, cur_scene.sh_degree, mask), np.uint32)
     w = lib().or_delta(cp, bp, _p(widths), n, mask, float(np.float32(tau)), _p(out))
     return out[:w]
+
+
+def codec_row_words(mode: int, bits: int, width: int) -> int:
+    if mode == 0:
+        return width
+    per = 32 // bits
+    return (width + per - 1) // per
+
+
+def codec_capacity_words(n: int, sh_degree: int, codecs, mask: int = 0x3F) -> int:
+    widths = [1, 3, 3 * ((sh_degree + 1) ** 2 - 1), 3, 3, 4]
+    return 9 + sum(n * (1 + codec_row_words(codecs[g][0], codecs[g][1], widths[g]))
+                   for g in range(6) if (mask >> g) & 1)
+
+
+def _codec_arrays(codecs):
+    assert len(codecs) == 6
+    modes = np.array([c[0] for c in codecs], np.int32)
+    bits = np.array([c[1] for c in codecs], np.int32)
+    steps = np.array([c[2] for c in codecs], np.float32)
+    los = np.array([c[3] for c in codecs], np.float32)
+    taus = np.array([c[4] for c in codecs], np.float32)
+    return modes, bits, steps, los, taus
+
+
+def delta_encode(cur_scene, base_scene, codecs, mask: int = 0x3F, epoch: int = 0):
+    """Delta codecs (residual coding for means and scales, quantized updates
+    for the other groups, Sec. 3.5; bit widths, steps and rounding are a
+    reading, written out in the C source).  codecs: six (mode, bits, step, lo,
+    rel_tau) tuples in group order.  Updates `base_scene` in place to what the
+    receiver reconstructs; returns the packet words."""
+    n = cur_scene.n
+    cur = [np.ascontiguousarray(a) for a in group_arrays(cur_scene)]
+    base = group_arrays(base_scene)
+    for b in base:
+        assert b.flags["C_CONTIGUOUS"] or b.size == 0
+    widths = np.array([a.shape[0] for a in cur], np.int32)
+    modes, bits, steps, los, taus = _codec_arrays(codecs)
+    cp = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in cur])
+    bp = (ctypes.c_void_p * 6)(*[b.ctypes.data for b in base])
+    out = np.zeros(codec_capacity_words(n, cur_scene.sh_degree, codecs, mask), np.uint32)
+    w = lib().or_codec_encode(cp, bp, _p(widths), n, mask, _p(modes), _p(bits), _p(steps), _p(los), _p(taus),
+                              int(epoch), _p(out))
+    return out[:w]
+
+
+def delta_apply(model_scene, packet, codecs, epoch: int = 0) -> int:
+    """Client replay of one packet onto the receiver's model (in place).
+    Returns the status bits (1 epoch mismatch, 2 malformed); nothing is
+    applied unless the status is 0."""
+    n = model_scene.n
+    model = group_arrays(model_scene)
+    for b in model:
+        assert b.flags["C_CONTIGUOUS"] or b.size == 0
+    widths = np.array([a.shape[0] for a in model], np.int32)
+    modes, bits, steps, los, _ = _codec_arrays(codecs)
+    mp = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in model])
+    pk = np.ascontiguousarray(packet, np.uint32)
+    return int(lib().or_codec_apply(mp, _p(widths), n, _p(pk), pk.size, _p(modes), _p(bits), _p(steps), _p(los),
+                                    int(epoch)))
 
 
 def freeze_partition(rows_all, rows_active, flags, n_active):
