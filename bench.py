@@ -152,6 +152,63 @@ def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log, froz
     return out
 
 
+def stream_rate(shape: dict, steps: int, torch, log) -> dict:
+    """The streaming path on the 3M-Gaussian dynamics workload: after each
+    optimize step (graph replay), the sender encodes the groups due in that
+    frame with the default codecs and schedule, and a receiver on the same
+    GPU replays the packet (the full buffer is handed over: the header's
+    total bounds it).  Encode and replay are timed with events of their own."""
+    from paper_2604_02851_amd import scenes as S
+    from paper_2604_02851_amd import stream as ST
+    from paper_2604_02851_amd.native import DeviceParams
+    from paper_2604_02851_amd.renderer import Optimizer, Renderer
+    w = S.workload(5)
+    stream = torch.cuda.current_stream()
+    pert = w.extra["perturbed"]
+    S.Dynamics(w.extra["rng_dyn"], w.scene).step([w.scene, pert])
+    params = DeviceParams.from_scene(w.scene)
+    r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, loss_mode=1, **shape)
+    r.fit_capacity(params)
+    pdev = DeviceParams.from_scene(pert)
+    r.fit_capacity(pdev)
+    targets = r.forward(pdev)[0].clone()
+    del pdev
+    opt = Optimizer(r, params, targets, stream=stream)
+    snd = ST.Sender(r.ctx, params, r.ws, stream=stream)
+    rcv = ST.Receiver(r.ctx, w.scene.n, w.scene.sh_degree, stream=stream)
+    rcv.load_snapshot(params, snd.epoch)
+    opt.step()
+    torch.cuda.synchronize()
+    opt.capture()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    words = []
+    for k in range(steps):
+        opt.replay()
+        ev[k][0].record(stream)
+        pk = snd.frame()
+        ev[k][1].record(stream)
+        ev[k][2].record(stream)
+        rcv.apply(pk)
+        ev[k][3].record(stream)
+        words.append(pk[8].clone())
+    torch.cuda.synchronize()
+    enc = [e[0].elapsed_time(e[1]) for e in ev]
+    app = [e[2].elapsed_time(e[3]) for e in ev]
+    words = [int(x.item()) for x in words]
+    ok = int(rcv.status.item()) == 0 and all(torch.equal(a.view(torch.int32), b.view(torch.int32))
+                                             for a, b in zip(rcv.model.tensors(), snd.baseline.tensors()))
+    if not ok:
+        raise SystemExit("streaming: the receiver's model differs from the sender's baseline")
+    out = {"gaussians": w.scene.n, "encode_ms": round(sum(enc) / steps, 4), "apply_ms": round(sum(app) / steps, 4),
+           "packet_words_mean": int(sum(words) / steps), "packet_words_all_groups": words[0],
+           "full_model_words": 11 * w.scene.n + 48 * w.scene.n, "frames": steps}
+    log(f"[bench] streaming 3M: encode {out['encode_ms']:.3f} ms, replay {out['apply_ms']:.3f} ms per frame, "
+        f"{out['packet_words_mean']} words per packet on average (first, all groups: {words[0]})")
+    del opt, r, params, targets, snd, rcv
+    torch.cuda.empty_cache()
+    return out
+
+
 def rig_rate(precull: bool, grouped: bool, shape: dict, steps: int, warmup: int, torch, log) -> dict:
     """Steps/s of a large-world workload: 2M Gaussians over an 80 x 8 x 80
     region seen from a rig of 8 outward-looking 1280x720 cameras at its
@@ -366,6 +423,8 @@ def main():
         # Gaussian freezing: cfg4 with half of the model in the frozen pool
         configs["cfg4_half_frozen"] = config_rate(4, shape, 10, 2, torch, log, frozen=0.5)
         # preculling by grid cells: a large world seen from a camera rig
+        # delta codecs and client replay after each step of the dynamics workload
+        configs["cfg5_stream"] = stream_rate(shape, 8, torch, log)
         configs["rig2M"] = rig_rate(False, False, shape, 10, 2, torch, log)
         configs["rig2M_grouped"] = rig_rate(False, True, shape, 10, 2, torch, log)
         configs["rig2M_grouped_precull"] = rig_rate(True, True, shape, 10, 2, torch, log)

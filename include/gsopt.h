@@ -289,6 +289,60 @@ gs_status gs_delta_extract(gs_ctx ctx, const gs_params* cur, const gs_params* ba
                            uint32_t group_mask, float rel_tau, uint32_t* dev_out,
                            int64_t out_cap_words, void* dev_workspace, hipStream_t stream);
 
+/* Delta codecs (Sec. 3.5: means and scales may be coded as residuals against
+ * the previously transmitted state, the other attributes as quantized
+ * updates; the codecs are configured per tensor before streaming).  Bit
+ * widths, steps and rounding are not given by the paper; this library's
+ * reading, per group with inv = fl32(1 / step), every operation a separately
+ * rounded FP32 operation, rint rounding half to even, NaN codes 0:
+ *   GS_CODEC_RAW       the rule of gs_delta_extract (rel_tau); FP32 values.
+ *   GS_CODEC_RESIDUAL  c = clamp(rint((cur - base) inv), +-(2^(bits-1) - 1));
+ *                      a row is sent when some c != 0; the baseline becomes
+ *                      base + c step (closed loop: what the receiver rebuilds).
+ *   GS_CODEC_QUANT     q(x) = clamp(rint((x - lo) inv), 0, 2^bits - 1); a row
+ *                      is sent when some q(cur) != q(base); the baseline
+ *                      becomes lo + q(cur) step.
+ * bits is 8 or 16 for the coded modes; step > 0 with a finite 1/step. */
+typedef enum { GS_CODEC_RAW = 0, GS_CODEC_RESIDUAL = 1, GS_CODEC_QUANT = 2 } gs_codec_mode;
+typedef struct {
+  int32_t mode;     /* gs_codec_mode */
+  int32_t bits;     /* 8 or 16 (residual, quant); ignored for raw */
+  float step;       /* quantization step (residual, quant) */
+  float lo;         /* quant: the value of code 0 */
+  float rel_tau;    /* raw: relative gate */
+} gs_codec;         /* 20 bytes */
+
+/* Words of the largest packet gs_delta_encode can write for n Gaussians of
+ * degree sh_degree under codecs[6] and group_mask: 9 + sum over masked
+ * groups of n (1 + row words), row words = width for raw, else
+ * ceil(width / (32 / bits)).  Host only; -1 for an invalid codec. */
+int64_t gs_codec_capacity_words(int32_t n, int32_t sh_degree, const gs_codec* codecs, uint32_t group_mask);
+
+/* Coded tensor-delta packet for the masked groups (group order and bits as in
+ * gs_delta_extract).  dev_out (uint32 words): [0] *dev_epoch (the
+ * transmission epoch that gs_delta_reset_baseline advances), [1] group_mask,
+ * [2..7] sent-row counts per group, [8] total words, then per masked group
+ * in order: the ascending indices, then each sent row's words (raw: FP32
+ * values; coded: codes packed little-endian, 32/bits per word, each row
+ * starting on a word).  Baseline rows that are sent are updated to the
+ * receiver's reconstruction.  out_cap_words below gs_codec_capacity_words
+ * gives GS_ERR_INVALID.  Uses the plan's workspace (n = planned n). */
+gs_status gs_delta_encode(gs_ctx ctx, const gs_params* cur, gs_params* baseline, const gs_codec* codecs,
+                          uint32_t group_mask, const uint32_t* dev_epoch, uint32_t* dev_out, int64_t out_cap_words,
+                          void* dev_workspace, hipStream_t stream);
+
+/* Client replay (Sec. 3.5: the receiver keeps a local model and applies
+ * incoming deltas): applies a gs_delta_encode packet (packet_words words on
+ * the device, e.g. as received) to `model` with the sender's codecs.
+ * *dev_status (device uint32) receives 0 when applied, else bits 1 (the
+ * packet's epoch differs from *dev_epoch, the receiver's) and 2 (malformed:
+ * shorter than its header says, mask bits above 5, rows in an unmasked
+ * group, a count above n, an index >= n, or indices not strictly ascending
+ * within a group); a packet with a nonzero status changes nothing.  Needs
+ * no plan (any context); model->n is the receiver's Gaussian count. */
+gs_status gs_delta_apply(gs_ctx ctx, gs_params* model, const gs_codec* codecs, const uint32_t* dev_packet,
+                         int64_t packet_words, const uint32_t* dev_epoch, uint32_t* dev_status, hipStream_t stream);
+
 /* Snapshot bookkeeping (Sec. 3.5): baseline := cur for every tensor and
  * *dev_epoch += 1. */
 gs_status gs_delta_reset_baseline(gs_ctx ctx, const gs_params* cur, const gs_params* baseline,

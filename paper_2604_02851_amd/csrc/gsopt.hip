@@ -531,6 +531,76 @@ gs_status gs_delta_extract(gs_ctx c, const gs_params* cur, const gs_params* base
   return GS_OK;
 }
 
+static bool codec_ok(const gs_codec& k) {
+  if (k.mode == GS_CODEC_RAW) return k.rel_tau >= 0.f && std::isfinite(k.rel_tau);
+  if (k.mode != GS_CODEC_RESIDUAL && k.mode != GS_CODEC_QUANT) return false;
+  if (k.bits != 8 && k.bits != 16) return false;
+  return k.step > 0.f && std::isfinite(k.step) && std::isfinite(1.0f / k.step) && std::isfinite(k.lo);
+}
+
+static int64_t codec_capacity(int64_t n, int sh_degree, const gs_codec* codecs, uint32_t mask) {
+  const int nk = (sh_degree + 1) * (sh_degree + 1);
+  const int widths[6] = {1, 3, 3 * (nk - 1), 3, 3, 4};
+  int64_t need = 9;
+  for (int g = 0; g < 6; ++g)
+    if ((mask >> g) & 1u) need += n * (1 + codec_row_words(codecs[g], widths[g]));
+  return need;
+}
+
+int64_t gs_codec_capacity_words(int32_t n, int32_t sh_degree, const gs_codec* codecs, uint32_t mask) {
+  if (!codecs || n < 0 || sh_degree < 0 || sh_degree > 3 || (mask & ~0x3Fu)) return -1;
+  for (int g = 0; g < 6; ++g)
+    if (!codec_ok(codecs[g])) return -1;
+  return codec_capacity(n, sh_degree, codecs, mask);
+}
+
+static gs_status check_codecs(gs_ctx c, const gs_codec* codecs, const char* what) {
+  if (!codecs) return fail(c, GS_ERR_INVALID, "%s: null codecs", what);
+  for (int g = 0; g < 6; ++g)
+    if (!codec_ok(codecs[g]))
+      return fail(c, GS_ERR_INVALID, "%s: codec of group %d invalid (mode %d, bits %d, step %g, lo %g, rel_tau %g)",
+                  what, g, codecs[g].mode, codecs[g].bits, (double)codecs[g].step, (double)codecs[g].lo,
+                  (double)codecs[g].rel_tau);
+  return GS_OK;
+}
+
+gs_status gs_delta_encode(gs_ctx c, const gs_params* cur, gs_params* base, const gs_codec* codecs, uint32_t mask,
+                          const uint32_t* epoch, uint32_t* out, int64_t cap_words, void* ws, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_delta_encode: no plan");
+  gs_status s;
+  if ((s = check_params(c, cur, "gs_delta_encode(cur)")) != GS_OK) return s;
+  if ((s = check_params(c, base, "gs_delta_encode(baseline)")) != GS_OK) return s;
+  if ((s = check_codecs(c, codecs, "gs_delta_encode")) != GS_OK) return s;
+  if (!out || !ws || !epoch) return fail(c, GS_ERR_INVALID, "gs_delta_encode: null output, epoch or workspace");
+  if (mask & ~0x3Fu) return fail(c, GS_ERR_INVALID, "gs_delta_encode: group_mask 0x%x has bits above 5", mask);
+  const int64_t need = codec_capacity(cur->n, cur->sh_degree, codecs, mask);
+  if (cap_words < need)
+    return fail(c, GS_ERR_INVALID, "gs_delta_encode: out_cap_words=%lld < %lld", (long long)cap_words,
+                (long long)need);
+  if (need > (int64_t)0xffffffffll) return fail(c, GS_ERR_INVALID, "gs_delta_encode: output above 2^32 words");
+  GS_HIP(c, timed(c, ST_DELTA, st,
+                  [&] { return launch_delta_encode(c->plan, *cur, *base, codecs, mask, epoch, out, ws, st); }));
+  return GS_OK;
+}
+
+gs_status gs_delta_apply(gs_ctx c, gs_params* model, const gs_codec* codecs, const uint32_t* packet,
+                         int64_t packet_words, const uint32_t* epoch, uint32_t* status, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!model || model->n < 0 || model->sh_degree < 0 || model->sh_degree > 3)
+    return fail(c, GS_ERR_INVALID, "gs_delta_apply: invalid model");
+  if (model->n > 0 && (!model->mean || !model->log_scale || !model->quat || !model->opacity_logit || !model->sh))
+    return fail(c, GS_ERR_INVALID, "gs_delta_apply: null model tensor");
+  gs_status s;
+  if ((s = check_codecs(c, codecs, "gs_delta_apply")) != GS_OK) return s;
+  if (!packet || !epoch || !status || packet_words < 0)
+    return fail(c, GS_ERR_INVALID, "gs_delta_apply: null packet, epoch or status");
+  GS_HIP(c, launch_delta_apply(*model, codecs, packet, packet_words, epoch, status, st));
+  return GS_OK;
+}
+
 gs_status gs_delta_reset_baseline(gs_ctx c, const gs_params* cur, const gs_params* base, uint32_t* epoch,
                                   hipStream_t st) {
   if (!c) return GS_ERR_INVALID;

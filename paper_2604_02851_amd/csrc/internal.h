@@ -168,6 +168,16 @@ hipError_t launch_sort_cells(const Plan& pl, const gs_params& p, const gs_params
                              void* ws, hipStream_t st);
 hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& base, uint32_t mask, float tau,
                         uint32_t* out, void* ws, hipStream_t st);
+hipError_t launch_delta_encode(const Plan& pl, const gs_params& cur, const gs_params& base, const gs_codec* codecs,
+                               uint32_t mask, const uint32_t* epoch, uint32_t* out, void* ws, hipStream_t st);
+hipError_t launch_delta_apply(const gs_params& model, const gs_codec* codecs, const uint32_t* packet,
+                              int64_t packet_words, const uint32_t* epoch, uint32_t* status, hipStream_t st);
+// words that one sent row of a group of `width` values occupies under a codec
+inline int64_t codec_row_words(const gs_codec& k, int width) {
+  if (k.mode == GS_CODEC_RAW) return width;
+  const int per = 32 / k.bits;
+  return (width + per - 1) / per;
+}
 hipError_t launch_epoch_bump(uint32_t* epoch, hipStream_t st);
 // whether the sorted tile lists of views [v0, v0+nv) end in the second buffer
 bool sorted_values_in_b(const Plan& pl, int v0, int nv);

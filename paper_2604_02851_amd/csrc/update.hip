@@ -97,18 +97,39 @@ __global__ void k_bump_u32(uint32_t* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1u;
 }
 
-// ---- delta extraction -------------------------------------------------------
+// ---- delta extraction and delta codecs ---------------------------------------
+// One set of kernels serves the plain extraction (every group raw, 6-word
+// header) and the coded packets (9-word header: epoch, mask, counts, total).
+// Per group the codec decides which rows are sent and what their words hold:
+//   raw       rows with fl32(|p - b|) > fl32(tau |b|); FP32 values
+//   residual  c = clamp(rint((p - b) * inv), +-(2^(B-1) - 1)); rows with some
+//             c != 0; baseline b + c step (what the receiver rebuilds)
+//   quantized q(x) = clamp(rint((x - lo) * inv), 0, 2^B - 1); rows with some
+//             q(p) != q(b); baseline lo + q(p) step
+// Every operation is a separately rounded FP32 operation (contraction is off
+// in these functions, written with plain operators: the header's rounding
+// intrinsics would be fused under the default contraction of their own
+// definitions),
+// so that sender and receiver reconstruct bit-identical values.  Codes are
+// packed little-endian, 32/B per word, each row starting on a word.
 struct DeltaGroups {
   const float* cur[6];
   float* base[6];
   int32_t width[6];
 };
 
+struct CodecDev {
+  int32_t mode[6], bits[6], wpr[6];
+  float step[6], inv[6], lo[6], tau[6];
+};
+
 struct DeltaArgs {
   DeltaGroups g;
+  CodecDev c;
   int64_t n;
   uint32_t mask;
-  float tau;
+  int32_t hdr;              // 6 (plain extraction) or 9 (coded packet)
+  const uint32_t* epoch;    // coded packets: the transmission epoch
   uint8_t* flags;
   uint32_t* bcount;   // [6][nb], scanned in place
   uint32_t* dbase;    // [0..5] section base, [6..11] count, [15] total
@@ -116,23 +137,47 @@ struct DeltaArgs {
   uint32_t* out;
 };
 
+__device__ __forceinline__ float q_index(float x) {   // rint, NaN -> 0
+  const float q = rintf(x);
+  return q == q ? q : 0.f;
+}
+
+__device__ __forceinline__ int32_t residual_code(float p, float b, float inv, int bits) {
+#pragma clang fp contract(off)
+  const float m = (float)((1 << (bits - 1)) - 1);
+  const float q = q_index((p - b) * inv);
+  return (int32_t)fminf(fmaxf(q, -m), m);
+}
+
+__device__ __forceinline__ int32_t quant_code(float x, float lo, float inv, int bits) {
+#pragma clang fp contract(off)
+  const float m = (float)((1 << bits) - 1);
+  const float q = q_index((x - lo) * inv);
+  return (int32_t)fminf(fmaxf(q, 0.f), m);
+}
+
+__device__ __forceinline__ bool row_sent(const DeltaArgs& a, int g, int64_t i) {
+#pragma clang fp contract(off)
+  const int md = a.c.mode[g];
+  for (int k = 0; k < a.g.width[g]; ++k) {
+    const float p = a.g.cur[g][(int64_t)k * a.n + i];
+    const float b = a.g.base[g][(int64_t)k * a.n + i];
+    bool hit;
+    if (md == 0) hit = fabsf(p - b) > a.c.tau[g] * fabsf(b);
+    else if (md == 1) hit = residual_code(p, b, a.c.inv[g], a.c.bits[g]) != 0;
+    else hit = quant_code(p, a.c.lo[g], a.c.inv[g], a.c.bits[g]) != quant_code(b, a.c.lo[g], a.c.inv[g], a.c.bits[g]);
+    if (hit) return true;
+  }
+  return false;
+}
+
 __global__ __launch_bounds__(256) void k_delta_flags(DeltaArgs a) {
   __shared__ uint32_t s_w[6][4];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   uint32_t f = 0;
   if (i < a.n) {
-    for (int g = 0; g < 6; ++g) {
-      if (!((a.mask >> g) & 1u)) continue;
-      bool hit = false;
-      for (int k = 0; k < a.g.width[g] && !hit; ++k) {
-        const float p = a.g.cur[g][(int64_t)k * a.n + i];
-        const float b = a.g.base[g][(int64_t)k * a.n + i];
-        const float diff = fabsf(p - b);
-        const float thr = a.tau * fabsf(b);
-        hit = diff > thr;
-      }
-      f |= hit ? (1u << g) : 0u;
-    }
+    for (int g = 0; g < 6; ++g)
+      if (((a.mask >> g) & 1u) && row_sent(a, g, i)) f |= 1u << g;
     a.flags[i] = (uint8_t)f;
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -149,19 +194,25 @@ __global__ __launch_bounds__(256) void k_delta_flags(DeltaArgs a) {
 
 __global__ void k_delta_header(DeltaArgs a) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t run = 6;
+  uint32_t run = (uint32_t)a.hdr;
   for (int g = 0; g < 6; ++g) {
     const uint32_t lo = a.bcount[(int64_t)g * a.nb];
     const uint32_t hi = g < 5 ? a.bcount[(int64_t)(g + 1) * a.nb] : a.dbase[15];
     const uint32_t c = hi - lo;
     a.dbase[g] = run;
     a.dbase[6 + g] = c;
-    a.out[g] = c;
-    run += c * (1u + (uint32_t)a.g.width[g]);
+    a.out[a.hdr == 6 ? g : 2 + g] = c;
+    run += c * (1u + (uint32_t)a.c.wpr[g]);
+  }
+  if (a.hdr == 9) {
+    a.out[0] = *a.epoch;
+    a.out[1] = a.mask;
+    a.out[8] = run;
   }
 }
 
 __global__ __launch_bounds__(256) void k_delta_write(DeltaArgs a) {
+#pragma clang fp contract(off)
   __shared__ uint32_t s_w[6][4];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const uint32_t f = i < a.n ? a.flags[i] : 0u;
@@ -181,13 +232,114 @@ __global__ __launch_bounds__(256) void k_delta_write(DeltaArgs a) {
     for (int q = 0; q < w; ++q) r += s_w[g][q];
     r += a.bcount[(int64_t)g * a.nb + blockIdx.x] - a.bcount[(int64_t)g * a.nb];
     const uint32_t base = a.dbase[g], cnt = a.dbase[6 + g];
-    const int wd = a.g.width[g];
+    const int wd = a.g.width[g], md = a.c.mode[g];
+    const int64_t wpr = a.c.wpr[g];
     a.out[base + r] = (uint32_t)i;
-    uint32_t* vals = a.out + base + cnt + (size_t)r * wd;
+    uint32_t* vals = a.out + base + cnt + (size_t)r * wpr;
+    if (md == 0) {
+      for (int k = 0; k < wd; ++k) {
+        const float p = a.g.cur[g][(int64_t)k * a.n + i];
+        vals[k] = __float_as_uint(p);
+        a.g.base[g][(int64_t)k * a.n + i] = p;
+      }
+      continue;
+    }
+    const int B = a.c.bits[g], per = 32 / B;
+    const uint32_t fmask = (1u << B) - 1u;
+    const float step = a.c.step[g], inv = a.c.inv[g], lo = a.c.lo[g];
+    uint32_t word = 0u;
     for (int k = 0; k < wd; ++k) {
       const float p = a.g.cur[g][(int64_t)k * a.n + i];
-      vals[k] = __float_as_uint(p);
-      a.g.base[g][(int64_t)k * a.n + i] = p;
+      float& b = a.g.base[g][(int64_t)k * a.n + i];
+      const int32_t c = md == 1 ? residual_code(p, b, inv, B) : quant_code(p, lo, inv, B);
+      const float t = (float)c * step;
+      b = md == 1 ? (b + t) : (lo + t);
+      word |= ((uint32_t)c & fmask) << ((k % per) * B);
+      if (k % per == per - 1 || k == wd - 1) {
+        vals[k / per] = word;
+        word = 0u;
+      }
+    }
+  }
+}
+
+// ---- client replay: apply a coded packet to the receiver's model -------------
+struct ApplyArgs {
+  float* grp[6];
+  int32_t width[6];
+  CodecDev c;
+  int64_t n;
+  const uint32_t* pk;
+  int64_t pk_words;
+  const uint32_t* epoch;
+  uint32_t* status;
+};
+
+// header sanity (every thread derives the same answer); false if malformed
+__device__ bool packet_layout(const ApplyArgs& a, int64_t* sec) {
+  if (a.pk_words < 9) return false;
+  const uint32_t mask = a.pk[1];
+  if (mask & ~0x3Fu) return false;
+  int64_t total = 9;
+  for (int g = 0; g < 6; ++g) {
+    const int64_t c = a.pk[2 + g];
+    if ((!((mask >> g) & 1u) && c != 0) || c > a.n) return false;
+    sec[g] = total;
+    total += c * (1 + (int64_t)a.c.wpr[g]);
+  }
+  return total == (int64_t)a.pk[8] && total <= a.pk_words;
+}
+
+__global__ __launch_bounds__(256) void k_apply_check(ApplyArgs a) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t sec[6];
+  if (!packet_layout(a, sec)) {
+    if (t0 == 0) atomicOr(a.status, 2u);
+    return;
+  }
+  if (t0 == 0 && a.pk[0] != *a.epoch) atomicOr(a.status, 1u);
+  uint32_t bad = 0u;
+  for (int g = 0; g < 6; ++g) {
+    const int64_t c = a.pk[2 + g];
+    const uint32_t* idx = a.pk + sec[g];
+    for (int64_t r = t0; r < c; r += stride) {
+      const uint32_t i = idx[r];
+      if ((int64_t)i >= a.n || (r > 0 && idx[r - 1] >= i)) bad = 2u;
+    }
+  }
+  if (bad) atomicOr(a.status, bad);
+}
+
+__global__ __launch_bounds__(256) void k_apply(ApplyArgs a) {
+#pragma clang fp contract(off)
+  if (*a.status != 0u) return;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t sec[6];
+  if (!packet_layout(a, sec)) return;   // (the check already reported it)
+  for (int g = 0; g < 6; ++g) {
+    const int64_t c = a.pk[2 + g];
+    const uint32_t* idx = a.pk + sec[g];
+    const int64_t wpr = a.c.wpr[g];
+    const uint32_t* vals = idx + c;
+    const int wd = a.width[g], md = a.c.mode[g];
+    for (int64_t r = t0; r < c; r += stride) {
+      const int64_t i = idx[r];
+      const uint32_t* row = vals + r * wpr;
+      if (md == 0) {
+        for (int k = 0; k < wd; ++k) a.grp[g][(int64_t)k * a.n + i] = __uint_as_float(row[k]);
+        continue;
+      }
+      const int B = a.c.bits[g], per = 32 / B;
+      const uint32_t fmask = (1u << B) - 1u;
+      for (int k = 0; k < wd; ++k) {
+        const uint32_t field = (row[k / per] >> ((k % per) * B)) & fmask;
+        const int32_t code = (md == 1 && ((field >> (B - 1)) & 1u)) ? (int32_t)field - (1 << B) : (int32_t)field;
+        float& x = a.grp[g][(int64_t)k * a.n + i];
+        const float t = (float)code * a.c.step[g];
+        x = md == 1 ? (x + t) : (a.c.lo[g] + t);
+      }
     }
   }
 }
@@ -320,25 +472,44 @@ hipError_t launch_epoch_bump(uint32_t* epoch, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& base, uint32_t mask, float tau,
-                        uint32_t* out, void* ws, hipStream_t st) {
-  DeltaArgs a;
+static void set_groups(const gs_params& cur, float* const* base_rows, DeltaGroups& g) {
   const int64_t n = cur.n;
   const int nk = (cur.sh_degree + 1) * (cur.sh_degree + 1);
-  a.g.cur[0] = cur.opacity_logit;  a.g.base[0] = base.opacity_logit;  a.g.width[0] = 1;
-  a.g.cur[1] = cur.sh;             a.g.base[1] = base.sh;             a.g.width[1] = 3;
-  a.g.cur[2] = cur.sh + 3 * n;     a.g.base[2] = base.sh + 3 * n;     a.g.width[2] = 3 * (nk - 1);
-  a.g.cur[3] = cur.mean;           a.g.base[3] = base.mean;           a.g.width[3] = 3;
-  a.g.cur[4] = cur.log_scale;      a.g.base[4] = base.log_scale;      a.g.width[4] = 3;
-  a.g.cur[5] = cur.quat;           a.g.base[5] = base.quat;           a.g.width[5] = 4;
-  a.n = n;
-  a.mask = mask;
-  a.tau = tau;
+  const float* c[6] = {cur.opacity_logit, cur.sh, cur.sh + 3 * n, cur.mean, cur.log_scale, cur.quat};
+  const int32_t w[6] = {1, 3, 3 * (nk - 1), 3, 3, 4};
+  for (int q = 0; q < 6; ++q) {
+    g.cur[q] = c[q];
+    g.base[q] = base_rows[q];
+    g.width[q] = w[q];
+  }
+}
+
+static void group_rows(const gs_params& t, float** rows) {
+  const int64_t n = t.n;
+  float* r[6] = {t.opacity_logit, t.sh, t.sh + 3 * n, t.mean, t.log_scale, t.quat};
+  for (int q = 0; q < 6; ++q) rows[q] = r[q];
+}
+
+static CodecDev codec_dev(const gs_codec* codecs, const int32_t* width) {
+  CodecDev d;
+  for (int g = 0; g < 6; ++g) {
+    const gs_codec& k = codecs[g];
+    d.mode[g] = k.mode;
+    d.bits[g] = k.mode == GS_CODEC_RAW ? 32 : k.bits;
+    d.wpr[g] = (int32_t)codec_row_words(k, width[g]);
+    d.step[g] = k.step;
+    d.inv[g] = 1.0f / k.step;
+    d.lo[g] = k.lo;
+    d.tau[g] = k.rel_tau;
+  }
+  return d;
+}
+
+static hipError_t run_delta(const Plan& pl, DeltaArgs& a, void* ws, hipStream_t st) {
   a.flags = seg<uint8_t>(ws, pl.ws.dflags);
   a.bcount = seg<uint32_t>(ws, pl.ws.dcount);
   a.dbase = seg<uint32_t>(ws, pl.ws.dbase);
-  a.nb = (int32_t)((n + 255) / 256);
-  a.out = out;
+  a.nb = (int32_t)((a.n + 255) / 256);
   if (a.nb > pl.ws.dblocks) return hipErrorInvalidValue;
   if (a.nb > 0) hipLaunchKernelGGL(k_delta_flags, dim3(a.nb), dim3(256), 0, st, a);
   hipError_t e = launch_scan(a.bcount, a.bcount, 6ll * a.nb, nullptr, seg<uint32_t>(ws, pl.ws.partial),
@@ -346,6 +517,61 @@ hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& b
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_delta_header, dim3(1), dim3(64), 0, st, a);
   if (a.nb > 0) hipLaunchKernelGGL(k_delta_write, dim3(a.nb), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& base, uint32_t mask, float tau,
+                        uint32_t* out, void* ws, hipStream_t st) {
+  DeltaArgs a;
+  float* rows[6];
+  group_rows(base, rows);
+  set_groups(cur, rows, a.g);
+  gs_codec raw[6];
+  for (int g = 0; g < 6; ++g) raw[g] = gs_codec{GS_CODEC_RAW, 32, 1.0f, 0.0f, tau};
+  a.c = codec_dev(raw, a.g.width);
+  a.n = cur.n;
+  a.mask = mask;
+  a.hdr = 6;
+  a.epoch = nullptr;
+  a.out = out;
+  return run_delta(pl, a, ws, st);
+}
+
+hipError_t launch_delta_encode(const Plan& pl, const gs_params& cur, const gs_params& base, const gs_codec* codecs,
+                               uint32_t mask, const uint32_t* epoch, uint32_t* out, void* ws, hipStream_t st) {
+  DeltaArgs a;
+  float* rows[6];
+  group_rows(base, rows);
+  set_groups(cur, rows, a.g);
+  a.c = codec_dev(codecs, a.g.width);
+  a.n = cur.n;
+  a.mask = mask;
+  a.hdr = 9;
+  a.epoch = epoch;
+  a.out = out;
+  return run_delta(pl, a, ws, st);
+}
+
+hipError_t launch_delta_apply(const gs_params& model, const gs_codec* codecs, const uint32_t* packet,
+                              int64_t packet_words, const uint32_t* epoch, uint32_t* status, hipStream_t st) {
+  ApplyArgs a;
+  group_rows(model, a.grp);
+  DeltaGroups g;
+  set_groups(model, a.grp, g);
+  for (int q = 0; q < 6; ++q) a.width[q] = g.width[q];
+  a.c = codec_dev(codecs, a.width);
+  a.n = model.n;
+  a.pk = packet;
+  a.pk_words = packet_words;
+  a.epoch = epoch;
+  a.status = status;
+  hipError_t e = launch_fill_u32(status, 0u, 1, st);
+  if (e != hipSuccess) return e;
+  // rows of all groups together are at most 6 n; a grid-stride loop covers them
+  const int64_t want = (model.n + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > 2048 ? 2048 : want));
+  hipLaunchKernelGGL(k_apply_check, dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_apply, dim3(blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS
 
 EXPORTED = ("gs_create", "gs_destroy", "gs_last_error", "gs_plan", "gs_frame_layout", "gs_workspace_init", "gs_project",
             "gs_build_tile_lists", "gs_composite", "gs_backward", "gs_adam_step", "gs_delta_extract",
-            "gs_delta_reset_baseline", "gs_freeze", "gs_sort_cells", "gs_assign_cells", "gs_visible_cells", "gs_set_precull",
+            "gs_delta_reset_baseline", "gs_codec_capacity_words", "gs_delta_encode", "gs_delta_apply", "gs_freeze", "gs_sort_cells", "gs_assign_cells", "gs_visible_cells", "gs_set_precull",
             "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
             "gs_step_launch", "gs_profile_enable", "gs_profile_read", "gs_profile_reset")
 STAGES = ("project", "tile_lists", "composite", "composite_bwd", "project_bwd", "adam", "delta")
@@ -51,6 +51,19 @@ class GsAdamHparams(ctypes.Structure):
 
 class GsGrid(ctypes.Structure):
     _fields_ = [("origin", c_float * 3), ("cell_size", c_float), ("dims", c_int32 * 3), ("reserved", c_int32)]
+
+
+class GsCodec(ctypes.Structure):
+    _fields_ = [("mode", c_int32), ("bits", c_int32), ("step", c_float), ("lo", c_float), ("rel_tau", c_float)]
+
+
+CODEC_RAW, CODEC_RESIDUAL, CODEC_QUANT = 0, 1, 2
+
+
+def codec_array(codecs):
+    """Six (mode, bits, step, lo, rel_tau) tuples -> a gs_codec[6] array."""
+    assert len(codecs) == 6
+    return (GsCodec * 6)(*[GsCodec(int(m), int(b), float(st), float(lo), float(t)) for m, b, st, lo, t in codecs])
 
 
 class GsCounters(ctypes.Structure):
@@ -97,6 +110,11 @@ def lib() -> ctypes.CDLL:
                                    c_void_p, POINTER(GsAdamHparams), c_void_p]
         L.gs_delta_extract.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), c_uint32, c_float, c_void_p,
                                        c_int64, c_void_p, c_void_p]
+        L.gs_codec_capacity_words.argtypes = [c_int32, c_int32, POINTER(GsCodec), c_uint32]
+        L.gs_delta_encode.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), POINTER(GsCodec), c_uint32, c_void_p,
+                                      c_void_p, c_int64, c_void_p, c_void_p]
+        L.gs_delta_apply.argtypes = [ctx, POINTER(GsParams), POINTER(GsCodec), c_void_p, c_int64, c_void_p, c_void_p,
+                                     c_void_p]
         L.gs_delta_reset_baseline.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), c_void_p, c_void_p]
         L.gs_assign_cells.argtypes = [ctx, POINTER(GsParams), POINTER(GsGrid), c_void_p, c_void_p, c_void_p]
         L.gs_visible_cells.argtypes = [ctx, POINTER(GsGrid), c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]
@@ -114,8 +132,9 @@ def lib() -> ctypes.CDLL:
         L.gs_step_capture.argtypes = [ctx, POINTER(GsStepArgs), c_void_p]
         L.gs_step_launch.argtypes = [ctx, POINTER(GsStepArgs), c_void_p]
         for name in EXPORTED:
-            if name != "gs_last_error":
+            if name not in ("gs_last_error", "gs_codec_capacity_words"):
                 getattr(L, name).restype = st
+        L.gs_codec_capacity_words.restype = c_int64
         _lib = L
     return _lib
 
@@ -125,6 +144,13 @@ def ptr(t: torch.Tensor | None) -> int | None:
         return None
     assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
     return t.data_ptr()
+
+
+def codec_capacity_words(n: int, sh_degree: int, codecs, group_mask: int = 0x3F) -> int:
+    w = lib().gs_codec_capacity_words(int(n), int(sh_degree), codec_array(codecs), int(group_mask))
+    if w < 0:
+        raise ValueError(f"invalid codecs {codecs} or arguments")
+    return int(w)
 
 
 def stream_handle(stream: torch.cuda.Stream | None = None) -> int:
@@ -263,6 +289,16 @@ class Context:
         c, b = cur.struct(), baseline.struct()
         self._chk(self.L.gs_delta_extract(self.h, ctypes.byref(c), ctypes.byref(b), group_mask, rel_tau, ptr(out),
                                           out.numel(), ptr(ws), stream_handle(stream)))
+
+    def delta_encode(self, cur, baseline, codecs, group_mask, dev_epoch, out, ws, stream=None):
+        c, b = cur.struct(), baseline.struct()
+        self._chk(self.L.gs_delta_encode(self.h, ctypes.byref(c), ctypes.byref(b), codec_array(codecs), group_mask,
+                                         ptr(dev_epoch), ptr(out), out.numel(), ptr(ws), stream_handle(stream)))
+
+    def delta_apply(self, model, codecs, packet, packet_words, dev_epoch, dev_status, stream=None):
+        m = model.struct()
+        self._chk(self.L.gs_delta_apply(self.h, ctypes.byref(m), codec_array(codecs), ptr(packet), int(packet_words),
+                                        ptr(dev_epoch), ptr(dev_status), stream_handle(stream)))
 
     def delta_reset_baseline(self, cur, baseline, dev_epoch, stream=None):
         c, b = cur.struct(), baseline.struct()

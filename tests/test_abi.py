@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared():
     src = open(os.path.join(ROOT, "include", "gsopt.h")).read()
-    return sorted(set(re.findall(r"^(?:gs_status|const char\*)\s+(gs_\w+)\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^(?:gs_status|const char\*|int64_t)\s+(gs_\w+)\(", src, flags=re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -37,7 +37,7 @@ def test_binding_structs_match_the_c_layout(tmp_path):
     import subprocess
     from paper_2604_02851_amd import native, scenes
     structs = {"gs_params": native.GsParams, "gs_render_opts": native.GsRenderOpts,
-               "gs_adam_hparams": native.GsAdamHparams, "gs_counters": native.GsCounters, "gs_grid": native.GsGrid,
+               "gs_adam_hparams": native.GsAdamHparams, "gs_counters": native.GsCounters, "gs_grid": native.GsGrid, "gs_codec": native.GsCodec,
                "gs_step_args": native.GsStepArgs}
     lines, expect = [], []
     for cname, cls in structs.items():

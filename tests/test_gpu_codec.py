@@ -1,0 +1,184 @@
+"""Delta codecs and client replay (Sec. 3.5) through the C ABI: coded packets
+and updated baselines bit-exact against the oracle (every codec mode, 8- and
+16-bit codes, ragged sizes across scan blocks, every SH degree, partial
+group masks, the full 3M-Gaussian model after drift); the receiver's replay
+bit-exact against the oracle's and equal to the sender's baseline after
+every packet of a scheduled stream with a snapshot in between; stale and
+malformed packets rejected whole."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import renderer_for
+from paper_2604_02851_amd import native as N
+from paper_2604_02851_amd import scenes as S
+from paper_2604_02851_amd import stream as ST
+from paper_2604_02851_amd.native import DeviceParams
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+RAW = (0, 32, 1.0, 0.0, 1e-3)
+CODEC_SETS = {
+    "default": ST.DEFAULT_CODECS,
+    "residual8": ((1, 8, 1e-2, 0.0, 0.0),) * 6,
+    "quant8": ((2, 8, 0.01, -1.5, 0.0),) * 6,
+    "raw": (RAW,) * 6,
+    "mixed": ((1, 16, 3e-3, 0.0, 0.0), RAW, (2, 16, 1e-3, -3.0, 0.0), (2, 8, 0.05, -6.0, 0.0),
+              (1, 8, 0.02, 0.0, 0.0), RAW),
+}
+
+
+def _drift(sc, rng, amount=0.02, frac=1.0):
+    out = sc.copy()
+    for _, a in out.tensors():
+        hit = rng.random(a.shape) < frac
+        a += (hit * amount * rng.normal(size=a.shape)).astype(F32)
+    return out
+
+
+def _host(dp: DeviceParams):
+    return dp.to_scene()
+
+
+def _same(a, b):
+    return all(np.array_equal(x.view(np.uint32), y.view(np.uint32)) for (_, x), (_, y) in zip(a.tensors(), b.tensors()))
+
+
+def _setup(n, deg, seed):
+    w = S.small_workload(150 + seed, n, 1.0, deg, [(48, 40)], dist=3.0)
+    r = renderer_for(w)
+    return w, r
+
+
+@pytest.mark.parametrize("name", list(CODEC_SETS))
+@pytest.mark.parametrize("n,deg,mask", [(1, 0, 0x3F), (255, 1, 0x3F), (257, 3, 0b101101), (5000, 2, 0x3F),
+                                        (70001, 3, 0b011011)])
+def test_encode_bit_exact(oracle, name, n, deg, mask):
+    codecs = CODEC_SETS[name]
+    w, r = _setup(n, deg, n % 7)
+    rng = np.random.default_rng(n + deg)
+    base_h = w.scene
+    cur_h = _drift(base_h, rng, 0.03, 0.5)
+    cur, base = DeviceParams.from_scene(cur_h), DeviceParams.from_scene(base_h)
+    epoch = torch.tensor([5], dtype=torch.int32, device="cuda")
+    out = torch.zeros(N.codec_capacity_words(n, deg, codecs, mask), dtype=torch.int32, device="cuda")
+    assert out.numel() == oracle.codec_capacity_words(n, deg, codecs, mask)
+    r.ctx.delta_encode(cur, base, codecs, mask, epoch, out, r.ws)
+    torch.cuda.synchronize()
+    ref_base = base_h.copy()
+    ref = oracle.delta_encode(cur_h, ref_base, codecs, mask, epoch=5)
+    got = out.cpu().numpy().view(np.uint32)
+    assert int(got[8]) == ref.size
+    assert np.array_equal(got[:ref.size], ref)
+    assert _same(_host(base), ref_base)
+
+
+def test_full_size_encode_after_drift(oracle):
+    """The 3M-Gaussian streaming model (degree 3) after drift of 10% of its
+    values, all six groups with the default codecs: packet and baselines
+    bit-exact."""
+    w = S.workload(5)
+    n, deg = w.scene.n, w.scene.sh_degree
+    from paper_2604_02851_amd.renderer import Renderer
+    r = Renderer(w.cams[:1], n, deg)
+    rng = np.random.default_rng(55)
+    cur_h = _drift(w.scene, rng, 0.01, 0.1)
+    cur, base = DeviceParams.from_scene(cur_h), DeviceParams.from_scene(w.scene)
+    codecs = ST.DEFAULT_CODECS
+    epoch = torch.tensor([1], dtype=torch.int32, device="cuda")
+    out = torch.zeros(N.codec_capacity_words(n, deg, codecs), dtype=torch.int32, device="cuda")
+    r.ctx.delta_encode(cur, base, codecs, 0x3F, epoch, out, r.ws)
+    torch.cuda.synchronize()
+    ref_base = w.scene.copy()
+    ref = oracle.delta_encode(cur_h, ref_base, codecs, 0x3F, epoch=1)
+    got = out.cpu().numpy().view(np.uint32)
+    print("full-size packet words", ref.size, "rows", ref[2:8].tolist())
+    assert np.array_equal(got[:ref.size], ref)
+    assert _same(_host(base), ref_base)
+
+
+@pytest.mark.parametrize("name", ["default", "mixed", "quant8"])
+def test_scheduled_stream_receiver_tracks_sender(oracle, name):
+    codecs = CODEC_SETS[name]
+    n, deg = 3001, 3
+    w, r = _setup(n, deg, 3)
+    rng = np.random.default_rng(9)
+    model_h = w.scene.copy()
+    params = DeviceParams.from_scene(model_h)
+    snd = ST.Sender(r.ctx, params, r.ws, codecs=codecs)
+    rcv = ST.Receiver(r.ctx, n, deg, codecs=codecs)
+    rcv.load_snapshot(params, snd.epoch)
+    ref_rcv = model_h.copy()
+    ref_base = model_h.copy()
+    ref_epoch = 0
+    for frame in range(10):
+        model_h = _drift(model_h, rng, 0.01, 0.3)
+        for dst, (_, src) in zip(params.tensors(), model_h.tensors()):
+            dst.copy_(torch.from_numpy(np.ascontiguousarray(src)))
+        if frame == 6:                                  # a snapshot: baselines, epoch, receiver reload
+            snd.snapshot()
+            rcv.load_snapshot(params, snd.epoch)
+            ref_base, ref_rcv, ref_epoch = model_h.copy(), model_h.copy(), ref_epoch + 1
+            continue
+        mask = ST.schedule_mask(snd.frames)
+        pk = snd.frame()
+        torch.cuda.synchronize()
+        words = int(pk[8].item())
+        ref = oracle.delta_encode(model_h, ref_base, codecs, mask, epoch=ref_epoch)
+        assert np.array_equal(pk[:words].cpu().numpy().view(np.uint32), ref), frame
+        # the packet as received: its own buffer of exactly `words` words
+        received = pk[:words].clone()
+        rcv.apply(received)
+        assert oracle.delta_apply(ref_rcv, ref, codecs, epoch=ref_epoch) == 0
+        torch.cuda.synchronize()
+        assert int(rcv.status.item()) == 0, frame
+        assert _same(_host(rcv.model), ref_rcv), frame
+        assert _same(_host(rcv.model), _host(snd.baseline)), frame
+
+
+def test_stale_and_malformed_packets_change_nothing(oracle):
+    codecs = ST.DEFAULT_CODECS
+    n, deg = 50, 1
+    w, r = _setup(n, deg, 4)
+    base_h = w.scene.copy()
+    cur_h = base_h.copy()
+    for _, a in cur_h.tensors():
+        a += F32(0.3)
+    pk = oracle.delta_encode(cur_h, base_h.copy(), codecs, 0x3F, epoch=1)
+    cases = {"ok": (pk, 0), "stale": (pk, 1)}
+    cases["short"] = (pk[:8], 2)
+    t = pk.copy(); t[1] |= 1 << 6; cases["mask bits"] = (t, 2)
+    t = pk.copy(); t[9] = n; cases["index out of range"] = (t, 2)
+    t = pk.copy(); t[10] = t[9]; cases["not ascending"] = (t, 2)
+    t = pk.copy(); t[8] += 1; cases["total"] = (t, 2)
+    cases["truncated"] = (pk[:-1], 2)
+    t = oracle.delta_encode(cur_h, base_h.copy(), codecs, 0b1, epoch=1)
+    t[3] = 1; cases["rows in unmasked group"] = (t, 2)
+    for name, (words, want) in cases.items():
+        model = DeviceParams.from_scene(base_h)
+        epoch = torch.tensor([2 if name == "stale" else 1], dtype=torch.int32, device="cuda")
+        status = torch.full((1,), 77, dtype=torch.int32, device="cuda")
+        packet = torch.from_numpy(words.view(np.int32).copy()).cuda()
+        r.ctx.delta_apply(model, codecs, packet, words.size, epoch, status)
+        torch.cuda.synchronize()
+        st = int(status.item())
+        ref_model = base_h.copy()
+        ref_st = oracle.delta_apply(ref_model, words, codecs, epoch=2 if name == "stale" else 1)
+        assert st == ref_st, name
+        assert (st & want) == want if want else st == 0, name
+        assert _same(_host(model), ref_model), name
+        if st:
+            assert _same(_host(model), base_h), name
+
+
+def test_invalid_codecs_are_refused():
+    w, r = _setup(10, 0, 5)
+    P = DeviceParams.from_scene(w.scene)
+    epoch = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = torch.zeros(4096, dtype=torch.int32, device="cuda")
+    for bad in [(1, 12, 0.1, 0.0, 0.0), (2, 8, 0.0, 0.0, 0.0), (2, 8, float("inf"), 0.0, 0.0), (3, 8, 0.1, 0.0, 0.0),
+                (0, 32, 1.0, 0.0, -1.0), (2, 16, 1e-40, 0.0, 0.0)]:
+        with pytest.raises(N.GsError):
+            r.ctx.delta_encode(P, P.clone(), (bad,) + ST.DEFAULT_CODECS[1:], 0x3F, epoch, out, r.ws)
+    with pytest.raises(N.GsError):
+        r.ctx.delta_encode(P, P.clone(), ST.DEFAULT_CODECS, 0x3F, epoch, out[:8], r.ws)   # capacity
