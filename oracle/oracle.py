@@ -360,3 +360,81 @@ def cell_order(cells, n_active, n_cells):
             order[lo + less + tie] = i
     return order
 
+
+# ---- scene dynamics (Sec. 3.4) ------------------------------------------------
+
+def _rot_of_quat(q):
+    """3x3 rotation of the unit quaternion (w, x, y, z) = q / |q| (FP64)."""
+    w, x, y, z = np.asarray(q, np.float64) / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _hamilton(a, b):
+    """Quaternion product a b, (w, x, y, z) order; b may be [4, m]."""
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw])
+
+
+def object_transform(mean, quat, object_of, transforms):
+    """Rigid-object dynamics (Sec. 3.4: Gaussians carry object identifiers and
+    follow the engine's object transforms before each optimization).  Each
+    object k moves by the rigid motion x -> R_k (x - p_k) + p_k + t_k, given
+    as transforms[k] = (q_k (w, x, y, z), p_k pivot, t_k translation) with
+    R_k the rotation of q_k / |q_k|; its Gaussians' means follow it and their
+    orientations compose as q_k/|q_k| * quat (scales, opacity and colour do
+    not change).  object_of[i] < 0 or >= the number of objects: static.
+    FP64, rounded once to FP32.  Returns new (mean, quat) arrays."""
+    mean = np.asarray(mean, np.float32)
+    quat = np.asarray(quat, np.float32)
+    out_m, out_q = mean.copy(), quat.copy()
+    obj = np.asarray(object_of, np.int64)
+    for k, (q, p, t) in enumerate(transforms):
+        idx = np.nonzero(obj == k)[0]
+        if idx.size == 0:
+            continue
+        R = _rot_of_quat(q)
+        p = np.asarray(p, np.float64).reshape(3, 1)
+        t = np.asarray(t, np.float64).reshape(3, 1)
+        mu = mean[:, idx].astype(np.float64)
+        out_m[:, idx] = (R @ (mu - p) + p + t).astype(np.float32)
+        qu = np.asarray(q, np.float64) / np.linalg.norm(q)
+        out_q[:, idx] = _hamilton(qu, quat[:, idx].astype(np.float64)).astype(np.float32)
+    return out_m, out_q
+
+
+SH_C0 = 1.0 / (2.0 * np.sqrt(np.pi))
+
+
+def relight_dc(sh, gain):
+    """Relighting restricted to the diffuse DC term (Sec. 3.4 combines the
+    Gaussians' SH with lighting SH by a rule the paper does not give): the DC
+    colour C0 dc + 1/2 of Gaussian i, channel c, is scaled by gain[c or 0, i]
+    (gain [1, N] for all channels alike or [3, N]); a gain of exactly 1 leaves
+    the coefficient as it is.  FP64, rounded once to FP32.  Returns new sh."""
+    sh = np.asarray(sh, np.float32)
+    gain = np.asarray(gain, np.float32)
+    out = sh.copy()
+    for c in range(3):
+        g = gain[c if gain.shape[0] == 3 else 0].astype(np.float64)
+        dc = sh[c].astype(np.float64)
+        new = ((SH_C0 * dc + 0.5) * g - 0.5) / SH_C0
+        out[c] = np.where(g == 1.0, sh[c], new.astype(np.float32))
+    return out
+
+
+def append_rows(old, add, n_active):
+    """Model expansion (Sec. 3.3: new Gaussians join the trainable part, the
+    trainable tensors and the optimizer state are extended): per row, the
+    active prefix, then the k new Gaussians, then the frozen suffix.  For
+    optimizer moments pass the active rows as `old`, n_active = their count,
+    and zeros as `add`."""
+    old = np.asarray(old)
+    add = np.asarray(add)
+    return np.concatenate([old[..., :n_active], add, old[..., n_active:]], axis=-1)
+
