@@ -365,7 +365,8 @@ def cell_order(cells, n_active, n_cells):
 
 def _rot_of_quat(q):
     """3x3 rotation of the unit quaternion (w, x, y, z) = q / |q| (FP64)."""
-    w, x, y, z = np.asarray(q, np.float64) / np.linalg.norm(q)
+    q = np.asarray(q, np.float64)
+    w, x, y, z = q / np.linalg.norm(q)
     return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
                      [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
                      [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
@@ -403,7 +404,8 @@ def object_transform(mean, quat, object_of, transforms):
         t = np.asarray(t, np.float64).reshape(3, 1)
         mu = mean[:, idx].astype(np.float64)
         out_m[:, idx] = (R @ (mu - p) + p + t).astype(np.float32)
-        qu = np.asarray(q, np.float64) / np.linalg.norm(q)
+        qu = np.asarray(q, np.float64)
+        qu = qu / np.linalg.norm(qu)
         out_q[:, idx] = _hamilton(qu, quat[:, idx].astype(np.float64)).astype(np.float32)
     return out_m, out_q
 
