@@ -209,6 +209,88 @@ def stream_rate(shape: dict, steps: int, torch, log) -> dict:
     return out
 
 
+def dynamics_rate(shape: dict, steps: int, torch, log) -> dict:
+    """Scene dynamics on the device, on the 3M-Gaussian workload: before each
+    optimize step (graph replay) the 20 objects of the dynamics harness move
+    rigidly (a random rotation of up to 5 degrees about the object's initial
+    centroid and a N(0, 0.02) translation, drawn on the host beforehand) and
+    10% of the Gaussians get their DC colour rescaled by U[0.5, 1.5] (a dense
+    gain array, 1 elsewhere).  The dynamics kernels are timed with events of
+    their own; afterwards, appending 100k Gaussians to the model (parameters
+    and moments, new buffers) is timed the same way."""
+    import math
+    import numpy as np
+    from paper_2604_02851_amd import native as N
+    from paper_2604_02851_amd import scenes as S
+    from paper_2604_02851_amd.native import DeviceParams
+    from paper_2604_02851_amd.renderer import Optimizer, Renderer
+    w = S.workload(5)
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(2604)
+    dyn = S.Dynamics(w.extra["rng_dyn"], w.scene)
+    obj = np.full(w.scene.n, -1, np.int32)
+    pivots = []
+    for k, idx in enumerate(dyn.members):
+        obj[idx] = k
+        pivots.append(w.scene.mean[:, idx].astype(np.float64).mean(1))
+    tfs, gains = [], []
+    for _ in range(steps):
+        frame = []
+        for c in pivots:
+            axis = rng.normal(size=3)
+            axis /= np.linalg.norm(axis)
+            ang = math.radians(rng.uniform(0.0, 5.0))
+            frame.append((np.r_[math.cos(ang / 2), math.sin(ang / 2) * axis], c, rng.normal(0.0, 0.02, 3)))
+        tfs.append(N.transforms_tensor(frame))
+        g = np.ones((1, w.scene.n), np.float32)
+        g[0, rng.choice(w.scene.n, w.scene.n // 10, replace=False)] = rng.uniform(0.5, 1.5, w.scene.n // 10)
+        gains.append(torch.from_numpy(g).cuda())
+    obj_dev = torch.from_numpy(obj).cuda()
+    params = DeviceParams.from_scene(w.scene)
+    r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, loss_mode=1, **shape)
+    pdev = DeviceParams.from_scene(w.extra["perturbed"])
+    r.fit_capacity(pdev)
+    r.fit_capacity(params)
+    targets = r.forward(pdev)[0].clone()
+    del pdev
+    opt = Optimizer(r, params, targets, stream=stream)
+    opt.step()
+    torch.cuda.synchronize()
+    opt.capture()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(steps):
+        ev[k][0].record(stream)
+        r.ctx.object_transform(params, obj_dev, tfs[k], len(pivots), stream)
+        r.ctx.relight_dc(params, gains[k], 1, stream)
+        ev[k][1].record(stream)
+        opt.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    dyn_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    if r.counters().overflow:
+        raise SystemExit("dynamics: key capacity overflowed during the timed steps")
+    add = DeviceParams.from_scene(S.draw_scene(rng, 100_000, 5.0, w.scene.sh_degree))
+    n, na, k = params.n, opt.n_active, add.n
+    new_p = DeviceParams.zeros(n + k, w.scene.sh_degree)
+    new_m, new_v = DeviceParams.zeros(na + k, w.scene.sh_degree), DeviceParams.zeros(na + k, w.scene.sh_degree)
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    r.ctx.append(params, add, new_p, na, moments=(opt.m, opt.v, new_m, new_v), stream=stream)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    out = {"steps_per_s": round(1000.0 / ms, 3), "ms_per_step": round(ms, 4), "dynamics_ms": round(dyn_ms, 4),
+           "moved_gaussians": int((obj >= 0).sum()), "relit_gaussians": w.scene.n // 10,
+           "append_100k_ms": round(a0.elapsed_time(a1), 4), "gaussians": w.scene.n}
+    log(f"[bench] dynamics 3M: {ms:.3f} ms/step ({1000 / ms:.2f} steps/s) including object transforms and "
+        f"relighting {dyn_ms:.3f} ms; append 100k: {out['append_100k_ms']:.3f} ms")
+    del opt, r, params, targets, new_p, new_m, new_v, add
+    torch.cuda.empty_cache()
+    return out
+
+
 def rig_rate(precull: bool, grouped: bool, shape: dict, steps: int, warmup: int, torch, log) -> dict:
     """Steps/s of a large-world workload: 2M Gaussians over an 80 x 8 x 80
     region seen from a rig of 8 outward-looking 1280x720 cameras at its
@@ -425,6 +507,8 @@ def main():
         # preculling by grid cells: a large world seen from a camera rig
         # delta codecs and client replay after each step of the dynamics workload
         configs["cfg5_stream"] = stream_rate(shape, 8, torch, log)
+        # object transforms and DC relighting on the device before each step
+        configs["cfg5_dynamics"] = dynamics_rate(shape, 8, torch, log)
         configs["rig2M"] = rig_rate(False, False, shape, 10, 2, torch, log)
         configs["rig2M_grouped"] = rig_rate(False, True, shape, 10, 2, torch, log)
         configs["rig2M_grouped_precull"] = rig_rate(True, True, shape, 10, 2, torch, log)

@@ -274,6 +274,53 @@ gs_status gs_freeze(gs_ctx ctx, gs_params* params, gs_params* m, gs_params* v, c
 gs_status gs_sort_cells(gs_ctx ctx, gs_params* params, gs_params* m, gs_params* v, uint32_t* cell_of,
                         int32_t n_cells, uint32_t* ids, gs_params* baseline, void* ws, hipStream_t stream);
 
+/* ---- scene dynamics and expansion ---------------------------------------- */
+
+/* Rigid motion of one object: x -> R (x - pivot) + pivot + t, R the rotation
+ * of the quaternion q / |q| (w, x, y, z; q must be nonzero). */
+typedef struct {
+  float q[4];
+  float pivot[3];
+  float t[3];
+} gs_transform;   /* 40 bytes */
+
+/* Rigid-object dynamics (Sec. 3.4: Gaussians are tied to engine objects by
+ * identifiers, and the objects' motion is applied to them before each
+ * optimization).  For every Gaussian i with 0 <= object_of[i] < n_objects
+ * (device int32 per Gaussian; other values: static), the mean moves by
+ * dev_transforms[object_of[i]] (device array of n_objects) and the
+ * orientation becomes (q / |q|) * quat (Hamilton product); scales, opacity
+ * and colour do not change.  FP64 arithmetic, each stored value rounded once
+ * to FP32.  In place on params (any n; no plan needed). */
+gs_status gs_object_transform(gs_ctx ctx, gs_params* params, const int32_t* object_of,
+                              const gs_transform* dev_transforms, int32_t n_objects, hipStream_t stream);
+
+/* Relighting of the diffuse term (Sec. 3.4; the paper's full combination of
+ * Gaussian SH with lighting SH is not specified, so only the DC colour is
+ * rescaled): the DC colour C0 dc + 1/2 of Gaussian i and channel c becomes
+ * gain[(channels == 3 ? c : 0) * n + i] times itself (device FP32, channels
+ * 1 or 3 rows of n); a gain of exactly 1 leaves the coefficient unchanged.
+ * FP64 arithmetic, rounded once.  In place on params->sh (any n). */
+gs_status gs_relight_dc(gs_ctx ctx, gs_params* params, const float* dev_gain, int32_t channels,
+                        hipStream_t stream);
+
+/* Model expansion (Sec. 3.3: new Gaussians are appended to the trainable part
+ * and the trainable tensors and optimizer state are extended): writes into
+ * new_params (n = old n + add n) every row as the old active prefix
+ * [0, n_active), then the add Gaussians, then the old frozen suffix; new_m
+ * and new_v (n = n_active + add n) get the old moments followed by zeros
+ * (old_m, old_v, new_m, new_v all NULL when there is no optimizer state;
+ * old moments have n = n_active).  n_cols extra per-Gaussian uint32 columns
+ * (IDs, object indices, cells) are extended the same way: old_cols[c] (old
+ * n), add_cols[c] (add n), new_cols[c] (new n), host arrays of device
+ * pointers.  Out of place; all tensors share the SH degree.  Afterwards the
+ * caller plans for the new n (gs_plan) and, when streaming, sends a
+ * snapshot. */
+gs_status gs_append(gs_ctx ctx, const gs_params* old_params, const gs_params* old_m, const gs_params* old_v,
+                    int32_t n_active, const gs_params* add, gs_params* new_params, gs_params* new_m,
+                    gs_params* new_v, const uint32_t* const* old_cols, const uint32_t* const* add_cols,
+                    uint32_t* const* new_cols, int32_t n_cols, hipStream_t stream);
+
 /* Changed-Gaussian delta (Sec. 3.5: per-attribute tensor deltas relative to
  * the previously transmitted state, Gaussian-ID ordering).  Groups, in this
  * order and bit position of group_mask: 0 opacity (1 value), 1 SH DC (3),

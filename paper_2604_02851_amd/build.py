@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgsopt.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["gsopt.hip", "project.hip", "tiles.hip", "raster.hip", "update.hip", "cells.hip"]
+SOURCES = ["gsopt.hip", "project.hip", "tiles.hip", "raster.hip", "update.hip", "cells.hip", "dynamics.hip"]
 ARCH = os.environ.get("GSOPT_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

@@ -601,6 +601,77 @@ gs_status gs_delta_apply(gs_ctx c, gs_params* model, const gs_codec* codecs, con
   return GS_OK;
 }
 
+static gs_status check_tensor(gs_ctx c, const gs_params* t, const char* what) {
+  if (!t || t->n < 0 || t->sh_degree < 0 || t->sh_degree > 3) return fail(c, GS_ERR_INVALID, "%s: invalid", what);
+  if (t->n > 0 && (!t->mean || !t->log_scale || !t->quat || !t->opacity_logit || !t->sh))
+    return fail(c, GS_ERR_INVALID, "%s: null tensor pointer", what);
+  return GS_OK;
+}
+
+gs_status gs_object_transform(gs_ctx c, gs_params* params, const int32_t* object_of, const gs_transform* tf,
+                              int32_t n_objects, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  gs_status s;
+  if ((s = check_tensor(c, params, "gs_object_transform(params)")) != GS_OK) return s;
+  if (n_objects < 0) return fail(c, GS_ERR_INVALID, "gs_object_transform: n_objects=%d", n_objects);
+  if (params->n > 0 && n_objects > 0 && (!object_of || !tf))
+    return fail(c, GS_ERR_INVALID, "gs_object_transform: null object_of or transforms");
+  GS_HIP(c, launch_object_transform(*params, object_of, tf, n_objects, st));
+  return GS_OK;
+}
+
+gs_status gs_relight_dc(gs_ctx c, gs_params* params, const float* gain, int32_t channels, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  gs_status s;
+  if ((s = check_tensor(c, params, "gs_relight_dc(params)")) != GS_OK) return s;
+  if (channels != 1 && channels != 3) return fail(c, GS_ERR_INVALID, "gs_relight_dc: channels=%d", channels);
+  if (params->n > 0 && !gain) return fail(c, GS_ERR_INVALID, "gs_relight_dc: null gain");
+  GS_HIP(c, launch_relight_dc(*params, gain, channels, st));
+  return GS_OK;
+}
+
+gs_status gs_append(gs_ctx c, const gs_params* old_p, const gs_params* old_m, const gs_params* old_v,
+                    int32_t n_active, const gs_params* add, gs_params* new_p, gs_params* new_m, gs_params* new_v,
+                    const uint32_t* const* old_cols, const uint32_t* const* add_cols, uint32_t* const* new_cols,
+                    int32_t n_cols, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  gs_status s;
+  if ((s = check_tensor(c, old_p, "gs_append(old_params)")) != GS_OK) return s;
+  if ((s = check_tensor(c, add, "gs_append(add)")) != GS_OK) return s;
+  if ((s = check_tensor(c, new_p, "gs_append(new_params)")) != GS_OK) return s;
+  const int deg = old_p->sh_degree;
+  if (add->sh_degree != deg || new_p->sh_degree != deg)
+    return fail(c, GS_ERR_INVALID, "gs_append: SH degrees differ");
+  if ((int64_t)new_p->n != (int64_t)old_p->n + add->n)
+    return fail(c, GS_ERR_INVALID, "gs_append: new n=%d != old n %d + added %d", new_p->n, old_p->n, add->n);
+  if (n_active < 0 || n_active > old_p->n)
+    return fail(c, GS_ERR_INVALID, "gs_append: n_active=%d outside [0, %d]", n_active, old_p->n);
+  const bool moments = old_m || old_v || new_m || new_v;
+  if (moments) {
+    if (!old_m || !old_v || !new_m || !new_v)
+      return fail(c, GS_ERR_INVALID, "gs_append: give all four moment tensors or none");
+    const gs_params* mv[4] = {old_m, old_v, new_m, new_v};
+    const int32_t want[4] = {n_active, n_active, n_active + add->n, n_active + add->n};
+    for (int q = 0; q < 4; ++q) {
+      if ((s = check_tensor(c, mv[q], "gs_append(moments)")) != GS_OK) return s;
+      if (mv[q]->n != want[q] || mv[q]->sh_degree != deg)
+        return fail(c, GS_ERR_INVALID, "gs_append: moment tensor %d has n=%d, want %d", q, mv[q]->n, want[q]);
+    }
+  }
+  if (n_cols < 0 || (n_cols > 0 && (!old_cols || !add_cols || !new_cols)))
+    return fail(c, GS_ERR_INVALID, "gs_append: n_cols=%d with null column arrays", n_cols);
+  for (int q = 0; q < n_cols; ++q)
+    if ((old_p->n > 0 && !old_cols[q]) || (add->n > 0 && !add_cols[q]) || (new_p->n > 0 && !new_cols[q]))
+      return fail(c, GS_ERR_INVALID, "gs_append: null column %d", q);
+  GS_HIP(c, launch_append(*old_p, moments ? old_m : nullptr, moments ? old_v : nullptr, n_active, *add, *new_p,
+                          moments ? new_m : nullptr, moments ? new_v : nullptr, old_cols, add_cols, new_cols, n_cols,
+                          st));
+  return GS_OK;
+}
+
 gs_status gs_delta_reset_baseline(gs_ctx c, const gs_params* cur, const gs_params* base, uint32_t* epoch,
                                   hipStream_t st) {
   if (!c) return GS_ERR_INVALID;

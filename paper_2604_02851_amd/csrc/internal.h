@@ -179,6 +179,13 @@ inline int64_t codec_row_words(const gs_codec& k, int width) {
   return (width + per - 1) / per;
 }
 hipError_t launch_epoch_bump(uint32_t* epoch, hipStream_t st);
+hipError_t launch_object_transform(const gs_params& p, const int32_t* object_of, const gs_transform* tf,
+                                   int32_t n_objects, hipStream_t st);
+hipError_t launch_relight_dc(const gs_params& p, const float* gain, int channels, hipStream_t st);
+hipError_t launch_append(const gs_params& old_p, const gs_params* old_m, const gs_params* old_v, int64_t na,
+                         const gs_params& add, const gs_params& new_p, const gs_params* new_m,
+                         const gs_params* new_v, const uint32_t* const* old_cols, const uint32_t* const* add_cols,
+                         uint32_t* const* new_cols, int n_cols, hipStream_t st);
 // whether the sorted tile lists of views [v0, v0+nv) end in the second buffer
 bool sorted_values_in_b(const Plan& pl, int v0, int nv);
 // whether compositing kernels were built for this tile shape / pixels per thread

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS
 
 EXPORTED = ("gs_create", "gs_destroy", "gs_last_error", "gs_plan", "gs_frame_layout", "gs_workspace_init", "gs_project",
             "gs_build_tile_lists", "gs_composite", "gs_backward", "gs_adam_step", "gs_delta_extract",
-            "gs_delta_reset_baseline", "gs_codec_capacity_words", "gs_delta_encode", "gs_delta_apply", "gs_freeze", "gs_sort_cells", "gs_assign_cells", "gs_visible_cells", "gs_set_precull",
+            "gs_delta_reset_baseline", "gs_codec_capacity_words", "gs_delta_encode", "gs_delta_apply", "gs_object_transform", "gs_relight_dc", "gs_append", "gs_freeze", "gs_sort_cells", "gs_assign_cells", "gs_visible_cells", "gs_set_precull",
             "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
             "gs_step_launch", "gs_profile_enable", "gs_profile_read", "gs_profile_reset")
 STAGES = ("project", "tile_lists", "composite", "composite_bwd", "project_bwd", "adam", "delta")
@@ -58,6 +58,16 @@ class GsCodec(ctypes.Structure):
 
 
 CODEC_RAW, CODEC_RESIDUAL, CODEC_QUANT = 0, 1, 2
+
+
+class GsTransform(ctypes.Structure):
+    _fields_ = [("q", c_float * 4), ("pivot", c_float * 3), ("t", c_float * 3)]
+
+
+def transforms_tensor(transforms, device="cuda") -> torch.Tensor:
+    """[(q (w, x, y, z), pivot, t), ...] -> a device buffer of gs_transform."""
+    a = np.asarray([list(q) + list(p) + list(t) for q, p, t in transforms], np.float32).reshape(-1, 10)
+    return torch.from_numpy(a.copy()).to(device)
 
 
 def codec_array(codecs):
@@ -115,6 +125,11 @@ def lib() -> ctypes.CDLL:
                                       c_void_p, c_int64, c_void_p, c_void_p]
         L.gs_delta_apply.argtypes = [ctx, POINTER(GsParams), POINTER(GsCodec), c_void_p, c_int64, c_void_p, c_void_p,
                                      c_void_p]
+        L.gs_object_transform.argtypes = [ctx, POINTER(GsParams), c_void_p, c_void_p, c_int32, c_void_p]
+        L.gs_relight_dc.argtypes = [ctx, POINTER(GsParams), c_void_p, c_int32, c_void_p]
+        L.gs_append.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), POINTER(GsParams), c_int32,
+                                POINTER(GsParams), POINTER(GsParams), POINTER(GsParams), POINTER(GsParams),
+                                c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
         L.gs_delta_reset_baseline.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), c_void_p, c_void_p]
         L.gs_assign_cells.argtypes = [ctx, POINTER(GsParams), POINTER(GsGrid), c_void_p, c_void_p, c_void_p]
         L.gs_visible_cells.argtypes = [ctx, POINTER(GsGrid), c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]
@@ -299,6 +314,27 @@ class Context:
         m = model.struct()
         self._chk(self.L.gs_delta_apply(self.h, ctypes.byref(m), codec_array(codecs), ptr(packet), int(packet_words),
                                         ptr(dev_epoch), ptr(dev_status), stream_handle(stream)))
+
+    def object_transform(self, params, object_of, dev_transforms, n_objects: int, stream=None):
+        p = params.struct()
+        self._chk(self.L.gs_object_transform(self.h, ctypes.byref(p), ptr(object_of), ptr(dev_transforms),
+                                             int(n_objects), stream_handle(stream)))
+
+    def relight_dc(self, params, gain, channels: int, stream=None):
+        p = params.struct()
+        self._chk(self.L.gs_relight_dc(self.h, ctypes.byref(p), ptr(gain), int(channels), stream_handle(stream)))
+
+    def append(self, old, add, new, n_active: int, moments=None, cols=(), stream=None):
+        """moments: (old_m, old_v, new_m, new_v) or None; cols: [(old, add,
+        new)] per-Gaussian 32-bit columns."""
+        o, a, nw = old.struct(), add.struct(), new.struct()
+        ms = [x.struct() for x in moments] if moments is not None else [None] * 4
+        ref = lambda x: ctypes.byref(x) if x is not None else None
+        nc = len(cols)
+        arr = lambda k: (c_void_p * max(nc, 1))(*[ptr(c[k]) for c in cols])
+        self._chk(self.L.gs_append(self.h, ctypes.byref(o), ref(ms[0]), ref(ms[1]), int(n_active), ctypes.byref(a),
+                                   ctypes.byref(nw), ref(ms[2]), ref(ms[3]), arr(0), arr(1), arr(2), nc,
+                                   stream_handle(stream)))
 
     def delta_reset_baseline(self, cur, baseline, dev_epoch, stream=None):
         c, b = cur.struct(), baseline.struct()

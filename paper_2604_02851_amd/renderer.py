@@ -87,6 +87,17 @@ class Renderer:
         self.precull = None
         self.ctx.set_precull(None, None, 0)
 
+    def resize(self, n: int):
+        """Plans the frame for a model of n Gaussians (after appending): new
+        workspace; the cell assignment buffer of preculling grows with it
+        (call update_precull() before the next step)."""
+        self.n = int(n)
+        if getattr(self, "precull", None) is not None:
+            self.cell_of = torch.zeros(max(self.n, 1), dtype=torch.int32, device=self.device)
+            self.precull = (self.cell_of, self.cell_mask, self.n_cells)
+        self.ws = None
+        self._plan()
+
     def replan(self, key_capacity: int):
         self.key_capacity = int(key_capacity)
         self.ws = None
@@ -245,6 +256,45 @@ class Optimizer:
         a captured graph remains valid."""
         base = self.delta["baseline"] if self.delta is not None else None
         self.r.sort_cells(self.params, stream=self.stream, m=self.m, v=self.v, ids=self.ids, baseline=base)
+
+    def append(self, add: DeviceParams, add_ids: torch.Tensor | None = None) -> DeviceParams:
+        """Model expansion: appends `add` to the end of the active pool
+        (ahead of the frozen pool), extends the moments with zeros, the ids
+        (`add_ids`, default: continuing after the largest id) and the delta
+        baseline (with the new values: send a snapshot), and re-plans the
+        renderer for the new size.  Returns the new parameters, which
+        replace `params` (the old tensors are no longer used).  Synchronises;
+        a captured graph must be captured again."""
+        dev, deg = self.r.device, self.params.sh_degree
+        n, na, k = self.params.n, self.n_active, add.n
+        new_p = DeviceParams.zeros(n + k, deg, dev)
+        new_m, new_v = DeviceParams.zeros(na + k, deg, dev), DeviceParams.zeros(na + k, deg, dev)
+        cols = []
+        if self.ids is not None:
+            if add_ids is None:
+                start = int(self.ids.max().item()) + 1 if n > 0 else 0
+                add_ids = torch.arange(start, start + k, dtype=self.ids.dtype, device=dev)
+            new_ids = torch.zeros(n + k, dtype=self.ids.dtype, device=dev)
+            cols.append((self.ids, add_ids.contiguous(), new_ids))
+        self.r.ctx.append(self.params, add, new_p, na, moments=(self.m, self.v, new_m, new_v), cols=cols,
+                          stream=self.stream)
+        if self.delta is not None:
+            nb = DeviceParams.zeros(n + k, deg, dev)
+            self.r.ctx.append(self.delta["baseline"], add, nb, na, stream=self.stream)
+            self.delta["baseline"] = nb
+            words = N.delta_capacity_words(n + k, deg, self.delta["mask"])
+            self.delta["out"] = torch.zeros(words, dtype=torch.int32, device=dev)
+        (self.stream or torch.cuda.current_stream()).synchronize()
+        self.params, self.m, self.v = new_p, new_m, new_v
+        self.grads = DeviceParams.zeros(na + k, deg, dev)
+        if cols:
+            self.ids = cols[0][2]
+        self.r.resize(n + k)
+        if getattr(self.r, "precull", None) is not None:
+            self.r.update_precull(self.params, self.stream)
+        self.r.fit_capacity(self.params)
+        self._args_cache.clear()
+        return new_p
 
     def step(self, plain: bool = False):
         self.r.ctx.step(self.args(plain), self.stream)

@@ -37,7 +37,7 @@ def test_binding_structs_match_the_c_layout(tmp_path):
     import subprocess
     from paper_2604_02851_amd import native, scenes
     structs = {"gs_params": native.GsParams, "gs_render_opts": native.GsRenderOpts,
-               "gs_adam_hparams": native.GsAdamHparams, "gs_counters": native.GsCounters, "gs_grid": native.GsGrid, "gs_codec": native.GsCodec,
+               "gs_adam_hparams": native.GsAdamHparams, "gs_counters": native.GsCounters, "gs_grid": native.GsGrid, "gs_codec": native.GsCodec, "gs_transform": native.GsTransform,
                "gs_step_args": native.GsStepArgs}
     lines, expect = [], []
     for cname, cls in structs.items():
