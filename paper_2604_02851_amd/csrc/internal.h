@@ -112,14 +112,22 @@ struct SplatGeom {
   float dx, dy, e, P;
 };
 
-__device__ __forceinline__ SplatGeom splat_power(float pxc, float pyc, const float4& r0, const float4& r1) {
+// The compositing kernels stage each record with the conic's a and s already
+// multiplied by -1/2 (halved_conic), so that P = (-a/2 e) e + (-s/2) dy^2 needs
+// no final scaling: multiplying by -1/2 is exact and commutes with every
+// rounding here, so P is bit for bit the value of -1/2 (a e^2 + s dy^2).
+__device__ __forceinline__ float4 halved_conic(const float4& r1) {
+  return make_float4(-0.5f * r1.x, r1.y, -0.5f * r1.z, r1.w);
+}
+
+// r1h: the record's second float4 after halved_conic
+__device__ __forceinline__ SplatGeom splat_power(float pxc, float pyc, const float4& r0, const float4& r1h) {
 #pragma clang fp contract(off)
   SplatGeom g;
   g.dx = (pxc - r0.x) - r0.z;
   g.dy = (pyc - r0.y) - r0.w;
-  g.e = fmaf(r1.y, g.dy, g.dx);
-  const float q = fmaf(r1.x * g.e, g.e, r1.z * (g.dy * g.dy));
-  g.P = -0.5f * q;
+  g.e = fmaf(r1h.y, g.dy, g.dx);
+  g.P = fmaf(r1h.x * g.e, g.e, r1h.z * (g.dy * g.dy));
   return g;
 }
 

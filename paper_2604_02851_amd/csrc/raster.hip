@@ -226,7 +226,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
       const uint32_t id = a.vals[b0 + j];
       const float4 r0 = a.rec[(size_t)id * 3 + 0], r1 = a.rec[(size_t)id * 3 + 1];
       s_rec[j * 3 + 0] = r0;
-      s_rec[j * 3 + 1] = r1;
+      s_rec[j * 3 + 1] = halved_conic(r1);
       s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
       s_mask[j] = splat_wave_mask<G, SW>(r0, r1, tx * TW, ty * TH);
     }
@@ -338,6 +338,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   const bool lo8 = (lane & 8) == 0;
   const int my_field = reduce8_field(lane, lo8);
   const bool writer = (lane & 7) == 0;
+  const float unhalve = my_field < 2 ? -2.f : 1.f;   // fields 0, 1 were summed with the halved conic
   if (threadIdx.x == 0) s_max = rg.x;
   __syncthreads();
   float G0[PPT], G1[PPT], G2[PPT], S0[PPT], S1[PPT], S2[PPT];
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       const float4 r0 = a.rec[(size_t)id * 3 + 0], r1 = a.rec[(size_t)id * 3 + 1];
       s_id[j] = id;
       s_rec[j * 3 + 0] = r0;
-      s_rec[j * 3 + 1] = r1;
+      s_rec[j * 3 + 1] = halved_conic(r1);
       s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
       // bit 31: the splat's Gaussian is trainable (frozen ones still shape T and S)
       s_mask[j] = splat_wave_mask<G, SW>(r0, r1, tx * TW, ty * TH) | (id % a.n_gauss < a.n_active ? kActiveBit : 0u);
@@ -415,24 +416,29 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         bool clamped;
         const bool take = splat_alpha(sg.P, r1.w, Gs, al, clamped) && cand;
         contrib = contrib || take;
-        // predicated from here on; lanes that do not take the splat add zeros.
-        // A frozen splat runs the same arithmetic (its sums are dropped below):
-        // a second, gradient-free copy of this loop costs more registers
-        // than the work it would save.
-        const float Tj = T[q] * __builtin_amdgcn_rcpf(1.f - al);
+        // predicated from here on: a lane that does not take the splat runs
+        // with alpha 0, which leaves its S unchanged and adds zeros (staged
+        // records are finite, so 0 times any product is 0).  A frozen splat
+        // runs the same arithmetic (its sums are dropped below): a second,
+        // gradient-free copy of this loop costs more registers than the
+        // work it would save.
+        const float alt = take ? al : 0.f;
+        const float Tj = T[q] * __builtin_amdgcn_rcpf(1.f - alt);
         T[q] = take ? Tj : T[q];
-        const float at = take ? al * Tj : 0.f;
+        const float at = alt * Tj;
         g[6] = fmaf(at, G0[q], g[6]);
         g[7] = fmaf(at, G1[q], g[7]);
         g[8] = fmaf(at, G2[q], g[8]);
         const float d0 = r2.x - S0[q], d1 = r2.y - S1[q], d2 = r2.z - S2[q];
-        const float dLda = take ? Tj * (d0 * G0[q] + d1 * G1[q] + d2 * G2[q]) : 0.f;
-        S0[q] = take ? fmaf(al, d0, S0[q]) : S0[q];
-        S1[q] = take ? fmaf(al, d1, S1[q]) : S1[q];
-        S2[q] = take ? fmaf(al, d2, S2[q]) : S2[q];
-        const float dLda_u = clamped ? 0.f : dLda;   // the clamp cuts alpha off from opacity and power
-        const float dLdP = dLda_u * al;
-        g[5] = fmaf(dLda_u, Gs, g[5]);
+        // the clamp cuts alpha off from opacity and power
+        const float dLda = (take && !clamped) ? Tj * (d0 * G0[q] + d1 * G1[q] + d2 * G2[q]) : 0.f;
+        S0[q] = fmaf(alt, d0, S0[q]);
+        S1[q] = fmaf(alt, d1, S1[q]);
+        S2[q] = fmaf(alt, d2, S2[q]);
+        const float dLdP = dLda * alt;
+        g[5] = fmaf(dLda, Gs, g[5]);
+        // with the halved conic, fields 0 and 1 collect -1/2 of their sums
+        // (restored exactly after the reduction)
         const float ae = r1.x * sg.e;
         g[0] = fmaf(dLdP, ae, g[0]);
         g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * sg.dy), g[1]);
@@ -442,7 +448,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         g[4] = fmaf(hm * sg.dy, sg.dy, g[4]);
       }
       if (!act || __ballot(contrib) == 0ull) continue;
-      const float tot8 = reduce8(g, lo8);
+      const float tot8 = reduce8(g, lo8) * unhalve;
       const float tot9 = wave_total_lane63(g[8]);
       if (kMultiWave) {
         float* dst = s_g + (wave * BATCH + j) * 9;
