@@ -206,18 +206,19 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
   const int px = x0 + lane % SW, py0 = y0 + lane / SW;
   const uint2 rg = clamp_range(a.ranges[t], a.cap);
   const float pxc = (float)px + 0.5f;
+  // T > 0 while the pixel composites; a pixel that stopped (or lies outside
+  // the image) carries -T, so that one compare answers both questions
   float T[PPT], c0[PPT], c1[PPT], c2[PPT];
   uint32_t n[PPT], last[PPT];
-  bool done[PPT];
   bool live = false;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
-    T[q] = 1.f;
+    const bool inside = px < view.width && py0 + q * G::LROWS < view.height;
+    T[q] = inside ? 1.f : -1.f;
     c0[q] = c1[q] = c2[q] = 0.f;
     n[q] = 0;
     last[q] = rg.x;
-    done[q] = !(px < view.width && py0 + q * G::LROWS < view.height);
-    live |= !done[q];
+    live |= inside;
   }
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
     if (__syncthreads_count(live) == 0) break;
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
         for (int q = 0; q < PPT; ++q) {
           const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
           const SplatGeom sg = splat_power(pxc, pyc, r0, r1);
-          const bool cand = !done[q] && sg.P >= kCutoff;
+          const bool cand = T[q] > 0.f && sg.P >= kCutoff;
           if (__ballot(cand) == 0ull) continue;   // uniform: no lane of this row slot is near the splat
           float Gs, al;
           bool clamped;
@@ -249,19 +250,18 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
           const float Tn = T[q] * (1.f - al);
           const bool stop = take && Tn < kTMin;
           const bool comp = take && !stop;
-          done[q] = done[q] || stop;
           const float w = comp ? al * T[q] : 0.f;
           c0[q] = fmaf(r2.x, w, c0[q]);
           c1[q] = fmaf(r2.y, w, c1[q]);
           c2[q] = fmaf(r2.z, w, c2[q]);
-          T[q] = comp ? Tn : T[q];
+          T[q] = comp ? Tn : (stop ? -T[q] : T[q]);
           n[q] += comp ? 1u : 0u;
           last[q] = comp ? pos1 : last[q];
         }
       }
       live = false;
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) live |= !done[q];
+      for (int q = 0; q < PPT; ++q) live |= T[q] > 0.f;
     }
   }
   const int64_t HW = (int64_t)view.width * view.height;
@@ -271,10 +271,11 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
     const int py = py0 + q * G::LROWS;
     if (px < view.width && py < view.height) {
       const int64_t p = (int64_t)py * view.width + px;
-      im[p] = fmaf(T[q], a.bg0, c0[q]);
-      im[HW + p] = fmaf(T[q], a.bg1, c1[q]);
-      im[2 * HW + p] = fmaf(T[q], a.bg2, c2[q]);
-      a.T[view.pix_off + p] = T[q];
+      const float Tf = fabsf(T[q]);
+      im[p] = fmaf(Tf, a.bg0, c0[q]);
+      im[HW + p] = fmaf(Tf, a.bg1, c1[q]);
+      im[2 * HW + p] = fmaf(Tf, a.bg2, c2[q]);
+      a.T[view.pix_off + p] = Tf;
       a.ncontrib[view.pix_off + p] = n[q];
       a.last[view.pix_off + p] = last[q];
     }
@@ -338,7 +339,10 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   const bool lo8 = (lane & 8) == 0;
   const int my_field = reduce8_field(lane, lo8);
   const bool writer = (lane & 7) == 0;
-  const float unhalve = my_field < 2 ? -2.f : 1.f;   // fields 0, 1 were summed with the halved conic
+  // constant factors left out of the per-pixel sums, powers of two (exact):
+  // fields 0, 1 were summed with the halved conic, fields 2-4 without
+  // d P / d conic's factors -1/2, -1, -1/2
+  const float unhalve = my_field < 2 ? -2.f : my_field == 3 ? -1.f : my_field < 5 ? -0.5f : 1.f;
   if (threadIdx.x == 0) s_max = rg.x;
   __syncthreads();
   float G0[PPT], G1[PPT], G2[PPT], S0[PPT], S1[PPT], S2[PPT];
@@ -438,14 +442,15 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         const float dLdP = dLda * alt;
         g[5] = fmaf(dLda, Gs, g[5]);
         // with the halved conic, fields 0 and 1 collect -1/2 of their sums
-        // (restored exactly after the reduction)
         const float ae = r1.x * sg.e;
         g[0] = fmaf(dLdP, ae, g[0]);
         g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * sg.dy), g[1]);
-        const float hm = -0.5f * dLdP;
-        g[2] = fmaf(hm * sg.dx, sg.dx, g[2]);
-        g[3] = fmaf(2.f * hm * sg.dx, sg.dy, g[3]);
-        g[4] = fmaf(hm * sg.dy, sg.dy, g[4]);
+        // conic fields without their constant factors -1/2, -1, -1/2 (also
+        // restored exactly after the reduction)
+        const float tx_ = dLdP * sg.dx, ty_ = dLdP * sg.dy;
+        g[2] = fmaf(tx_, sg.dx, g[2]);
+        g[3] = fmaf(tx_, sg.dy, g[3]);
+        g[4] = fmaf(ty_, sg.dy, g[4]);
       }
       if (!act || __ballot(contrib) == 0ull) continue;
       const float tot8 = reduce8(g, lo8) * unhalve;
