@@ -409,7 +409,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       float g[9];
 #pragma unroll
       for (int f = 0; f < 9; ++f) g[f] = 0.f;
-      bool contrib = false;
+      float contrib = 0.f;   // > 0 once the lane took the splat at one of its pixels
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
         const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
@@ -419,7 +419,6 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         float Gs, al;
         bool clamped;
         const bool take = splat_alpha(sg.P, r1.w, Gs, al, clamped) && cand;
-        contrib = contrib || take;
         // predicated from here on: a lane that does not take the splat runs
         // with alpha 0, which leaves its S unchanged and adds zeros (staged
         // records are finite, so 0 times any product is 0).  A frozen splat
@@ -427,6 +426,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         // gradient-free copy of this loop costs more registers than the
         // work it would save.
         const float alt = take ? al : 0.f;
+        contrib += alt;
         const float Tj = T[q] * __builtin_amdgcn_rcpf(1.f - alt);
         T[q] = take ? Tj : T[q];
         const float at = alt * Tj;
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         g[3] = fmaf(tx_, sg.dy, g[3]);
         g[4] = fmaf(ty_, sg.dy, g[4]);
       }
-      if (!act || __ballot(contrib) == 0ull) continue;
+      if (!act || __ballot(contrib > 0.f) == 0ull) continue;
       const float tot8 = reduce8(g, lo8) * unhalve;
       const float tot9 = wave_total_lane63(g[8]);
       if (kMultiWave) {
