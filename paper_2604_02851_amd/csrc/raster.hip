@@ -36,6 +36,7 @@ struct Geom {
   static_assert(NT % 64 == 0 && 64 % SW == 0 && TW % SW == 0 && TH % WROWS == 0 &&
                     NWAVES == WPR * (TH / WROWS),
                 "tile / pixels-per-thread / wave shape");
+  static_assert(NWAVES * PPT <= 31, "one strip bit per wavefront and pixel slot, below the active bit");
 };
 
 // Workgroup -> tile.  Schedule 0: row-major tile order.  Schedule 1: each
@@ -57,7 +58,7 @@ __device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t ntiles, i
 // 0.1% + 0.01 for FP32 rounding of both evaluations, so culling never
 // changes a result.
 constexpr float kCullQ = 9.0f * 1.001f + 0.01f;
-constexpr uint32_t kActiveBit = 0x80000000u;   // in the per-splat wavefront mask (at most 16 wavefronts)
+constexpr uint32_t kActiveBit = 0x80000000u;   // in the per-splat strip mask (at most 31 strip bits)
 
 __device__ __forceinline__ float rect_qmin(float a, float r, float s, float inv, float cu, float cw, float x0,
                                            float x1, float y0, float y1) {
@@ -80,21 +81,35 @@ __device__ __forceinline__ float rect_qmin(float a, float r, float s, float inv,
   return best;
 }
 
-// Bit w set when the splat may reach a pixel of wavefront w's sub-tile of the
-// tile whose top-left pixel is (tx0, ty0).
-template <class G, int SW>
-__device__ __forceinline__ uint32_t splat_wave_mask(const float4& r0, const float4& r1, int tx0, int ty0) {
+// Bit (w * PPT + q) set when the splat may reach a pixel of pixel slot q of
+// wavefront w (a strip of SW x LROWS pixels of the tile whose top-left pixel
+// is (tx0, ty0)), for the wavefronts w in [w0, w1).
+template <class G, int SW, int PPT>
+__device__ __forceinline__ uint32_t splat_strip_mask(const float4& r0, const float4& r1, int tx0, int ty0, int w0,
+                                                     int w1) {
   const float cu = r0.x + r0.z, cw = r0.y + r0.w;
   const float a = r1.x, r = r1.y, s = r1.z;
   const float inv = 1.f / fmaf(a * r, r, s);
   uint32_t m = 0;
-#pragma unroll
-  for (int w = 0; w < G::NWAVES; ++w) {
+  // not unrolled: the compositing kernels' register budget is set by their
+  // main loops, and unrolled strip tests would raise it
+#pragma unroll 1
+  for (int w = w0; w < w1; ++w) {
     const float x0 = (float)(tx0 + (w % G::WPR) * SW) + 0.5f, x1 = x0 + (float)(SW - 1);
-    const float y0 = (float)(ty0 + (w / G::WPR) * G::WROWS) + 0.5f, y1 = y0 + (float)(G::WROWS - 1);
-    if (!(rect_qmin(a, r, s, inv, cu, cw, x0, x1, y0, y1) > kCullQ)) m |= 1u << w;
+#pragma unroll 1
+    for (int q = 0; q < PPT; ++q) {
+      const float y0 = (float)(ty0 + (w / G::WPR) * G::WROWS + q * G::LROWS) + 0.5f;
+      const float y1 = y0 + (float)(G::LROWS - 1);
+      if (!(rect_qmin(a, r, s, inv, cu, cw, x0, x1, y0, y1) > kCullQ)) m |= 1u << (w * PPT + q);
+    }
   }
   return m;
+}
+
+// The strip bits of staged splat j (the halves' words combined).
+template <uint32_t H>
+__device__ __forceinline__ uint32_t strip_word(const uint32_t* m, uint32_t j) {
+  return H == 2 ? (m[2 * j] | m[2 * j + 1]) : m[j];
 }
 
 // Ranges are clamped to the key capacity so that a workspace whose lists were
@@ -194,8 +209,9 @@ struct CompArgs {
 template <int TW, int TH, int PPT, int SW, int BATCH>
 __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
   using G = Geom<TW, TH, PPT, SW>;
+  constexpr uint32_t kHalves = G::NWAVES >= 2 ? 2 : 1;
   __shared__ float4 s_rec[BATCH * 3];
-  __shared__ uint32_t s_mask[BATCH];
+  __shared__ uint32_t s_mask[BATCH * kHalves];
   const uint32_t slot = tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule);
   const int t = a.tile_begin + (int)slot;
   const ViewInfo view = a.views[a.tile_view[t]];
@@ -223,22 +239,30 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
     if (__syncthreads_count(live) == 0) break;
     const uint32_t cnt = min((uint32_t)BATCH, rg.y - b0);
-    for (uint32_t j = threadIdx.x; j < cnt; j += G::NT) {
+    // two threads per splat share its strip tests (half the wavefronts each)
+    for (uint32_t u = threadIdx.x; u < cnt * kHalves; u += G::NT) {
+      const uint32_t j = u / kHalves, h = u % kHalves;
       const uint32_t id = a.vals[b0 + j];
       const float4 r0 = a.rec[(size_t)id * 3 + 0], r1 = a.rec[(size_t)id * 3 + 1];
-      s_rec[j * 3 + 0] = r0;
-      s_rec[j * 3 + 1] = halved_conic(r1);
-      s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
-      s_mask[j] = splat_wave_mask<G, SW>(r0, r1, tx * TW, ty * TH);
+      if (h == 0) {
+        s_rec[j * 3 + 0] = r0;
+        s_rec[j * 3 + 1] = halved_conic(r1);
+        s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
+      }
+      s_mask[u] = splat_strip_mask<G, SW, PPT>(r0, r1, tx * TW, ty * TH, (int)h * G::NWAVES / kHalves,
+                                               ((int)h + 1) * G::NWAVES / kHalves);
     }
     __syncthreads();
     if (live) {
       for (uint32_t j = 0; j < cnt; ++j) {
-        if (!((__builtin_amdgcn_readfirstlane(s_mask[j]) >> wave) & 1u)) continue;
+        const uint32_t qb = (__builtin_amdgcn_readfirstlane(strip_word<kHalves>(s_mask, j)) >> (wave * PPT)) &
+                            ((1u << PPT) - 1u);
+        if (qb == 0u) continue;
         const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1], r2 = s_rec[j * 3 + 2];
         const uint32_t pos1 = b0 + j + 1;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
+          if (!((qb >> q) & 1u)) continue;   // uniform: the splat misses this pixel slot's strip
           const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
           const SplatGeom sg = splat_power(pxc, pyc, r0, r1);
           const bool cand = T[q] > 0.f && sg.P >= kCutoff;
@@ -319,8 +343,9 @@ template <int TW, int TH, int PPT, int SW, int BATCH>
 __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   using G = Geom<TW, TH, PPT, SW>;
   constexpr bool kMultiWave = G::NWAVES > 1;
+  constexpr uint32_t kHalves = G::NWAVES >= 2 ? 2 : 1;
   __shared__ float4 s_rec[BATCH * 3];
-  __shared__ uint32_t s_mask[BATCH];
+  __shared__ uint32_t s_mask[BATCH * kHalves];
   __shared__ uint32_t s_id[BATCH];
   __shared__ float s_g[kMultiWave ? G::NWAVES * BATCH * 9 : 1];   // per-wavefront splat sums of a batch
   __shared__ uint32_t s_max;
@@ -386,22 +411,29 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   for (uint32_t b_end = end_all; b_end > rg.x;) {
     const uint32_t b_begin = (b_end - rg.x > (uint32_t)BATCH) ? b_end - BATCH : rg.x;
     const uint32_t cnt = b_end - b_begin;
-    for (uint32_t j = threadIdx.x; j < cnt; j += G::NT) {
+    // two threads per splat share its strip tests (half the wavefronts each)
+    for (uint32_t u = threadIdx.x; u < cnt * kHalves; u += G::NT) {
+      const uint32_t j = u / kHalves, h = u % kHalves;
       const uint32_t id = a.vals[b_begin + j];
       const float4 r0 = a.rec[(size_t)id * 3 + 0], r1 = a.rec[(size_t)id * 3 + 1];
-      s_id[j] = id;
-      s_rec[j * 3 + 0] = r0;
-      s_rec[j * 3 + 1] = halved_conic(r1);
-      s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
+      if (h == 0) {
+        s_id[j] = id;
+        s_rec[j * 3 + 0] = r0;
+        s_rec[j * 3 + 1] = halved_conic(r1);
+        s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
+      }
       // bit 31: the splat's Gaussian is trainable (frozen ones still shape T and S)
-      s_mask[j] = splat_wave_mask<G, SW>(r0, r1, tx * TW, ty * TH) | (id % a.n_gauss < a.n_active ? kActiveBit : 0u);
+      s_mask[u] = splat_strip_mask<G, SW, PPT>(r0, r1, tx * TW, ty * TH, (int)h * G::NWAVES / kHalves,
+                                               ((int)h + 1) * G::NWAVES / kHalves) |
+                  (h == 0 && id % a.n_gauss < a.n_active ? kActiveBit : 0u);
     }
     if (kMultiWave)
       for (uint32_t q = threadIdx.x; q < G::NWAVES * BATCH * 9; q += G::NT) s_g[q] = 0.f;
     __syncthreads();
     for (int j = (int)cnt - 1; j >= 0; --j) {
-      const uint32_t mword = __builtin_amdgcn_readfirstlane(s_mask[j]);
-      if (!((mword >> wave) & 1u)) continue;
+      const uint32_t mword = __builtin_amdgcn_readfirstlane(strip_word<kHalves>(s_mask, (uint32_t)j));
+      const uint32_t qb = (mword >> (wave * PPT)) & ((1u << PPT) - 1u);
+      if (qb == 0u) continue;
       const bool act = (mword & kActiveBit) != 0u;
       const uint32_t pos = b_begin + (uint32_t)j;
       const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1];
@@ -412,6 +444,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       float contrib = 0.f;   // > 0 once the lane took the splat at one of its pixels
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
+        if (!((qb >> q) & 1u)) continue;   // uniform: the splat misses this pixel slot's strip
         const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
         const SplatGeom sg = splat_power(pxc, pyc, r0, r1);
         const bool cand = pos < last[q] && sg.P >= kCutoff;
