@@ -335,6 +335,9 @@ struct BwdArgs {
 //   T_j = T_{j+1} / (1 - alpha_j)
 //   d out / d col_j   = alpha_j T_j
 //   d out / d alpha_j = T_j (col_j - S_j),   S_{j-1} = alpha_j col_j + (1 - alpha_j) S_j
+// Only the projection SG_j = S_j . G of S onto the pixel's upstream gradient
+// G enters the adjoint, so one scalar per pixel is carried back:
+//   d L / d alpha_j = T_j (col_j . G - SG_j),   SG_{j-1} = SG_j + alpha_j (col_j . G - SG_j).
 // The division chain runs in FP32 with the hardware reciprocal: each step adds
 // at most about 4 units of 2^-24 to T_j's relative error (reciprocal, product,
 // and 1 - alpha), which stays inside the same E_p = sum 1/(1 - alpha) bound
@@ -370,7 +373,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   const float unhalve = my_field < 2 ? -2.f : my_field == 3 ? -1.f : my_field < 5 ? -0.5f : 1.f;
   if (threadIdx.x == 0) s_max = rg.x;
   __syncthreads();
-  float G0[PPT], G1[PPT], G2[PPT], S0[PPT], S1[PPT], S2[PPT];
+  float G0[PPT], G1[PPT], G2[PPT], SG[PPT];
   float T[PPT];
   uint32_t last[PPT];
   float lossv = 0.f;
@@ -379,9 +382,6 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   for (int q = 0; q < PPT; ++q) {
     G0[q] = G1[q] = G2[q] = 0.f;
     T[q] = 1.f;
-    S0[q] = a.bg0;
-    S1[q] = a.bg1;
-    S2[q] = a.bg2;
     last[q] = rg.x;
     const int py = py0 + q * G::LROWS;
     if (px < view.width && py < view.height) {
@@ -404,6 +404,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       last[q] = min(max(a.last[view.pix_off + p], rg.x), rg.y);
       my_max = max(my_max, last[q]);
     }
+    SG[q] = fmaf(a.bg2, G2[q], fmaf(a.bg1, G1[q], a.bg0 * G0[q]));   // the background behind all splats
   }
   atomicMax(&s_max, my_max);
   __syncthreads();
@@ -466,12 +467,10 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         g[6] = fmaf(at, G0[q], g[6]);
         g[7] = fmaf(at, G1[q], g[7]);
         g[8] = fmaf(at, G2[q], g[8]);
-        const float d0 = r2.x - S0[q], d1 = r2.y - S1[q], d2 = r2.z - S2[q];
+        const float diff = fmaf(r2.z, G2[q], fmaf(r2.y, G1[q], r2.x * G0[q])) - SG[q];
         // the clamp cuts alpha off from opacity and power
-        const float dLda = (take && !clamped) ? Tj * (d0 * G0[q] + d1 * G1[q] + d2 * G2[q]) : 0.f;
-        S0[q] = fmaf(alt, d0, S0[q]);
-        S1[q] = fmaf(alt, d1, S1[q]);
-        S2[q] = fmaf(alt, d2, S2[q]);
+        const float dLda = (take && !clamped) ? Tj * diff : 0.f;
+        SG[q] = fmaf(alt, diff, SG[q]);
         const float dLdP = dLda * alt;
         g[5] = fmaf(dLda, Gs, g[5]);
         // with the halved conic, fields 0 and 1 collect -1/2 of their sums
