@@ -106,6 +106,13 @@ __device__ __forceinline__ uint32_t splat_strip_mask(const float4& r0, const flo
   return m;
 }
 
+// Largest value over the wavefront's 64 lanes (every lane receives it).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+  return v;
+}
+
 // The strip bits of staged splat j (the halves' words combined).
 template <uint32_t H>
 __device__ __forceinline__ uint32_t strip_word(const uint32_t* m, uint32_t j) {
@@ -407,6 +414,14 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
     SG[q] = fmaf(a.bg2, G2[q], fmaf(a.bg1, G1[q], a.bg0 * G0[q]));   // the background behind all splats
   }
   atomicMax(&s_max, my_max);
+  // per pixel slot, the wavefront's largest last position: list entries at or
+  // past it reach no lane of that slot, so the slot skips them outright
+  uint32_t qlast[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) qlast[q] = __builtin_amdgcn_readfirstlane(wave_max_u32(last[q]));
+  uint32_t wlast = qlast[0];
+#pragma unroll
+  for (int q = 1; q < PPT; ++q) wlast = max(wlast, qlast[q]);
   __syncthreads();
   const uint32_t end_all = s_max;
   for (uint32_t b_end = end_all; b_end > rg.x;) {
@@ -431,7 +446,9 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
     if (kMultiWave)
       for (uint32_t q = threadIdx.x; q < G::NWAVES * BATCH * 9; q += G::NT) s_g[q] = 0.f;
     __syncthreads();
-    for (int j = (int)cnt - 1; j >= 0; --j) {
+    // the wavefront starts at its own last position within the batch
+    const int j_hi = wlast > b_begin ? (int)min(cnt, wlast - b_begin) - 1 : -1;
+    for (int j = j_hi; j >= 0; --j) {
       const uint32_t mword = __builtin_amdgcn_readfirstlane(strip_word<kHalves>(s_mask, (uint32_t)j));
       const uint32_t qb = (mword >> (wave * PPT)) & ((1u << PPT) - 1u);
       if (qb == 0u) continue;
@@ -445,7 +462,9 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       float contrib = 0.f;   // > 0 once the lane took the splat at one of its pixels
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        if (!((qb >> q) & 1u)) continue;   // uniform: the splat misses this pixel slot's strip
+        // uniform: the splat misses this pixel slot's strip, or lies behind
+        // every lane's last composited splat
+        if (!((qb >> q) & 1u) || pos >= qlast[q]) continue;
         const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
         const SplatGeom sg = splat_power(pxc, pyc, r0, r1);
         const bool cand = pos < last[q] && sg.P >= kCutoff;
