@@ -261,9 +261,14 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
     }
     __syncthreads();
     if (live) {
+      // pixel slots whose lanes have all stopped skip the batch (uniform)
+      uint32_t qlive = 0u;
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) qlive |= __ballot(T[q] > 0.f) != 0ull ? 1u << q : 0u;
+      qlive = __builtin_amdgcn_readfirstlane(qlive);
       for (uint32_t j = 0; j < cnt; ++j) {
         const uint32_t qb = (__builtin_amdgcn_readfirstlane(strip_word<kHalves>(s_mask, j)) >> (wave * PPT)) &
-                            ((1u << PPT) - 1u);
+                            qlive;
         if (qb == 0u) continue;
         const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1], r2 = s_rec[j * 3 + 2];
         const uint32_t pos1 = b0 + j + 1;
