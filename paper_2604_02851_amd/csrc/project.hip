@@ -124,7 +124,8 @@ __device__ __forceinline__ void load_gauss(const ParamPtrs& p, int64_t i, Gauss&
   g.qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   g.ok = fin && g.qn > 0.0;
   if (!g.ok) return;
-  const double a = qw / g.qn, b = qx / g.qn, c = qy / g.qn, d = qz / g.qn;
+  const double iqn = 1.0 / g.qn;
+  const double a = qw * iqn, b = qx * iqn, c = qy * iqn, d = qz * iqn;
   g.rho[0] = a; g.rho[1] = b; g.rho[2] = c; g.rho[3] = d;
   double* R = g.Rq;
   R[0] = 1 - 2 * (c * c + d * d); R[1] = 2 * (b * c - a * d);     R[2] = 2 * (b * d + a * c);
@@ -170,15 +171,16 @@ __device__ __forceinline__ bool view_geom(const Gauss& g, const gs_camera& cam, 
   const double fx = cam.fx, fy = cam.fy, z = vg.x[2];
   const double limx = (double)kGuard * (0.5 * (double)cam.width) / fx;
   const double limy = (double)kGuard * (0.5 * (double)cam.height) / fy;
-  double tx = vg.x[0] / z, ty = vg.x[1] / z;
+  const double iz = 1.0 / z;   // one FP64 division per view; the rest multiply by it
+  double tx = vg.x[0] * iz, ty = vg.x[1] * iz;
   vg.clx = tx < -limx || tx > limx;
   vg.cly = ty < -limy || ty > limy;
   tx = fmin(limx, fmax(-limx, tx));
   ty = fmin(limy, fmax(-limy, ty));
-  vg.j00 = fx / z;
-  vg.j02 = -fx * tx / z;
-  vg.j11 = fy / z;
-  vg.j12 = -fy * ty / z;
+  vg.j00 = fx * iz;
+  vg.j02 = -fx * tx * iz;
+  vg.j11 = fy * iz;
+  vg.j12 = -fy * ty * iz;
   const double M00 = vg.M[0], M01 = vg.M[1], M02 = vg.M[2], M11 = vg.M[3], M12 = vg.M[4], M22 = vg.M[5];
   const double s00 = vg.j00 * vg.j00 * M00 + 2.0 * vg.j00 * vg.j02 * M02 + vg.j02 * vg.j02 * M22;
   const double s01 = vg.j00 * vg.j11 * M01 + vg.j00 * vg.j12 * M02 + vg.j02 * vg.j11 * M12 + vg.j02 * vg.j12 * M22;
@@ -187,8 +189,8 @@ __device__ __forceinline__ bool view_geom(const Gauss& g, const gs_camera& cam, 
   vg.B = s01;
   vg.C = s11 + (double)kDilation;
   vg.det = vg.A * vg.C - vg.B * vg.B;
-  vg.u = fx * vg.x[0] / z + (double)cam.cx;
-  vg.w = fy * vg.x[1] / z + (double)cam.cy;
+  vg.u = fx * vg.x[0] * iz + (double)cam.cx;
+  vg.w = fy * vg.x[1] * iz + (double)cam.cy;
   return vg.det > 0.0 && isfinite(vg.det) && isfinite(vg.u) && isfinite(vg.w);
 }
 
@@ -275,9 +277,10 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
           // splat record
           const float uh = (float)vg.u, wh = (float)vg.w;
           const float ul = (float)(vg.u - (double)uh), wl = (float)(vg.w - (double)wh);
+          const double iC = 1.0 / vg.C;
           const float qa = (float)(vg.C / vg.det);
-          const float qr = (float)(-vg.B / vg.C);
-          const float qs = (float)(1.0 / vg.C);
+          const float qr = (float)(-vg.B * iC);
+          const float qs = (float)iC;
           float d[3], len;
           view_dir(cam, g.mu, d, &len);
           float Y[16];
@@ -329,6 +332,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
   g.ok = false;
   // Gaussians visible in no view of the last projection need no set-up
   if (i < na && wave < a.nv && a.seen[i]) load_gauss(a.p, i, g, true);
+  const double iqn = g.ok ? 1.0 / g.qn : 0.0;
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
 #pragma unroll 1
   for (int v = a.v0 + wave; v < a.v0 + a.nv && g.ok; v += kViewWaves) {
@@ -342,7 +346,8 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
     // opacity
     go += gop * (double)g.o * (1.0 - (double)g.o);
     // conic -> screen covariance: dL/dSigma2 = -Q G_Q Q
-    const double qa = vg.C / vg.det, qb = -vg.B / vg.det, qc = vg.A / vg.det;
+    const double idet = 1.0 / vg.det;
+    const double qa = vg.C * idet, qb = -vg.B * idet, qc = vg.A * idet;
     const double S00 = -(qa * qa * ga + qa * qb * gb + qb * qb * gc);
     const double S01 = -(qa * qb * ga + 0.5 * (qb * qb + qa * qc) * gb + qb * qc * gc);
     const double S11 = -(qb * qb * ga + qb * qc * gb + qc * qc * gc);
@@ -362,15 +367,16 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
     const double GJ02 = 2.0 * (S00 * JM0[2] + S01 * JM1[2]);
     const double GJ11 = 2.0 * (S01 * JM0[1] + S11 * JM1[1]);
     const double GJ12 = 2.0 * (S01 * JM0[2] + S11 * JM1[2]);
-    const double fx = cam.fx, fy = cam.fy, z = vg.x[2], z2 = z * z;
+    const double fx = cam.fx, fy = cam.fy, z = vg.x[2];
     double gx[3];
-    gx[0] = gu * fx / z;
-    gx[1] = gw * fy / z;
-    gx[2] = -gu * fx * vg.x[0] / z2 - gw * fy * vg.x[1] / z2 - GJ00 * fx / z2 - GJ11 * fy / z2;
-    if (!vg.clx) { gx[0] += -GJ02 * fx / z2; gx[2] += GJ02 * 2.0 * fx * vg.x[0] / (z2 * z); }
-    else { gx[2] += -GJ02 * j02 / z; }          // j02 = -fx c / z, c fixed
-    if (!vg.cly) { gx[1] += -GJ12 * fy / z2; gx[2] += GJ12 * 2.0 * fy * vg.x[1] / (z2 * z); }
-    else { gx[2] += -GJ12 * j12 / z; }
+    const double iz = 1.0 / z, iz2 = iz * iz, iz3 = iz2 * iz;
+    gx[0] = gu * fx * iz;
+    gx[1] = gw * fy * iz;
+    gx[2] = -(gu * fx * vg.x[0] + gw * fy * vg.x[1] + GJ00 * fx + GJ11 * fy) * iz2;
+    if (!vg.clx) { gx[0] += -GJ02 * fx * iz2; gx[2] += GJ02 * 2.0 * fx * vg.x[0] * iz3; }
+    else { gx[2] += -GJ02 * j02 * iz; }          // j02 = -fx c / z, c fixed
+    if (!vg.cly) { gx[1] += -GJ12 * fy * iz2; gx[2] += GJ12 * 2.0 * fy * vg.x[1] * iz3; }
+    else { gx[2] += -GJ12 * j12 * iz; }
     // x = W mu + t ;  M = W Sigma W^T
     double W[9];
     for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
@@ -404,7 +410,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
     gr[3] = 2 * (-2 * z_ * GR[0] - w_ * GR[1] + x_ * GR[2] + w_ * GR[3] - 2 * z_ * GR[4] + y_ * GR[5] +
                  x_ * GR[6] + y_ * GR[7]);
     const double dot = w_ * gr[0] + x_ * gr[1] + y_ * gr[2] + z_ * gr[3];
-    for (int k = 0; k < 4; ++k) gq[k] += (gr[k] - g.rho[k] * dot) / g.qn;
+    for (int k = 0; k < 4; ++k) gq[k] += (gr[k] - g.rho[k] * dot) * iqn;
   }
   // sum over the wavefronts: waves 1.. park their partial sums in LDS
   float part[kOut];
