@@ -145,7 +145,7 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   L.partial = take(4 * L.partial_len);
   L.ranges = take(8 * tiles);
   L.last = take(4 * pixels);
-  L.seen = take(n);
+  L.vmask = take(8 * n);
   L.dflags = take(n);
   L.dcount = take(4 * (6ll * L.dblocks + 1));
   L.dbase = take(4 * 16);

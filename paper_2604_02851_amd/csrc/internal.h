@@ -58,7 +58,8 @@ struct WsLayout {
   size_t partial;     // u32 [scan partials]
   size_t ranges;      // u32x2 [tiles]
   size_t last;        // u32 [pixels]
-  size_t seen;        // u8 [n] Gaussian visible in some view of the last projection call
+  size_t vmask;       // u64 [n] views of the last projection call that see the Gaussian
+                      // (bit v - v0 when the call has at most 64 views, else all ones)
   size_t dflags;      // u8 [n] delta flags
   size_t dcount;      // u32 [6 * dblocks + 1] delta block counts (scanned in place)
   size_t dbase;       // u32 [16] delta section bases

@@ -211,14 +211,14 @@ struct ProjArgs {
   uint32_t* count;
   ushort4* rect;
   float4* rec;
-  uint8_t* seen;             // per Gaussian: visible in some view of this call
+  uint64_t* vmask;           // per Gaussian: the views of this call that see it
   const uint32_t* cell_of;   // preculling (null = off)
   const uint8_t* cell_mask;
   int32_t cell_row;
 };
 
-constexpr int kViewWaves = 1;   // (the per-Gaussian "seen" flag assumes a single wavefront per Gaussian)
-static_assert(kViewWaves == 1, "one wavefront writes a Gaussian's seen flag");
+constexpr int kViewWaves = 1;   // (the per-Gaussian view mask assumes a single wavefront per Gaussian)
+static_assert(kViewWaves == 1, "one wavefront writes a Gaussian's view mask");
 
 template <int DEG>
 __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
     for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) any |= a.cell_mask[(int64_t)v * a.cell_row + cell] != 0;
     if (!any) {
       for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) a.count[(int64_t)v * n + i] = 0u;
-      a.seen[i] = 0;
+      a.vmask[i] = 0ull;
       return;
     }
   }
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
   }
   Gauss g;
   load_gauss(a.p, i, g, sh_ok);
-  bool seen = false;
+  uint64_t vm = 0ull;
 #pragma unroll 1
   for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) {
     const int64_t o = (int64_t)v * n + i;
@@ -300,9 +300,49 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
       }
     }
     a.count[o] = cnt;
-    seen |= cnt != 0u;
+    if (cnt != 0u) vm |= a.nv <= 64 ? 1ull << (v - a.v0) : ~0ull;
   }
-  a.seen[i] = seen ? 1 : 0;
+  a.vmask[i] = vm;
+}
+
+// OR of a 64-bit value over the wavefront's lanes (every lane receives it).
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo |= (uint32_t)__shfl_xor((int)lo, off, 64);
+    hi |= (uint32_t)__shfl_xor((int)hi, off, 64);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Runs body(v, o) for the views v of the call that see this lane's Gaussian
+// (vm from the projection).  With at most 64 views the wavefront walks the
+// union of its lanes' masks (uniform) and a lane takes the views of its own
+// mask, with no per-view memory traffic; with more views every view's count
+// is read as the mask cannot hold them.
+template <class F>
+__device__ __forceinline__ void for_seen_views(int v0, int nv, int64_t n, int64_t i, uint64_t vm, const uint32_t* count,
+                                               F&& body) {
+  if (nv <= 64) {
+    const uint64_t any = wave_or_u64(vm);
+    const uint64_t wm = (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)any) |
+                        ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(any >> 32)) << 32);
+#pragma unroll 1
+    for (uint64_t m = wm; m != 0ull; m &= m - 1ull) {
+      const int vi = __builtin_ctzll(m);
+      if (!((vm >> vi) & 1ull)) continue;
+      const int v = v0 + vi;
+      body(v, (int64_t)v * n + i);
+    }
+  } else {
+#pragma unroll 1
+    for (int v = v0; v < v0 + nv; ++v) {
+      const int64_t o = (int64_t)v * n + i;
+      if (vm == 0ull || count[o] == 0u) continue;
+      body(v, o);
+    }
+  }
 }
 
 struct ProjBwdArgs {
@@ -310,7 +350,7 @@ struct ProjBwdArgs {
   const gs_camera* cams;
   int v0, nv;
   const uint32_t* count;
-  const uint8_t* seen;
+  const uint64_t* vmask;
   const float4* g2;
   float4* g2z;   // the same slots, cleared by k_color_bwd after reading
   float* gmean; float* glsc; float* gquat; float* gopac; float* gsh;
@@ -331,13 +371,11 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
   Gauss g;
   g.ok = false;
   // Gaussians visible in no view of the last projection need no set-up
-  if (i < na && wave < a.nv && a.seen[i]) load_gauss(a.p, i, g, true);
+  const uint64_t vm = (i < na && wave < a.nv) ? a.vmask[i] : 0ull;
+  if (vm != 0ull) load_gauss(a.p, i, g, true);
   const double iqn = g.ok ? 1.0 / g.qn : 0.0;
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
-#pragma unroll 1
-  for (int v = a.v0 + wave; v < a.v0 + a.nv && g.ok; v += kViewWaves) {
-    const int64_t o = (int64_t)v * n + i;
-    if (a.count[o] == 0) continue;
+  for_seen_views(a.v0, a.nv, n, i, g.ok ? vm : 0ull, a.count, [&](int v, int64_t o) {
     const float4 t0 = a.g2[o * 3 + 0], t1 = a.g2[o * 3 + 1];
     const double gu = t0.x, gw = t0.y, ga = t0.z, gb = t0.w, gc = t1.x, gop = t1.y;
     const gs_camera cam = a.cams[v];
@@ -411,7 +449,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
                  x_ * GR[6] + y_ * GR[7]);
     const double dot = w_ * gr[0] + x_ * gr[1] + y_ * gr[2] + z_ * gr[3];
     for (int k = 0; k < 4; ++k) gq[k] += (gr[k] - g.rho[k] * dot) * iqn;
-  }
+  });
   // sum over the wavefronts: waves 1.. park their partial sums in LDS
   float part[kOut];
 #pragma unroll
@@ -455,16 +493,17 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
 #pragma unroll
   for (int k = 0; k < kOut; ++k) part[k] = 0.f;
   __shared__ float s_sh[kViewWaves][3 * nk][64];   // per-lane columns: no barrier needed
-  if (i < na && wave < a.nv && a.seen[i]) {
+  const uint64_t vm = (i < na && wave < a.nv) ? a.vmask[i] : 0ull;
+  {
     float* sh_col = &s_sh[wave][0][lane];
+    float mu[3] = {0.f, 0.f, 0.f};
+    if (vm != 0ull) {
 #pragma unroll
-    for (int k = 0; k < 3 * nk; ++k) sh_col[k * 64] = a.p.sh[(int64_t)k * n + i];
+      for (int k = 0; k < 3 * nk; ++k) sh_col[k * 64] = a.p.sh[(int64_t)k * n + i];
+      mu[0] = a.p.mean[i], mu[1] = a.p.mean[n + i], mu[2] = a.p.mean[2 * n + i];
+    }
 #define SH(k) sh_col[(k) * 64]
-    const float mu[3] = {a.p.mean[i], a.p.mean[n + i], a.p.mean[2 * n + i]};
-#pragma unroll 1
-    for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) {
-      const int64_t o = (int64_t)v * n + i;
-      if (a.count[o] == 0) continue;
+    for_seen_views(a.v0, a.nv, n, i, vm, a.count, [&](int v, int64_t o) {
       const float* g2 = reinterpret_cast<const float*>(a.g2) + o * kG2Stride;
       const float gcol[3] = {g2[6], g2[7], g2[8]};
       static_assert(kG2Stride == 12, "three float4 slots per pair");
@@ -493,7 +532,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
       sh_grad_accum(DEG, d[0], d[1], d[2], wk, gd);
       const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
       for (int k = 0; k < 3; ++k) part[k] += (gd[k] - d[k] * dd) / len;
-    }
+    });
 #undef SH
   }
   if (wave > 0) {
@@ -530,7 +569,7 @@ hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* c
   a.count = seg<uint32_t>(ws, pl.ws.count);
   a.rect = seg<ushort4>(ws, pl.ws.rect);
   a.rec = seg<float4>(ws, pl.ws.rec);
-  a.seen = seg<uint8_t>(ws, pl.ws.seen);
+  a.vmask = seg<uint64_t>(ws, pl.ws.vmask);
   a.cell_of = pl.cell_of;
   a.cell_mask = pl.cell_mask;
   a.cell_row = pl.cell_row;
@@ -555,7 +594,7 @@ hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camer
   a.v0 = v0;
   a.nv = nv;
   a.count = seg<uint32_t>(ws, pl.ws.count);
-  a.seen = seg<uint8_t>(ws, pl.ws.seen);
+  a.vmask = seg<uint64_t>(ws, pl.ws.vmask);
   a.g2 = seg<float4>(ws, pl.ws.g2);
   a.g2z = seg<float4>(ws, pl.ws.g2);
   a.gmean = grads.mean;
