@@ -260,16 +260,25 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
                                                ((int)h + 1) * G::NWAVES / kHalves);
     }
     __syncthreads();
-    if (live) {
+    // uniform: the splat walk below needs every lane (lane l reads splat
+    // base + l's strip word); lanes that stopped take nothing, as their T < 0
+    if (__ballot(live) != 0ull) {
       // pixel slots whose lanes have all stopped skip the batch (uniform)
       uint32_t qlive = 0u;
 #pragma unroll
       for (int q = 0; q < PPT; ++q) qlive |= __ballot(T[q] > 0.f) != 0ull ? 1u << q : 0u;
       qlive = __builtin_amdgcn_readfirstlane(qlive);
-      for (uint32_t j = 0; j < cnt; ++j) {
-        const uint32_t qb = (__builtin_amdgcn_readfirstlane(strip_word<kHalves>(s_mask, j)) >> (wave * PPT)) &
-                            qlive;
-        if (qb == 0u) continue;
+      // 64 splats at a time: lane l reads the strip word of splat base + l, and
+      // the wavefront then visits only the splats that touch one of its live strips
+      for (uint32_t base = 0; base < cnt; base += 64) {
+       const uint32_t jl = base + (uint32_t)lane;
+       const uint32_t mw = jl < cnt ? strip_word<kHalves>(s_mask, jl) : 0u;
+       uint64_t pend = __ballot(((mw >> (wave * PPT)) & qlive) != 0u);
+       while (pend != 0ull) {
+        const int l = __builtin_ctzll(pend);
+        pend &= pend - 1ull;
+        const uint32_t j = base + (uint32_t)l;
+        const uint32_t qb = ((uint32_t)__builtin_amdgcn_readlane((int)mw, l) >> (wave * PPT)) & qlive;
         const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1], r2 = s_rec[j * 3 + 2];
         const uint32_t pos1 = b0 + j + 1;
 #pragma unroll
@@ -294,6 +303,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
           n[q] += comp ? 1u : 0u;
           last[q] = comp ? pos1 : last[q];
         }
+       }
       }
       live = false;
 #pragma unroll
@@ -453,10 +463,18 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
     __syncthreads();
     // the wavefront starts at its own last position within the batch
     const int j_hi = wlast > b_begin ? (int)min(cnt, wlast - b_begin) - 1 : -1;
-    for (int j = j_hi; j >= 0; --j) {
-      const uint32_t mword = __builtin_amdgcn_readfirstlane(strip_word<kHalves>(s_mask, (uint32_t)j));
+    // 64 splats at a time: lane l reads the strip word of splat base - l, and
+    // the wavefront then visits only the splats that touch one of its strips
+    for (int base = j_hi; base >= 0; base -= 64) {
+     const int jl = base - lane;
+     const uint32_t mw = jl >= 0 ? strip_word<kHalves>(s_mask, (uint32_t)jl) : 0u;
+     uint64_t pend = __ballot(((mw >> (wave * PPT)) & ((1u << PPT) - 1u)) != 0u);
+     while (pend != 0ull) {
+      const int l = __builtin_ctzll(pend);
+      pend &= pend - 1ull;
+      const int j = base - l;
+      const uint32_t mword = (uint32_t)__builtin_amdgcn_readlane((int)mw, l);
       const uint32_t qb = (mword >> (wave * PPT)) & ((1u << PPT) - 1u);
-      if (qb == 0u) continue;
       const bool act = (mword & kActiveBit) != 0u;
       const uint32_t pos = b_begin + (uint32_t)j;
       const float4 r0 = s_rec[j * 3], r1 = s_rec[j * 3 + 1];
@@ -520,6 +538,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         if (writer && tot8 != 0.f) atomicAdd(dst + my_field, tot8);
         if (lane == 63 && tot9 != 0.f) atomicAdd(dst + 8, tot9);
       }
+     }
     }
     __syncthreads();
     if (kMultiWave) {
