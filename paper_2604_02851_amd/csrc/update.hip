@@ -25,6 +25,7 @@ struct AdamArgs {
   float beta1, beta2, eps;
 };
 
+typedef float V4 __attribute__((ext_vector_type(4)));
 constexpr int kAdamVec = 4;                    // elements per thread
 constexpr int kAdamChunk = 256 * kAdamVec;     // elements per workgroup
 
@@ -67,17 +68,21 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
                    ((reinterpret_cast<uintptr_t>(th_p) | reinterpret_cast<uintptr_t>(g_p) |
                      reinterpret_cast<uintptr_t>(m_p) | reinterpret_cast<uintptr_t>(v_p)) & 15u) == 0;
   if (vec) {
-    float4 th = *reinterpret_cast<const float4*>(th_p);
-    const float4 g = *reinterpret_cast<const float4*>(g_p);
-    float4 m = *reinterpret_cast<const float4*>(m_p);
-    float4 v = *reinterpret_cast<const float4*>(v_p);
-    adam_one(th.x, g.x, m.x, v.x, b1, b2, c1, c2, step, rbc2, eps);
-    adam_one(th.y, g.y, m.y, v.y, b1, b2, c1, c2, step, rbc2, eps);
-    adam_one(th.z, g.z, m.z, v.z, b1, b2, c1, c2, step, rbc2, eps);
-    adam_one(th.w, g.w, m.w, v.w, b1, b2, c1, c2, step, rbc2, eps);
-    *reinterpret_cast<float4*>(m_p) = m;
-    *reinterpret_cast<float4*>(v_p) = v;
-    *reinterpret_cast<float4*>(th_p) = th;
+    // every value is touched once per step: streaming (non-temporal) accesses
+    // keep the update from evicting what the other stages reuse
+    V4 th = __builtin_nontemporal_load(reinterpret_cast<const V4*>(th_p));
+    const V4 g = __builtin_nontemporal_load(reinterpret_cast<const V4*>(g_p));
+    V4 m = __builtin_nontemporal_load(reinterpret_cast<const V4*>(m_p));
+    V4 v = __builtin_nontemporal_load(reinterpret_cast<const V4*>(v_p));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float t = th[c], mc = m[c], vc = v[c];
+      adam_one(t, g[c], mc, vc, b1, b2, c1, c2, step, rbc2, eps);
+      th[c] = t, m[c] = mc, v[c] = vc;
+    }
+    __builtin_nontemporal_store(m, reinterpret_cast<V4*>(m_p));
+    __builtin_nontemporal_store(v, reinterpret_cast<V4*>(v_p));
+    __builtin_nontemporal_store(th, reinterpret_cast<V4*>(th_p));
   } else {
     for (int c = 0; c < kAdamVec && k0 + c < a.n_active; ++c) {
       float th = th_p[c], m = m_p[c], v = v_p[c];
