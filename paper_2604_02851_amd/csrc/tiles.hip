@@ -313,9 +313,18 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
 #pragma unroll
   for (int r = 0; r < kWaveRounds; ++r) {
     const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
-    key[r] = li < cnt ? kin[begin + li] : 0u;
-    val[r] = li < cnt ? vin[begin + li] : 0u;
-    if constexpr (kPay) pay[r] = li < cnt ? pin[begin + li] : make_uint2(0u, 0u);
+    // each pass reads its input once: streaming loads leave the cache to the
+    // histogram, the offsets and the output being assembled
+    key[r] = li < cnt ? __builtin_nontemporal_load(kin + begin + li) : 0u;
+    val[r] = li < cnt ? __builtin_nontemporal_load(vin + begin + li) : 0u;
+    if constexpr (kPay) {
+      if (li < cnt) {
+        const uint32_t* pp = reinterpret_cast<const uint32_t*>(pin + begin + li);
+        pay[r] = make_uint2(__builtin_nontemporal_load(pp), __builtin_nontemporal_load(pp + 1));
+      } else {
+        pay[r] = make_uint2(0u, 0u);
+      }
+    }
   }
   __syncthreads();
   // 1. stable ranks within (wavefront, digit)
