@@ -112,13 +112,13 @@ __device__ __forceinline__ void load_gauss(const ParamPtrs& p, int64_t i, Gauss&
   const int64_t n = p.n;
   bool fin = true;
   for (int k = 0; k < 3; ++k) {
-    g.mu[k] = p.mean[k * n + i];
+    g.mu[k] = __builtin_nontemporal_load(p.mean + k * n + i);
     fin &= isfinite(g.mu[k]);
   }
   float ls[3], q[4];
-  for (int k = 0; k < 3; ++k) { ls[k] = p.lsc[k * n + i]; fin &= isfinite(ls[k]); }
-  for (int k = 0; k < 4; ++k) { q[k] = p.quat[k * n + i]; fin &= isfinite(q[k]); }
-  const float w = p.opac[i];
+  for (int k = 0; k < 3; ++k) { ls[k] = __builtin_nontemporal_load(p.lsc + k * n + i); fin &= isfinite(ls[k]); }
+  for (int k = 0; k < 4; ++k) { q[k] = __builtin_nontemporal_load(p.quat + k * n + i); fin &= isfinite(q[k]); }
+  const float w = __builtin_nontemporal_load(p.opac + i);
   fin &= isfinite(w) && sh_finite;
   const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
   g.qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
   bool sh_ok = true;
 #pragma unroll
   for (int k = 0; k < 3 * nk; ++k) {
-    const float c = a.p.sh[(int64_t)k * n + i];
+    const float c = __builtin_nontemporal_load(a.p.sh + (int64_t)k * n + i);
     sh_ok &= isfinite(c);
     s_sh[wave][k][lane] = c;
   }

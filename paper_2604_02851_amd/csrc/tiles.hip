@@ -227,8 +227,9 @@ __global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* count, 
   if (count[base + k] != 0u) {
     const uint32_t p = pos[k];
     vis_ids[p] = (uint32_t)(base + k);
-    vis_keys[p] = depth[base + k];
-    vis_rect[p] = rect[base + k];
+    vis_keys[p] = __builtin_nontemporal_load(depth + base + k);
+    const uint32_t* rp = reinterpret_cast<const uint32_t*>(rect + base + k);
+    vis_rect[p] = make_uint2(__builtin_nontemporal_load(rp), __builtin_nontemporal_load(rp + 1));
   }
 }
 
@@ -523,7 +524,8 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys, const uint
     const uint32_t k0 = qd * 4u;
     uint32_t t[6];
     if (aligned && k0 + 4u <= n) {
-      const uint4 x = *reinterpret_cast<const uint4*>(keys + k0);
+      typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+      const U4 x = __builtin_nontemporal_load(reinterpret_cast<const U4*>(keys + k0));
       t[1] = x.x, t[2] = x.y, t[3] = x.z, t[4] = x.w;
     } else {
 #pragma unroll
