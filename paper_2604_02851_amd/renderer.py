@@ -313,8 +313,8 @@ class Optimizer:
 # (tile, batch depth, pixels per thread, wave sub-tile width, tile schedule)
 TUNE_CANDIDATES = [((16, 16), 64, 2, 16, 0), ((16, 16), 64, 4, 16, 0), ((32, 16), 128, 4, 32, 0),
                    ((32, 16), 128, 4, 16, 0), ((32, 32), 64, 4, 32, 0), ((32, 32), 128, 4, 32, 0),
-                   ((32, 32), 128, 2, 16, 0), ((32, 32), 128, 4, 16, 0), ((32, 32), 128, 4, 32, 1),
-                   ((32, 32), 128, 4, 16, 1)]
+                   ((32, 32), 128, 2, 16, 0), ((32, 32), 128, 4, 16, 0), ((32, 32), 64, 4, 16, 0),
+                   ((32, 32), 128, 4, 32, 1), ((32, 32), 128, 4, 16, 1)]
 SHAPE_KEYS = ("tile", "batch_depth", "pixels_per_thread", "wave_w", "schedule")
 
 
