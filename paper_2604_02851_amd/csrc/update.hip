@@ -201,8 +201,9 @@ __global__ void k_delta_header(DeltaArgs a) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   uint32_t run = (uint32_t)a.hdr;
   for (int g = 0; g < 6; ++g) {
-    const uint32_t lo = a.bcount[(int64_t)g * a.nb];
-    const uint32_t hi = g < 5 ? a.bcount[(int64_t)(g + 1) * a.nb] : a.dbase[15];
+    // (no Gaussians: no block counts were written, every group is empty)
+    const uint32_t lo = a.nb > 0 ? a.bcount[(int64_t)g * a.nb] : 0u;
+    const uint32_t hi = a.nb > 0 ? (g < 5 ? a.bcount[(int64_t)(g + 1) * a.nb] : a.dbase[15]) : 0u;
     const uint32_t c = hi - lo;
     a.dbase[g] = run;
     a.dbase[6 + g] = c;

@@ -4,7 +4,7 @@ and updated baselines bit-exact against the oracle (every codec mode, 8- and
 group masks, the full 3M-Gaussian model after drift); the receiver's replay
 bit-exact against the oracle's and equal to the sender's baseline after
 every packet of a scheduled stream with a snapshot in between; stale and
-malformed packets rejected whole."""
+malformed packets rejected whole; empty group masks and empty models."""
 import numpy as np
 import pytest
 import torch
@@ -182,3 +182,39 @@ def test_invalid_codecs_are_refused():
             r.ctx.delta_encode(P, P.clone(), (bad,) + ST.DEFAULT_CODECS[1:], 0x3F, epoch, out, r.ws)
     with pytest.raises(N.GsError):
         r.ctx.delta_encode(P, P.clone(), ST.DEFAULT_CODECS, 0x3F, epoch, out[:8], r.ws)   # capacity
+
+
+def test_empty_mask_and_empty_model(oracle):
+    """A packet with no groups is the header alone and replays as a no-op; a
+    model of zero Gaussians encodes and replays too."""
+    codecs = ST.DEFAULT_CODECS
+    w, r = _setup(300, 2, 6)
+    cur_h = _drift(w.scene, np.random.default_rng(1), 0.05)
+    cur, base = DeviceParams.from_scene(cur_h), DeviceParams.from_scene(w.scene)
+    epoch = torch.tensor([3], dtype=torch.int32, device="cuda")
+    out = torch.zeros(N.codec_capacity_words(300, 2, codecs, 0), dtype=torch.int32, device="cuda")
+    assert out.numel() == 9
+    r.ctx.delta_encode(cur, base, codecs, 0, epoch, out, r.ws)
+    torch.cuda.synchronize()
+    ref = oracle.delta_encode(cur_h, w.scene.copy(), codecs, 0, epoch=3)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
+    assert _same(_host(base), w.scene)                       # nothing sent, nothing changed
+    model = DeviceParams.from_scene(w.scene)
+    status = torch.full((1,), 9, dtype=torch.int32, device="cuda")
+    r.ctx.delta_apply(model, codecs, out, 9, epoch, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0 and _same(_host(model), w.scene)
+    # zero Gaussians
+    w0, r0 = _setup(0, 1, 7)
+    e0 = DeviceParams.from_scene(w0.scene)
+    out0 = torch.zeros(N.codec_capacity_words(0, 1, codecs), dtype=torch.int32, device="cuda")
+    r0.ctx.delta_encode(e0, e0.clone(), codecs, 0x3F, epoch, out0, r0.ws)
+    torch.cuda.synchronize()
+    assert out0.cpu().numpy().view(np.uint32).tolist() == [3, 0x3F, 0, 0, 0, 0, 0, 0, 9]
+    r0.ctx.delta_apply(e0, codecs, out0, 9, epoch, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    raw0 = torch.full((N.delta_capacity_words(0, 1),), 5, dtype=torch.int32, device="cuda")
+    r0.ctx.delta_extract(e0, e0.clone(), 0x3F, 1e-3, raw0, r0.ws)
+    torch.cuda.synchronize()
+    assert raw0.cpu().numpy().tolist() == [0] * 6
