@@ -372,7 +372,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   __shared__ float4 s_rec[BATCH * 3];
   __shared__ uint32_t s_mask[BATCH * kHalves];
   __shared__ uint32_t s_id[BATCH];
-  __shared__ float s_g[kMultiWave ? G::NWAVES * BATCH * 9 : 1];   // per-wavefront splat sums of a batch
+  __shared__ float s_g[kMultiWave ? BATCH * 9 : 1];   // the batch's splat sums over the tile's wavefronts
   __shared__ uint32_t s_max;
   const uint32_t slot = tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule);
   const int t = a.tile_begin + (int)slot;
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
                   (h == 0 && id % a.n_gauss < a.n_active ? kActiveBit : 0u);
     }
     if (kMultiWave)
-      for (uint32_t q = threadIdx.x; q < G::NWAVES * BATCH * 9; q += G::NT) s_g[q] = 0.f;
+      for (uint32_t q = threadIdx.x; q < cnt * 9; q += G::NT) s_g[q] = 0.f;
     __syncthreads();
     // the wavefront starts at its own last position within the batch
     const int j_hi = wlast > b_begin ? (int)min(cnt, wlast - b_begin) - 1 : -1;
@@ -530,9 +530,10 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
       const float tot8 = reduce8(g, lo8) * unhalve;
       const float tot9 = wave_total_lane63(g[8]);
       if (kMultiWave) {
-        float* dst = s_g + (wave * BATCH + j) * 9;
-        if (writer) dst[my_field] = tot8;
-        if (lane == 63) dst[8] = tot9;
+        // LDS float adds: one slot per (splat, field) for all wavefronts
+        float* dst = s_g + j * 9;
+        if (writer && tot8 != 0.f) atomicAdd(dst + my_field, tot8);
+        if (lane == 63 && tot9 != 0.f) atomicAdd(dst + 8, tot9);
       } else {
         float* dst = a.g2 + (size_t)s_id[j] * kG2Stride;
         if (writer && tot8 != 0.f) atomicAdd(dst + my_field, tot8);
@@ -543,9 +544,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
     __syncthreads();
     if (kMultiWave) {
       for (uint32_t q = threadIdx.x; q < cnt * 9; q += G::NT) {
-        float v = 0.f;
-#pragma unroll
-        for (int w = 0; w < G::NWAVES; ++w) v += s_g[w * BATCH * 9 + q];
+        const float v = s_g[q];
         if (v != 0.f) atomicAdd(&a.g2[(size_t)s_id[q / 9] * kG2Stride + (q % 9)], v);
       }
       __syncthreads();
