@@ -1,8 +1,10 @@
 """Parity at the configured sizes, through the C ABI in the benchmark's launch
 configuration: cfg2 in full (autograd Function, oracle gradient and FP64
-finite differences), cfg3 / cfg4 on sampled rows of every view plus a full
-gradient check on two views, cfg5 delta extraction bit-exact at 3M Gaussians
-after scene dynamics and a GPU step, and graph replay against eager steps."""
+finite differences), cfg3 / cfg4 on sampled rows of every view, a full
+gradient check on two views of cfg3, the 16-view batched cfg4 backward
+against the oracle's gradient of the three views it is given gradients on,
+cfg5 delta extraction bit-exact at 3M Gaussians after scene dynamics and a
+GPU step, and graph replay against eager steps."""
 import numpy as np
 import pytest
 import torch
@@ -143,6 +145,30 @@ def test_config4_sampled_rows(oracle):
     torch.cuda.synchronize()
     n = _rows_check(oracle, w, img.cpu().numpy(), rows_per_view=4)
     print("cfg4 pixels checked", n)
+
+
+def test_config4_batched_gradient_three_views(oracle):
+    """The 16-view batched backward of the 1M-Gaussian workload, the call the
+    benchmark step makes, with an upstream gradient that is zero outside views
+    3-5 (640x360 each): every other view then adds exact zeros, so the whole
+    gradient must equal the oracle's gradient over those three views."""
+    w = S.workload(4)
+    assert list(w.cams["width"][3:6]) == [640] * 3 and list(w.cams["height"][3:6]) == [360] * 3
+    P = DeviceParams.from_scene(w.scene)
+    r = _renderer(w)
+    r.fit_capacity(P)
+    off = oracle.pixel_offsets(w.cams)
+    lo, hi = 3 * int(off[3]), 3 * int(off[6])
+    G = np.zeros(3 * w.n_pixels, F32)
+    G[lo:hi] = np.random.default_rng(44).normal(size=hi - lo).astype(F32)
+    r.forward(P)
+    grads = DeviceParams.zeros_like(P)
+    r.backward(P, torch.from_numpy(G).cuda(), 0, grads)
+    torch.cuda.synchronize()
+    b = oracle.backward(w.scene, w.cams[3:6], G[lo:hi], mode=0)
+    rep = grad_report(flat_grads(grads), b)
+    print("cfg4 batched gradient (views 3-5 nonzero)", rep)
+    assert rep["fail"] == 0
 
 
 def test_config5_delta_after_dynamics_and_step(oracle):
