@@ -1,7 +1,8 @@
 """Parity at the configured sizes, through the C ABI in the benchmark's launch
 configuration: cfg2 in full (autograd Function, oracle gradient and FP64
 finite differences), cfg3 / cfg4 on sampled rows of every view, a full
-gradient check on two views of cfg3, the 16-view batched cfg4 backward
+gradient check on two views of cfg3, cfg4 tile lists of three views
+bit-exact inside the 16-view batched call, the 16-view batched cfg4 backward
 against the oracle's gradient of the three views it is given gradients on,
 Adam over the whole cfg4 model on every element, cfg5 delta extraction
 bit-exact at 3M Gaussians after scene dynamics and a GPU step, and graph
@@ -10,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import EPS_ACC, EPS_T, compare_images, flat_grads, grad_report
+from gpu_util import EPS_ACC, EPS_T, compare_images, flat_grads, grad_report, seg_np
 from paper_2604_02851_amd import scenes as S
 from paper_2604_02851_amd.native import DeviceParams
 from paper_2604_02851_amd.renderer import GaussianRasterize, Optimizer, Renderer
@@ -146,6 +147,36 @@ def test_config4_sampled_rows(oracle):
     torch.cuda.synchronize()
     n = _rows_check(oracle, w, img.cpu().numpy(), rows_per_view=4)
     print("cfg4 pixels checked", n)
+
+
+def test_config4_tile_lists_three_views(oracle):
+    """Tile lists of the 16-view batched cfg4 call (60M keys, 32x32 tiles)
+    bit-exact for views 3-5: they are the contiguous run of the global tile
+    range that belongs to those views, so they equal the oracle's lists of
+    the three views alone, with view indices shifted by 3 and list positions
+    by the start of the run."""
+    w = S.workload(4)
+    P = DeviceParams.from_scene(w.scene)
+    r = _renderer(w)
+    r.fit_capacity(P)
+    r.forward(P)
+    c = r.counters()
+    assert c.overflow == 0 and c.keys > 50_000_000
+    tw, th = BENCH_SHAPE["tile"]
+    vals_o, ranges_o = oracle.tile_lists(w.scene, w.cams[3:6], tw, th)
+    base = oracle.tile_layout(w.cams, tw, th)
+    t0, t1 = int(base[3]), int(base[6])
+    ranges = seg_np(r, "ranges", np.uint32).reshape(-1, 2)[t0:t1].astype(np.int64)
+    assert ranges.shape == ranges_o.shape
+    empty_o = ranges_o[:, 0] == ranges_o[:, 1]
+    assert np.array_equal(ranges[:, 0] == ranges[:, 1], empty_o)
+    assert (~empty_o).any()
+    off = int(ranges[~empty_o, 0].min())
+    assert np.array_equal(ranges[~empty_o] - off, ranges_o[~empty_o].astype(np.int64))
+    vals = seg_np(r, "sorted_values", np.uint32)[off:off + len(vals_o)]
+    n = w.scene.n
+    assert np.array_equal(vals, vals_o + np.uint32(3 * n))
+    print("cfg4 tile lists of views 3-5:", len(vals_o), "keys of", c.keys)
 
 
 def test_config4_batched_gradient_three_views(oracle):
