@@ -1,6 +1,6 @@
 """Parity at the configured sizes, through the C ABI in the benchmark's launch
 configuration: cfg2 in full (autograd Function, oracle gradient and FP64
-finite differences), cfg3 / cfg4 on sampled rows of every view, a full
+finite differences), cfg3 / cfg4 / cfg5 on sampled rows of every view, a full
 gradient check on two views of cfg3, cfg4 tile lists of three views
 bit-exact inside the 16-view batched call, the 16-view batched cfg4 backward
 against the oracle's gradient of the three views it is given gradients on,
@@ -147,6 +147,21 @@ def test_config4_sampled_rows(oracle):
     torch.cuda.synchronize()
     n = _rows_check(oracle, w, img.cpu().numpy(), rows_per_view=4)
     print("cfg4 pixels checked", n)
+
+
+def test_config5_sampled_rows(oracle):
+    """The 3M-Gaussian model over four 1920x1080 views (the densest overlap
+    of the workloads) in the benchmark's launch shape: rows from the top,
+    middle and bottom of every view against the oracle."""
+    w = S.workload(5)
+    P = DeviceParams.from_scene(w.scene)
+    r = _renderer(w)
+    r.fit_capacity(P)
+    img = r.forward(P)[0]
+    torch.cuda.synchronize()
+    assert r.counters().overflow == 0
+    n = _rows_check(oracle, w, img.cpu().numpy(), rows_per_view=4)
+    print("cfg5 pixels checked", n)
 
 
 def test_config4_tile_lists_three_views(oracle):
