@@ -89,3 +89,28 @@ def grad_report(g_gpu: np.ndarray, b, rel=GRAD_REL, floor=GRAD_ABS):
                                    if (np.abs(b.grad) > 1e-2).any() else 0.0),
         "worst_idx": np.unravel_index(int(np.argmax(err / tol)), err.shape),
     }
+
+
+def adam_check(oracle, theta0, g0, m0, v0, out_t, out_m, out_v, lr, b1, b2, eps, step):
+    """Checks one Adam step of the library against the oracle's FP64 step on
+    every element and returns the worst error / bound.  The hyperparameters
+    reach the library as FP32 numbers, so the oracle gets the same rounded
+    values.  Bounds, with u = 2^-24 and d = theta - theta' (oracle):
+      m': 4u (beta1 |m| + (1 - beta1) |g|)    (a product, a fused add)
+      v': 4u |v'|                             (a sum of non-negative terms)
+      theta': 2u |theta'| + 16u |d| + 4u (|d| / |m'|) (beta1 |m| + (1 - beta1) |g|)
+    (the final subtraction, the roundings of the update's own chain, and the
+    rounding of m' carried through the update's factor d / m')."""
+    f32 = lambda x: float(np.float32(x))
+    u = 2.0 ** -24
+    th, mo, vo = oracle.adam(theta0, g0, m0, v0, f32(lr), f32(b1), f32(b2), f32(eps), step)
+    mg = f32(b1) * np.abs(m0) + (1 - f32(b1)) * np.abs(g0)
+    assert (mo != 0).all()
+    d = np.abs(np.asarray(theta0, np.float64) - th)
+    tol_t = 2 * u * np.abs(th) + 16 * u * d + 4 * u * (d / np.abs(mo)) * mg
+    worst = 0.0
+    for got, ref, tol, what in ((out_t, th, tol_t, "theta"), (out_m, mo, 4 * u * mg, "m"), (out_v, vo, 4 * u * np.abs(vo), "v")):
+        r = np.abs(got - ref) / tol
+        worst = max(worst, float(r.max()))
+        assert (r <= 1.0).all(), (what, float(r.max()))
+    return worst

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import (IMG_TOL, compare_images, flat_grads, grad_report, renderer_for, seg_np)
+from gpu_util import (IMG_TOL, adam_check, compare_images, flat_grads, grad_report, renderer_for, seg_np)
 from paper_2604_02851_amd import scenes as S
 from paper_2604_02851_amd.native import DeviceParams
 
@@ -270,14 +270,12 @@ def test_adam_matches_oracle(oracle):
     ctx.adam_step(P, g, m, v, step, lr, 0.9, 0.999, 1e-8)
     torch.cuda.synchronize()
     assert step.item() == 5
-    out = [t.cpu().numpy() for t in P.tensors()]
-    n = sc.n
+    out_t, out_m, out_v = ([t.cpu().numpy() for t in d.tensors()] for d in (P, m, v))
     groups = [(0, slice(None), lr[0]), (1, slice(None), lr[1]), (2, slice(None), lr[2]), (3, slice(None), lr[3]),
               (4, slice(0, 3), lr[4]), (4, slice(3, None), lr[5])]
     for ti, sl, l in groups:
-        th, mo, vo = oracle.adam(theta0[ti][sl], g0[ti][sl], m0[ti][sl], v0[ti][sl], l, 0.9, 0.999, 1e-8, 5)
-        err = np.abs(out[ti][sl] - th)
-        assert (err <= 1e-6 * np.abs(th) + 1e-9).all(), (ti, err.max())
+        adam_check(oracle, theta0[ti][sl], g0[ti][sl], m0[ti][sl], v0[ti][sl], out_t[ti][sl], out_m[ti][sl],
+                   out_v[ti][sl], l, 0.9, 0.999, 1e-8, 5)
 
 
 def test_delta_bit_exact(oracle):
