@@ -141,7 +141,7 @@ def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log, froz
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    if r.counters().overflow:
+    if r.counters().overflow_any:
         raise SystemExit(f"cfg{cfg}: key capacity overflowed during the timed steps")
     out = {"steps_per_s": round(1000.0 / ms, 3), "ms_per_step": round(ms, 4), "views": len(w.cams),
            "views_per_s": round(len(w.cams) * 1000.0 / ms, 2), "gaussians": w.scene.n, "pixels": w.n_pixels,
@@ -270,7 +270,7 @@ def dynamics_rate(shape: dict, steps: int, torch, log) -> dict:
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     dyn_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
-    if r.counters().overflow:
+    if r.counters().overflow_any:
         raise SystemExit("dynamics: key capacity overflowed during the timed steps")
     add = DeviceParams.from_scene(S.draw_scene(rng, 100_000, 5.0, w.scene.sh_degree))
     n, na, k = params.n, opt.n_active, add.n
@@ -340,7 +340,7 @@ def rig_rate(precull: bool, grouped: bool, shape: dict, steps: int, warmup: int,
     e1.record(s2)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    if r.counters().overflow:
+    if r.counters().overflow_any:
         raise SystemExit("rig workload: key capacity overflowed during the timed steps")
     c = r.counters()
     log(f"[bench] rig 2M/8 views/60deg, precull={precull}, grouped={grouped}: {ms:.3f} ms/step "
@@ -438,7 +438,7 @@ def main():
     t_wall = time.perf_counter() - t_wall
     ms_batched = ev0.elapsed_time(ev1) / args.steps
     c = r.counters()
-    if c.overflow:
+    if c.overflow_any:
         raise SystemExit("key capacity overflowed during the timed steps: measurement invalid")
     log(f"[bench] batched graph: {ms_batched:.3f} ms/step ({1000 / ms_batched:.2f} steps/s), "
         f"wall {t_wall / args.steps * 1000:.3f} ms/step, loss {opt.loss.item():.5f}")
@@ -454,7 +454,7 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         ms_plain = ev0.elapsed_time(ev1) / args.plain_steps
-        if r.counters().overflow:
+        if r.counters().overflow_any:
             raise SystemExit("key capacity overflowed in the plain path")
         log(f"[bench] plain eager: {ms_plain:.3f} ms/step ({1000 / ms_plain:.2f} steps/s)")
 

@@ -30,6 +30,16 @@
  *    GS_ERR_STALE for a graph launch whose bound arguments changed,
  *    GS_ERR_UNSUPPORTED for an option outside the built kernels.
  *    gs_last_error() returns a message for the last failing call.
+ *  - Key capacity: the number of (tile, Gaussian) keys is data dependent and
+ *    is never synchronised on.  A tile-list build that needs more keys than
+ *    the plan holds emits only the first key_capacity ones (their lists, and
+ *    every image and gradient computed from them, are then invalid) and sets
+ *    a device flag that stays set across later steps and graph replays.
+ *    gs_read_counters reports and clears it and marks the context: from then
+ *    on gs_project, gs_build_tile_lists, gs_composite, gs_backward, gs_step,
+ *    gs_step_capture and gs_step_launch return GS_ERR_CAPACITY without
+ *    enqueueing anything, until gs_plan is called again (with a larger
+ *    key_capacity).
  */
 #ifndef GSOPT_H
 #define GSOPT_H
@@ -114,8 +124,10 @@ typedef struct {
   int64_t visible;       /* visible (view, Gaussian) pairs */
   int64_t keys;          /* (tile, Gaussian) keys needed */
   int64_t key_capacity;  /* keys the plan can hold */
-  uint32_t overflow;     /* 1 if keys > key_capacity (outputs then invalid) */
-  uint32_t reserved;
+  uint32_t overflow;     /* 1 if the last build's keys > key_capacity (its outputs are invalid) */
+  uint32_t overflow_any; /* 1 if any build since the previous gs_read_counters (or since
+                            gs_workspace_init) overflowed; reading it marks the context
+                            (GS_ERR_CAPACITY until the next gs_plan) */
 } gs_counters;
 
 /* ---- context ------------------------------------------------------------ */
@@ -434,7 +446,11 @@ gs_status gs_profile_enable(gs_ctx ctx, int32_t on);
 gs_status gs_profile_read(gs_ctx ctx, const char* stage, double* total_ms, int64_t* calls);
 gs_status gs_profile_reset(gs_ctx ctx);
 
-/* Synchronous: waits for `stream` and reads the counters of the last step. */
+/* Synchronous: waits for `stream` and reads the counters of the last step.
+ * When a build overflowed the key capacity since the previous read, sets
+ * out->overflow_any, clears the workspace's sticky flag and marks ctx, so
+ * that the rendering calls return GS_ERR_CAPACITY until the next gs_plan
+ * (the read itself returns GS_OK). */
 gs_status gs_read_counters(gs_ctx ctx, const void* dev_workspace, hipStream_t stream, gs_counters* out);
 
 /* ---- whole optimize step ------------------------------------------------ */

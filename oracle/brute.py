@@ -61,15 +61,23 @@ def to_torch(scene, requires_grad=True):
     return ts
 
 
-def render_torch(ts: dict, sh_degree: int, cam, bg=(0.0, 0.0, 0.0), np_mean=None):
-    """Returns (image [3,H,W], T [H,W], n [H,W]) in FP64 with autograd."""
+FIELDS = ("u", "w", "a", "b", "c", "o", "r", "g", "bl")   # screen-space quantities per splat
+
+
+def project_torch(ts: dict, sh_degree: int, cam):
+    """Differentiable projection of every Gaussian into one view (FP64).
+    Returns (fields, keep, order): fields maps each name of FIELDS to an [N]
+    tensor (projected mean u, w; conic [[a, b], [b, c]]; opacity o; colour
+    r, g, bl after the clamp at 0), keep the numpy mask of Gaussians that
+    pass the near plane and have a positive screen determinant, order the
+    depth order (FP32 depth bits, then index)."""
     W_img, H_img = int(cam["width"]), int(cam["height"])
     Rw = torch.tensor(cam["R"].astype(np.float64).reshape(3, 3))
     tw = torch.tensor(cam["t"].astype(np.float64))
     fx, fy, cx, cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
     mean = ts["mean"]                      # [3, N]
     N = mean.shape[1]
-    mean_np = np_mean if np_mean is not None else ts["mean"].detach().numpy().astype(F32)
+    mean_np = ts["mean"].detach().numpy().astype(F32)
     z32 = depth_keys(mean_np, cam)
     order = np.lexsort((np.arange(N), z32.view(np.uint32)))
     keep = z32 >= NEAR
@@ -103,10 +111,6 @@ def render_torch(ts: dict, sh_degree: int, cam, bg=(0.0, 0.0, 0.0), np_mean=None
     C = S2[1, 1] + DILATION
     det = A * C - B * B
     keep = keep & (det.detach().numpy() > 0)
-    ca, cb, cc = C / det, -B / det, A / det
-    u = fx * x[0] / x[2] + cx
-    v = fy * x[1] / x[2] + cy
-    o = torch.sigmoid(ts["opacity_logit"])
     campos = torch.tensor(cam["campos"].astype(np.float64))
     dv = mean - campos[:, None]
     d = (dv / dv.norm(dim=0, keepdim=True)).T          # [N, 3]
@@ -114,7 +118,28 @@ def render_torch(ts: dict, sh_degree: int, cam, bg=(0.0, 0.0, 0.0), np_mean=None
     nk = (sh_degree + 1) ** 2
     sh = ts["sh"].reshape(nk, 3, N)
     col = torch.clamp(torch.einsum("nk,kcn->cn", Y, sh) + 0.5, min=0.0)  # [3, N]
+    fields = {"u": fx * x[0] / x[2] + cx, "w": fy * x[1] / x[2] + cy, "a": C / det, "b": -B / det, "c": A / det,
+              "o": torch.sigmoid(ts["opacity_logit"]), "r": col[0], "g": col[1], "bl": col[2]}
+    return fields, keep, order
 
+
+def _per_gaussian(v, N):
+    a = np.asarray(v, np.float64)
+    return np.broadcast_to(a, (N,)) if a.ndim == 0 else a
+
+
+def composite_torch(fields: dict, keep, order, H_img: int, W_img: int, bg=(0.0, 0.0, 0.0), cutoff=-4.5,
+                    alpha_min=ALPHA_MIN, t_min=T_MIN, clamp_at=ALPHA_MAX, stats: bool = False):
+    """Front-to-back compositing of every pixel against every Gaussian in
+    depth order (FP64, differentiable in the fields).  The thresholds may be
+    scalars or per-Gaussian arrays, so that a test can force the outcome of
+    one Gaussian's decision: the ellipse test P >= cutoff, the skip test
+    alpha >= alpha_min, the stop test T (1 - alpha) < t_min and the clamp
+    o e^P >= clamp_at (a clamped alpha is ALPHA_MAX).  Returns (image [3,H,W],
+    T [H,W], n [H,W]) and, with stats, also E [H,W] = sum over the composited
+    splats of 1 / (1 - alpha)."""
+    N = fields["u"].shape[0]
+    cut, amin, tmin, camp = (_per_gaussian(v, N) for v in (cutoff, alpha_min, t_min, clamp_at))
     py, px = torch.meshgrid(torch.arange(H_img, dtype=torch.float64), torch.arange(W_img, dtype=torch.float64),
                             indexing="ij")
     px = px.reshape(-1) + 0.5
@@ -124,25 +149,39 @@ def render_torch(ts: dict, sh_degree: int, cam, bg=(0.0, 0.0, 0.0), np_mean=None
     Cacc = torch.zeros(3, npx, dtype=torch.float64)
     done = torch.zeros(npx, dtype=torch.bool)
     ncon = torch.zeros(npx, dtype=torch.int64)
+    E = torch.zeros(npx, dtype=torch.float64)
+    u, v, ca, cb, cc, o = (fields[k] for k in ("u", "w", "a", "b", "c", "o"))
+    col = torch.stack([fields["r"], fields["g"], fields["bl"]])
     for i in order:
         if not keep[i]:
             continue
         dx = px - u[i]
         dy = py - v[i]
         P = -0.5 * (ca[i] * dx * dx + cc[i] * dy * dy) - cb[i] * dx * dy
-        alpha = torch.clamp(o[i] * torch.exp(P), max=ALPHA_MAX)
-        ok = (P.detach() >= -4.5) & (alpha.detach() >= ALPHA_MIN) & ~done
+        oG = o[i] * torch.exp(P)
+        clamped = oG.detach() >= camp[i]
+        alpha = torch.where(clamped, torch.full_like(oG, ALPHA_MAX), oG)
+        ok = (P.detach() >= cut[i]) & (alpha.detach() >= amin[i]) & ~done
         Tn = T * (1 - alpha)
-        stop = ok & (Tn.detach() < T_MIN)
+        stop = ok & (Tn.detach() < tmin[i])
         take = ok & ~stop
         done = done | stop
         w = torch.where(take, alpha * T, torch.zeros_like(T))
         Cacc = Cacc + col[:, i:i + 1] * w[None, :]
         T = torch.where(take, Tn, T)
         ncon = ncon + take.long()
+        E = E + torch.where(take, 1.0 / (1.0 - alpha.detach()), torch.zeros_like(E))
     bgt = torch.tensor(bg, dtype=torch.float64)[:, None]
     img = Cacc + T[None, :] * bgt
-    return img.reshape(3, H_img, W_img), T.reshape(H_img, W_img), ncon.reshape(H_img, W_img)
+    out = (img.reshape(3, H_img, W_img), T.reshape(H_img, W_img), ncon.reshape(H_img, W_img))
+    return out + (E.reshape(H_img, W_img),) if stats else out
+
+
+def render_torch(ts: dict, sh_degree: int, cam, bg=(0.0, 0.0, 0.0), **thresholds):
+    """Returns (image [3,H,W], T [H,W], n [H,W]) in FP64 with autograd;
+    keyword thresholds as in composite_torch."""
+    fields, keep, order = project_torch(ts, sh_degree, cam)
+    return composite_torch(fields, keep, order, int(cam["height"]), int(cam["width"]), bg, **thresholds)
 
 
 def pinhole(cam, p: np.ndarray) -> np.ndarray:

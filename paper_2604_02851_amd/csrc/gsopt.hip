@@ -2,6 +2,7 @@
 // sequencing (batched and plain), graph capture and replay.
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -36,6 +37,9 @@ struct gs_context {
   hipGraphExec_t exec = nullptr;
   gs_step_args captured{};
   uint64_t graph_gen = 0;
+  // set when gs_read_counters finds that a tile-list build overflowed the key
+  // capacity; the rendering calls refuse to run until the next gs_plan
+  bool capacity_exceeded = false;
 };
 
 namespace {
@@ -183,6 +187,12 @@ gs_status check_range(gs_ctx c, int v0, int nv, const void* ws, const char* what
   return GS_OK;
 }
 
+gs_status check_capacity(gs_ctx c, const char* what) {
+  if (!c->capacity_exceeded) return GS_OK;
+  return fail(c, GS_ERR_CAPACITY, "%s: a tile-list build overflowed the key capacity of %lld (reported by "
+              "gs_read_counters); call gs_plan with a larger key_capacity", what, (long long)c->plan.cap);
+}
+
 bool same_params(const gs_params& a, const gs_params& b) {
   return a.mean == b.mean && a.log_scale == b.log_scale && a.quat == b.quat && a.opacity_logit == b.opacity_logit &&
          a.sh == b.sh && a.n == b.n && a.sh_degree == b.sh_degree;
@@ -312,6 +322,7 @@ gs_status gs_plan(gs_ctx c, int32_t n, int32_t sh_degree, int32_t n_views, const
   pl.valid = true;
   c->plan = pl;
   c->plan_gen += 1;
+  c->capacity_exceeded = false;
   *ws_bytes = pl.ws.total;
   return GS_OK;
 }
@@ -342,6 +353,7 @@ gs_status gs_project(gs_ctx c, const gs_params* params, const gs_camera* cams, i
   if (!c) return GS_ERR_INVALID;
   gs_status s = check_range(c, v0, nv, ws, "gs_project");
   if (s != GS_OK) return s;
+  if ((s = check_capacity(c, "gs_project")) != GS_OK) return s;
   if ((s = check_params(c, params, "gs_project")) != GS_OK) return s;
   if (!cams) return fail(c, GS_ERR_INVALID, "gs_project: null cameras");
   const Plan& pl = c->plan;
@@ -357,6 +369,7 @@ gs_status gs_build_tile_lists(gs_ctx c, int32_t v0, int32_t nv, void* ws, hipStr
   if (!c) return GS_ERR_INVALID;
   gs_status s = check_range(c, v0, nv, ws, "gs_build_tile_lists");
   if (s != GS_OK) return s;
+  if ((s = check_capacity(c, "gs_build_tile_lists")) != GS_OK) return s;
   GS_HIP(c, timed(c, ST_LISTS, st, [&] { return launch_tile_lists(c->plan, v0, nv, ws, st); }));
   return GS_OK;
 }
@@ -366,6 +379,7 @@ gs_status gs_composite(gs_ctx c, int32_t v0, int32_t nv, void* ws, float* img, f
   if (!c) return GS_ERR_INVALID;
   gs_status s = check_range(c, v0, nv, ws, "gs_composite");
   if (s != GS_OK) return s;
+  if ((s = check_capacity(c, "gs_composite")) != GS_OK) return s;
   if (!img || !T || !nc) return fail(c, GS_ERR_INVALID, "gs_composite: null output");
   GS_HIP(c, timed(c, ST_COMPOSITE, st, [&] { return launch_composite(c->plan, v0, nv, ws, img, T, nc, st); }));
   return GS_OK;
@@ -377,6 +391,7 @@ gs_status gs_backward(gs_ctx c, const gs_params* params, const gs_camera* cams, 
   if (!c) return GS_ERR_INVALID;
   gs_status s = check_range(c, v0, nv, ws, "gs_backward");
   if (s != GS_OK) return s;
+  if ((s = check_capacity(c, "gs_backward")) != GS_OK) return s;
   if ((s = check_params(c, params, "gs_backward")) != GS_OK) return s;
   if ((s = check_trainable(c, grads, "gs_backward(grads)")) != GS_OK) return s;
   if (!cams || !img || !T || !up) return fail(c, GS_ERR_INVALID, "gs_backward: null input");
@@ -756,7 +771,14 @@ gs_status gs_read_counters(gs_ctx c, const void* ws, hipStream_t st, gs_counters
   out->keys = h.keys;
   out->key_capacity = c->plan.cap;
   out->overflow = h.overflow;
-  out->reserved = 0;
+  out->overflow_any = (h.overflow_any | h.overflow) != 0u ? 1u : 0u;
+  if (out->overflow_any) {
+    // reported once here; the context keeps refusing to render until re-planned
+    c->capacity_exceeded = true;
+    const uint32_t zero = 0u;
+    GS_HIP(c, hipMemcpy(seg<char>(const_cast<void*>(ws), c->plan.ws.counters + offsetof(Counters, overflow_any)),
+                        &zero, sizeof(zero), hipMemcpyHostToDevice));
+  }
   return GS_OK;
 }
 
@@ -796,6 +818,8 @@ gs_status gs_step(gs_ctx c, const gs_step_args* a, hipStream_t st) {
   if (!c) return GS_ERR_INVALID;
   c->err.clear();
   if (!a) return fail(c, GS_ERR_INVALID, "gs_step: null arguments");
+  gs_status s = check_capacity(c, "gs_step");
+  if (s != GS_OK) return s;
   return run_step(c, a, st);
 }
 
@@ -804,6 +828,7 @@ gs_status gs_step_capture(gs_ctx c, const gs_step_args* a, hipStream_t st) {
   c->err.clear();
   if (!a) return fail(c, GS_ERR_INVALID, "gs_step_capture: null arguments");
   if (st == nullptr) return fail(c, GS_ERR_INVALID, "gs_step_capture: capture needs a non-default stream");
+  if (check_capacity(c, "gs_step_capture") != GS_OK) return GS_ERR_CAPACITY;
   if (c->exec) { (void)hipGraphExecDestroy(c->exec); c->exec = nullptr; }
   if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
   GS_HIP(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -831,6 +856,7 @@ gs_status gs_step_launch(gs_ctx c, const gs_step_args* a, hipStream_t st) {
   if (!c->exec) return fail(c, GS_ERR_INVALID, "gs_step_launch: nothing captured");
   if (c->graph_gen != c->plan_gen || !same_args(*a, c->captured))
     return fail(c, GS_ERR_STALE, "gs_step_launch: arguments or plan changed since capture");
+  if (check_capacity(c, "gs_step_launch") != GS_OK) return GS_ERR_CAPACITY;
   GS_HIP(c, hipGraphLaunch(c->exec, st));
   return GS_OK;
 }

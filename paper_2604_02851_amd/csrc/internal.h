@@ -39,7 +39,9 @@ struct Counters {
   uint32_t keys;          // keys needed by the last tile-list build
   uint32_t overflow;      // set when keys > capacity
   uint32_t key_cap;
-  uint32_t pad[4];        // pad[0]: kept count of the last freeze
+  uint32_t kept;          // active count kept by the last freeze
+  uint32_t overflow_any;  // set with overflow, cleared only by gs_read_counters / gs_workspace_init
+  uint32_t pad[2];
 };
 
 // Byte offsets of the workspace segments (computed by the host at plan time).

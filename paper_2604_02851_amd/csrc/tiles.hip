@@ -508,7 +508,10 @@ __global__ void k_key_total(Counters* c, const uint32_t* total_keys, uint32_t ca
     const uint32_t k = *total_keys;
     c->keys = k;
     c->key_cap = cap;
-    if (k > cap) c->overflow = 1u;
+    if (k > cap) {
+      c->overflow = 1u;
+      c->overflow_any = 1u;
+    }
   }
 }
 

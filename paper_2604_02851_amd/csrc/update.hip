@@ -435,7 +435,7 @@ hipError_t launch_freeze(const Plan& pl, const gs_params& p, const gs_params& m,
   uint32_t* pos = seg<uint32_t>(ws, pl.ws.koff);
   uint32_t* dst = seg<uint32_t>(ws, pl.ws.vkey_a);
   uint32_t* scratch = seg<uint32_t>(ws, pl.ws.vkey_b);
-  uint32_t* kept = &seg<Counters>(ws, pl.ws.counters)->pad[0];
+  uint32_t* kept = &seg<Counters>(ws, pl.ws.counters)->kept;
   hipLaunchKernelGGL(k_keep_flags, dim3(blocks256(na)), dim3(256), 0, st, flags, na, keep);
   hipError_t e = launch_scan(keep, pos, na, nullptr, seg<uint32_t>(ws, pl.ws.partial), pl.ws.partial_len, kept, st);
   if (e != hipSuccess) return e;

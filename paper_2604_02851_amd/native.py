@@ -78,7 +78,7 @@ def codec_array(codecs):
 
 class GsCounters(ctypes.Structure):
     _fields_ = [("visible", c_int64), ("keys", c_int64), ("key_capacity", c_int64),
-                ("overflow", c_uint32), ("reserved", c_uint32)]
+                ("overflow", c_uint32), ("overflow_any", c_uint32)]
 
 
 class GsStepArgs(ctypes.Structure):

@@ -33,6 +33,9 @@ class Renderer:
         self.ppt, self.wave_w, self.schedule = pixels_per_thread, wave_w or tile[0], schedule
         self.dev_cams = torch.from_numpy(self.cams.view(np.uint8).copy()).to(self.device)
         self.key_capacity = int(key_capacity or max(1 << 16, 8 * n * len(self.cams)))
+        self.max_need = 0          # largest key count any fit_capacity call has seen
+        # incremented whenever the workspace's lists and per-pixel state change
+        self.forward_count = 0
         self._plan()
         P = int(self.pix_off[-1])
         self.images = torch.zeros(3 * P, dtype=torch.float32, device=self.device)
@@ -48,6 +51,7 @@ class Renderer:
                                self.loss_mode, self.key_capacity, self.ppt, self.wave_w, self.schedule)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.ctx.workspace_init(self.ws)
+        self.capacity_exceeded = False
         self.pix_off, self.tile_off = self.ctx.frame_layout()
         if getattr(self, "precull", None) is not None:   # a new plan turns preculling off: restore it
             self.ctx.set_precull(*self.precull)
@@ -80,6 +84,7 @@ class Renderer:
         optimizer's m, v, ids and baseline, permuted alike.  Results change
         only in the order of Gaussians with equal depth keys."""
         assert getattr(self, "grid", None) is not None, "sort_cells needs the grid of enable_precull()"
+        self.forward_count += 1     # the regrouping reuses the projection's buffers
         self.update_precull(params, stream)
         self.ctx.sort_cells(params, self.cell_of, self.n_cells, self.ws, stream=stream, **state)
 
@@ -108,25 +113,53 @@ class Renderer:
         return images[3 * self.pix_off[v]: 3 * self.pix_off[v + 1]].view(3, H, W)
 
     def counters(self):
-        return self.ctx.read_counters(self.ws)
+        """The counters of the last step (synchronises).  When a build
+        overflowed the key capacity since the previous read, overflow_any is
+        set and the context refuses to render (GsError GS_ERR_CAPACITY) until
+        replan()."""
+        c = self.ctx.read_counters(self.ws)
+        if c.overflow_any:
+            self.capacity_exceeded = True
+        return c
+
+    def check_capacity(self):
+        """Raises GsError(GS_ERR_CAPACITY) when a tile-list build since the
+        last read overflowed the key capacity (its outputs were invalid)."""
+        c = self.counters()
+        if c.overflow_any:
+            raise N.GsError(N.GS_ERR_CAPACITY, f"a tile-list build needed {int(c.keys)} keys of a capacity of "
+                                               f"{int(c.key_capacity)}: replan() with a larger capacity")
+        return c
 
     def fit_capacity(self, params: DeviceParams, per_view: bool = False, margin: float = 1.15):
-        """Runs project + tile lists and grows the key capacity if needed."""
+        """Runs project + tile lists for `params` (all views at once, or one
+        view per call) and re-plans when the key capacity is short of the
+        largest need this renderer has seen, or far above it (sort grids and
+        histogram scans are sized by the capacity).  Capacity never drops
+        below a need seen before, so fitting several models (targets, then
+        the trained model) leaves room for all of them.  Returns this
+        model's need."""
+        if self.capacity_exceeded:   # an overflow was reported: the context needs a new plan first
+            self.replan(self.key_capacity)
         need = 0
         ranges = [(v, 1) for v in range(self.n_views)] if per_view else [(0, self.n_views)]
         for v0, nv in ranges:
+            self.forward_count += 1
             self.ctx.project(params, self.dev_cams, v0, nv, self.ws)
             self.ctx.build_tile_lists(v0, nv, self.ws)
-            need = max(need, int(self.counters().keys))
-        # grow when short, shrink when far above the need (sort grids and the
-        # histogram scans are sized by the capacity)
-        if need > self.key_capacity or need * margin * 1.5 < self.key_capacity:
-            self.replan(max(1024, int(need * margin) + 1024))
+            c = self.counters()
+            need = max(need, int(c.keys))
+            if c.overflow_any:      # the context renders again only after a new plan
+                self.replan(max(1024, int(need * margin) + 1024))
+        self.max_need = max(self.max_need, need)
+        if self.max_need > self.key_capacity or self.max_need * margin * 1.5 < self.key_capacity:
+            self.replan(max(1024, int(self.max_need * margin) + 1024))
         return need
 
     # ---- stages -------------------------------------------------------------
     def forward(self, params: DeviceParams, v0: int = 0, nv: int | None = None):
         nv = self.n_views - v0 if nv is None else nv
+        self.forward_count += 1
         self.ctx.project(params, self.dev_cams, v0, nv, self.ws)
         self.ctx.build_tile_lists(v0, nv, self.ws)
         self.ctx.composite(v0, nv, self.ws, self.images, self.T, self.n_contrib)
@@ -142,8 +175,10 @@ class Renderer:
 class GaussianRasterize(torch.autograd.Function):
     """images = render(params) over every view of `renderer`, with the
     hand-written adjoint of the library as backward.  The renderer keeps the
-    tile lists and per-pixel state of the last forward; a backward must follow
-    its own forward before the renderer runs another one."""
+    tile lists and per-pixel state of the last forward only, so a backward
+    must follow its own forward before the renderer runs another one (or an
+    optimize step, a capacity fit or a regrouping); otherwise the backward
+    raises instead of returning gradients of another forward."""
 
     @staticmethod
     def forward(ctx, mean, log_scale, quat, opacity_logit, sh, renderer: Renderer):
@@ -152,6 +187,7 @@ class GaussianRasterize(torch.autograd.Function):
                               sh.detach().contiguous(), renderer.sh_degree)
         images, T, _ = renderer.forward(params)
         ctx.renderer = renderer
+        ctx.forward_id = renderer.forward_count
         ctx.params = params
         out = images.clone()
         ctx.save_for_backward(out)
@@ -160,6 +196,10 @@ class GaussianRasterize(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_images):
         r: Renderer = ctx.renderer
+        if r.forward_count != ctx.forward_id:
+            raise RuntimeError("GaussianRasterize.backward: the renderer has run another forward pass since this "
+                               "one (its tile lists and per-pixel state belong to that pass); use one renderer per "
+                               "pending backward")
         (images,) = ctx.saved_tensors
         grads = DeviceParams.zeros_like(ctx.params)
         up = grad_images.contiguous().float()
@@ -297,13 +337,25 @@ class Optimizer:
         return new_p
 
     def step(self, plain: bool = False):
+        self.r.forward_count += 1
         self.r.ctx.step(self.args(plain), self.stream)
 
     def capture(self, plain: bool = False):
         self.r.ctx.step_capture(self.args(plain), self.stream)
 
     def replay(self, plain: bool = False):
+        """Replays the captured step.  Raises GsError GS_ERR_CAPACITY once a
+        counter read (check_capacity, or Renderer.counters) has found a key
+        overflow, until the renderer is re-planned and the step captured
+        again."""
+        self.r.forward_count += 1
         self.r.ctx.step_launch(self.args(plain), self.stream)
+
+    def check_capacity(self):
+        """Synchronises and raises GsError(GS_ERR_CAPACITY) if any step since
+        the last check overflowed the key capacity."""
+        (self.stream or torch.cuda.current_stream()).synchronize()
+        return self.r.check_capacity()
 
 
 # ---------------------------------------------------------------------------

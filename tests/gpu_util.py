@@ -72,13 +72,27 @@ def grad_tol(b, rel=GRAD_REL, floor=GRAD_ABS):
 
 def grad_report(g_gpu: np.ndarray, b, rel=GRAD_REL, floor=GRAD_ABS):
     """Checks |g_gpu - g| <= rel |g| + floor + EPS_ACC scale + EPS_T scale_t
-    + slack and returns statistics."""
+    + slack and returns statistics, including which widening terms the
+    elements outside the strict bar rel |g| + floor needed:
+      via_acc / via_t / via_slack: the elements that pass with the strict bar
+        plus the accumulation term, then plus the transmittance term, then
+        plus the slack (each counted at the first sum that admits them);
+      only_acc / only_t / only_slack: the elements that would fail if that
+        one term were dropped from the full bar."""
     err = np.abs(g_gpu - b.grad)
     strict = rel * np.abs(b.grad) + floor
+    acc, tt, sl = EPS_ACC * b.scale, EPS_T * b.scale_t, b.slack
     tol = grad_tol(b, rel, floor)
     ok = err <= tol
     ratio = err / tol
+    s1, s2 = strict + acc, strict + acc + tt
     return {
+        "via_acc": int(((err > strict) & (err <= s1)).sum()),
+        "via_t": int(((err > s1) & (err <= s2)).sum()),
+        "via_slack": int(((err > s2) & ok).sum()),
+        "only_acc": int((ok & (err > tol - acc)).sum()),
+        "only_t": int((ok & (err > tol - tt)).sum()),
+        "only_slack": int((ok & (err > tol - sl)).sum()),
         "max_err_over_tol": float(ratio.max()),
         "p50_err_over_tol": float(np.percentile(ratio, 50)),
         "p99_err_over_tol": float(np.percentile(ratio, 99)),

@@ -236,17 +236,61 @@ def test_empty_and_non_finite(oracle):
 
 
 def test_key_capacity_overflow_is_reported_and_recoverable(oracle):
+    from paper_2604_02851_amd.native import GS_ERR_CAPACITY, GsError
     w = small(seed=109, n=1000)
     P = DeviceParams.from_scene(w.scene)
     r = renderer_for(w, cap=64)
     r.forward(P)
     c = r.counters()
-    assert c.overflow == 1 and c.keys > 64 and c.key_capacity == 64
+    assert c.overflow == 1 and c.overflow_any == 1 and c.keys > 64 and c.key_capacity == 64
+    # the read marks the context: rendering is refused until a new plan
+    with pytest.raises(GsError) as e:
+        r.forward(P)
+    assert e.value.status == GS_ERR_CAPACITY
     r.replan(c.keys)
     img = r.forward(P)[0]
     c = r.counters()
-    assert c.overflow == 0
+    assert c.overflow == 0 and c.overflow_any == 0
     compare_images(oracle, w, img.cpu().numpy())
+
+
+def test_capacity_error_is_sticky_across_graph_replays():
+    """An overflow in one replayed step is still reported after later steps
+    that fit, and from then on replays fail with GS_ERR_CAPACITY until the
+    renderer is re-planned and the step captured again."""
+    from paper_2604_02851_amd.native import GS_ERR_CAPACITY, GsError
+    from paper_2604_02851_amd.renderer import Optimizer
+    w = small(seed=110, n=2000)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        P = DeviceParams.from_scene(w.scene)
+        r = renderer_for(w, loss_mode=1)
+        r.fit_capacity(P)
+        tgt = r.forward(DeviceParams.from_scene(w.extra["perturbed"]))[0].clone()
+        opt = Optimizer(r, P, tgt, stream=s)
+        opt.capture()
+        opt.replay()
+        assert opt.check_capacity().overflow_any == 0
+        fit = r.key_capacity
+        P.log_scale.add_(1.5)        # in place: the captured graph stays valid, the splats grow
+        opt.replay()                 # overflows (keys beyond the capacity are dropped)
+        P.log_scale.sub_(1.5)
+        opt.replay()                 # fits again
+        s.synchronize()
+        c = r.counters()
+        assert c.overflow == 0 and c.overflow_any == 1 and c.keys <= fit
+        for call in (opt.replay, opt.step, lambda: r.forward(P)):
+            with pytest.raises(GsError) as e:
+                call()
+            assert e.value.status == GS_ERR_CAPACITY
+        big = DeviceParams(*[t.clone() for t in P.tensors()], P.sh_degree)
+        big.log_scale.add_(1.5)
+        r.fit_capacity(big)          # re-plans for the larger need
+        assert r.key_capacity > fit
+        opt.invalidate()
+        opt.capture()
+        opt.replay()
+        assert opt.check_capacity().overflow_any == 0
 
 
 def test_adam_matches_oracle(oracle):

@@ -1,9 +1,11 @@
 """Parity at the configured sizes, through the C ABI in the benchmark's launch
 configuration: cfg2 in full (autograd Function, oracle gradient and FP64
 finite differences), cfg3 / cfg4 / cfg5 on sampled rows of every view, a full
-gradient check on two views of cfg3, cfg4 tile lists of three views
-bit-exact inside the 16-view batched call, the 16-view batched cfg4 backward
-against the oracle's gradient of the three views it is given gradients on,
+gradient check on two views of cfg3, cfg4 tile lists of three 640x360 views
+and of a 1920x1080 view bit-exact inside the 16-view batched call, the
+16-view batched cfg4 backward against the oracle's gradient of the views it
+is given gradients on (three 640x360 views; a 1920x1080 and a 1280x720
+view), the four-view cfg5 backward against the oracle on one 1080p view,
 Adam over the whole cfg4 model on every element, cfg5 delta extraction
 bit-exact at 3M Gaussians after scene dynamics and a GPU step, and graph
 replay against eager steps."""
@@ -192,30 +194,70 @@ def test_config4_tile_lists_three_views(oracle):
     n = w.scene.n
     assert np.array_equal(vals, vals_o + np.uint32(3 * n))
     print("cfg4 tile lists of views 3-5:", len(vals_o), "keys of", c.keys)
+    # the closest 1920x1080 view (11) inside the same call
+    vals_o, ranges_o = oracle.tile_lists(w.scene, w.cams[11:12], tw, th)
+    t0, t1 = int(base[11]), int(base[12])
+    ranges = seg_np(r, "ranges", np.uint32).reshape(-1, 2)[t0:t1].astype(np.int64)
+    empty_o = ranges_o[:, 0] == ranges_o[:, 1]
+    assert np.array_equal(ranges[:, 0] == ranges[:, 1], empty_o)
+    off = int(ranges[~empty_o, 0].min())
+    assert np.array_equal(ranges[~empty_o] - off, ranges_o[~empty_o].astype(np.int64))
+    vals = seg_np(r, "sorted_values", np.uint32)[off:off + len(vals_o)]
+    assert np.array_equal(vals, vals_o + np.uint32(11 * n))
+    print("cfg4 tile lists of view 11 (1080p):", len(vals_o), "keys of", c.keys)
 
 
-def test_config4_batched_gradient_three_views(oracle):
-    """The 16-view batched backward of the 1M-Gaussian workload, the call the
-    benchmark step makes, with an upstream gradient that is zero outside views
-    3-5 (640x360 each): every other view then adds exact zeros, so the whole
-    gradient must equal the oracle's gradient over those three views."""
-    w = S.workload(4)
-    assert list(w.cams["width"][3:6]) == [640] * 3 and list(w.cams["height"][3:6]) == [360] * 3
+def _batched_gradient_check(oracle, w, views, seed, label):
+    """The batched backward over every view of `w` (the call the benchmark
+    step makes), with an upstream gradient that is zero outside `views`:
+    every other view then adds exact zeros, so the whole gradient must equal
+    the oracle's gradient over those views alone."""
     P = DeviceParams.from_scene(w.scene)
     r = _renderer(w)
     r.fit_capacity(P)
     off = oracle.pixel_offsets(w.cams)
-    lo, hi = 3 * int(off[3]), 3 * int(off[6])
     G = np.zeros(3 * w.n_pixels, F32)
-    G[lo:hi] = np.random.default_rng(44).normal(size=hi - lo).astype(F32)
+    rng = np.random.default_rng(seed)
+    for v in views:
+        lo, hi = 3 * int(off[v]), 3 * int(off[v + 1])
+        G[lo:hi] = rng.normal(size=hi - lo).astype(F32)
     r.forward(P)
     grads = DeviceParams.zeros_like(P)
     r.backward(P, torch.from_numpy(G).cuda(), 0, grads)
     torch.cuda.synchronize()
-    b = oracle.backward(w.scene, w.cams[3:6], G[lo:hi], mode=0)
+    assert r.counters().overflow_any == 0
+    sub = np.ascontiguousarray(w.cams[list(views)])
+    Gs = np.concatenate([G[3 * int(off[v]):3 * int(off[v + 1])] for v in views])
+    b = oracle.backward(w.scene, sub, Gs, mode=0)
     rep = grad_report(flat_grads(grads), b)
-    print("cfg4 batched gradient (views 3-5 nonzero)", rep)
+    print(label, rep)
     assert rep["fail"] == 0
+    return rep
+
+
+def test_config4_batched_gradient_three_views(oracle):
+    """Views 3-5 (640x360 each) of the 16-view batched cfg4 backward."""
+    w = S.workload(4)
+    assert list(w.cams["width"][3:6]) == [640] * 3 and list(w.cams["height"][3:6]) == [360] * 3
+    _batched_gradient_check(oracle, w, (3, 4, 5), 44, "cfg4 batched gradient (views 3-5 nonzero)")
+
+
+def test_config4_batched_gradient_1080p_and_720p(oracle):
+    """The closest 1920x1080 view (11, radius 6.9) and the closest 1280x720
+    view (7, radius 6.5) of the 16-view batched cfg4 backward: the largest
+    splats of the workload and the deepest lists."""
+    w = S.workload(4)
+    assert (int(w.cams["width"][11]), int(w.cams["height"][11])) == (1920, 1080)
+    assert (int(w.cams["width"][7]), int(w.cams["height"][7])) == (1280, 720)
+    _batched_gradient_check(oracle, w, (7, 11), 45, "cfg4 batched gradient (views 7 and 11 nonzero)")
+
+
+def test_config5_batched_gradient_1080p(oracle):
+    """The 3M-Gaussian four-view 1080p call with the upstream gradient on its
+    closest view (2, radius 6.3): the densest overlap of the workloads."""
+    w = S.workload(5)
+    assert all(int(c["width"]) == 1920 and int(c["height"]) == 1080 for c in w.cams)
+    _batched_gradient_check(oracle, w, (2,), 46, "cfg5 batched gradient (view 2 nonzero)")
 
 
 def test_config4_adam_every_element(oracle):
