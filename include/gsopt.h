@@ -390,6 +390,29 @@ gs_status gs_delta_encode(gs_ctx ctx, const gs_params* cur, gs_params* baseline,
                           uint32_t group_mask, const uint32_t* dev_epoch, uint32_t* dev_out, int64_t out_cap_words,
                           void* dev_workspace, hipStream_t stream);
 
+/* Largest model (Gaussians) that gs_delta_encode_noalloc accepts. */
+#define GS_NOALLOC_MAX_N (1 << 22)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * packet of gs_delta_encode, computed by the same kernels, without a plan or
+ * a workspace.  Its scratch (a flag byte per Gaussian, per-block counts, scan
+ * partials and section bases: about 4.6 MB) is a fixed device array of the
+ * library, one per GPU, held until the process ends; gs_create looks up its
+ * address on the context's device.  Arguments, packet layout and baseline
+ * update as in gs_delta_encode; cur->n and baseline->n must be equal and at
+ * most GS_NOALLOC_MAX_N (else GS_ERR_INVALID, nothing enqueued); n may
+ * differ from call to call.  Calls this function makes: kernel launches
+ * only, no hipMalloc, hipFree or other allocating call.  Every call on one
+ * GPU shares that GPU's scratch: calls that overlap in time on one GPU (two
+ * streams, two contexts, two threads) race and must be serialised by the
+ * caller; calls enqueued in order on one stream are safe.  Nothing in the
+ * scratch needs clearing between calls (each call writes every word it
+ * reads). */
+gs_status gs_delta_encode_noalloc(gs_ctx ctx, const gs_params* cur, gs_params* baseline, const gs_codec* codecs,
+                                  uint32_t group_mask, const uint32_t* dev_epoch, uint32_t* dev_out,
+                                  int64_t out_cap_words, hipStream_t stream);
+
 /* Client replay (Sec. 3.5: the receiver keeps a local model and applies
  * incoming deltas): applies a gs_delta_encode packet (packet_words words on
  * the device, e.g. as received) to `model` with the sender's codecs.

@@ -224,6 +224,8 @@ gs_status gs_create(int32_t hip_device, gs_ctx* out) {
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count) return GS_ERR_INVALID;
   if (hipSetDevice(hip_device) != hipSuccess) return GS_ERR_HIP;
+  // this device's copy of the allocation-free encoder's scratch
+  if (noalloc_scratch_init(hip_device) != hipSuccess) return GS_ERR_HIP;
   gs_ctx c = new gs_context();
   c->device = hip_device;
   *out = c;
@@ -600,6 +602,39 @@ gs_status gs_delta_encode(gs_ctx c, const gs_params* cur, gs_params* base, const
   return GS_OK;
 }
 
+static gs_status check_tensor(gs_ctx c, const gs_params* t, const char* what) {
+  if (!t || t->n < 0 || t->sh_degree < 0 || t->sh_degree > 3) return fail(c, GS_ERR_INVALID, "%s: invalid", what);
+  if (t->n > 0 && (!t->mean || !t->log_scale || !t->quat || !t->opacity_logit || !t->sh))
+    return fail(c, GS_ERR_INVALID, "%s: null tensor pointer", what);
+  return GS_OK;
+}
+
+gs_status gs_delta_encode_noalloc(gs_ctx c, const gs_params* cur, gs_params* base, const gs_codec* codecs,
+                                  uint32_t mask, const uint32_t* epoch, uint32_t* out, int64_t cap_words,
+                                  hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  gs_status s;
+  if ((s = check_tensor(c, cur, "gs_delta_encode_noalloc(cur)")) != GS_OK) return s;
+  if ((s = check_tensor(c, base, "gs_delta_encode_noalloc(baseline)")) != GS_OK) return s;
+  if (base->n != cur->n || base->sh_degree != cur->sh_degree)
+    return fail(c, GS_ERR_INVALID, "gs_delta_encode_noalloc: baseline (n=%d, degree %d) differs from cur (n=%d, degree %d)",
+                base->n, base->sh_degree, cur->n, cur->sh_degree);
+  if (cur->n > GS_NOALLOC_MAX_N)
+    return fail(c, GS_ERR_INVALID, "gs_delta_encode_noalloc: n=%d above GS_NOALLOC_MAX_N=%d", cur->n,
+                (int)GS_NOALLOC_MAX_N);
+  if ((s = check_codecs(c, codecs, "gs_delta_encode_noalloc")) != GS_OK) return s;
+  if (!out || !epoch) return fail(c, GS_ERR_INVALID, "gs_delta_encode_noalloc: null output or epoch");
+  if (mask & ~0x3Fu)
+    return fail(c, GS_ERR_INVALID, "gs_delta_encode_noalloc: group_mask 0x%x has bits above 5", mask);
+  const int64_t need = codec_capacity(cur->n, cur->sh_degree, codecs, mask);
+  if (cap_words < need)
+    return fail(c, GS_ERR_INVALID, "gs_delta_encode_noalloc: out_cap_words=%lld < %lld", (long long)cap_words,
+                (long long)need);
+  GS_HIP(c, launch_delta_encode_noalloc(c->device, *cur, *base, codecs, mask, epoch, out, st));
+  return GS_OK;
+}
+
 gs_status gs_delta_apply(gs_ctx c, gs_params* model, const gs_codec* codecs, const uint32_t* packet,
                          int64_t packet_words, const uint32_t* epoch, uint32_t* status, hipStream_t st) {
   if (!c) return GS_ERR_INVALID;
@@ -613,13 +648,6 @@ gs_status gs_delta_apply(gs_ctx c, gs_params* model, const gs_codec* codecs, con
   if (!packet || !epoch || !status || packet_words < 0)
     return fail(c, GS_ERR_INVALID, "gs_delta_apply: null packet, epoch or status");
   GS_HIP(c, launch_delta_apply(*model, codecs, packet, packet_words, epoch, status, st));
-  return GS_OK;
-}
-
-static gs_status check_tensor(gs_ctx c, const gs_params* t, const char* what) {
-  if (!t || t->n < 0 || t->sh_degree < 0 || t->sh_degree > 3) return fail(c, GS_ERR_INVALID, "%s: invalid", what);
-  if (t->n > 0 && (!t->mean || !t->log_scale || !t->quat || !t->opacity_logit || !t->sh))
-    return fail(c, GS_ERR_INVALID, "%s: null tensor pointer", what);
   return GS_OK;
 }
 

@@ -181,6 +181,13 @@ hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& b
                         uint32_t* out, void* ws, hipStream_t st);
 hipError_t launch_delta_encode(const Plan& pl, const gs_params& cur, const gs_params& base, const gs_codec* codecs,
                                uint32_t mask, const uint32_t* epoch, uint32_t* out, void* ws, hipStream_t st);
+// Largest model of gs_delta_encode_noalloc, whose scratch is a fixed device array.
+constexpr int64_t kNoAllocMaxN = GS_NOALLOC_MAX_N;
+size_t noalloc_scratch_bytes();
+// Looks up this device's copy of that array (the device must be current).
+hipError_t noalloc_scratch_init(int device);
+hipError_t launch_delta_encode_noalloc(int device, const gs_params& cur, const gs_params& base, const gs_codec* codecs,
+                                       uint32_t mask, const uint32_t* epoch, uint32_t* out, hipStream_t st);
 hipError_t launch_delta_apply(const gs_params& model, const gs_codec* codecs, const uint32_t* packet,
                               int64_t packet_words, const uint32_t* epoch, uint32_t* status, hipStream_t st);
 // words that one sent row of a group of `width` values occupies under a codec

@@ -511,19 +511,37 @@ static CodecDev codec_dev(const gs_codec* codecs, const int32_t* width) {
   return d;
 }
 
-static hipError_t run_delta(const Plan& pl, DeltaArgs& a, void* ws, hipStream_t st) {
-  a.flags = seg<uint8_t>(ws, pl.ws.dflags);
-  a.bcount = seg<uint32_t>(ws, pl.ws.dcount);
-  a.dbase = seg<uint32_t>(ws, pl.ws.dbase);
+// The delta kernels' scratch: a flag byte per Gaussian, six block-count rows
+// (scanned in place), the scan's partials and the section bases.  Nothing in
+// it needs to start at zero: every call writes each word it reads.
+struct DeltaScratch {
+  uint8_t* flags;
+  uint32_t* bcount;
+  uint32_t* partial;
+  int64_t partial_len;
+  uint32_t* dbase;
+  int32_t max_blocks;
+};
+
+static hipError_t run_delta(DeltaArgs& a, const DeltaScratch& s, hipStream_t st) {
+  a.flags = s.flags;
+  a.bcount = s.bcount;
+  a.dbase = s.dbase;
   a.nb = (int32_t)((a.n + 255) / 256);
-  if (a.nb > pl.ws.dblocks) return hipErrorInvalidValue;
+  if (a.nb > s.max_blocks) return hipErrorInvalidValue;
   if (a.nb > 0) hipLaunchKernelGGL(k_delta_flags, dim3(a.nb), dim3(256), 0, st, a);
-  hipError_t e = launch_scan(a.bcount, a.bcount, 6ll * a.nb, nullptr, seg<uint32_t>(ws, pl.ws.partial),
-                             pl.ws.partial_len, a.dbase + 15, st);
+  hipError_t e = launch_scan(a.bcount, a.bcount, 6ll * a.nb, nullptr, s.partial, s.partial_len, a.dbase + 15, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_delta_header, dim3(1), dim3(64), 0, st, a);
   if (a.nb > 0) hipLaunchKernelGGL(k_delta_write, dim3(a.nb), dim3(256), 0, st, a);
   return hipGetLastError();
+}
+
+static hipError_t run_delta(const Plan& pl, DeltaArgs& a, void* ws, hipStream_t st) {
+  const DeltaScratch s{seg<uint8_t>(ws, pl.ws.dflags), seg<uint32_t>(ws, pl.ws.dcount),
+                       seg<uint32_t>(ws, pl.ws.partial), pl.ws.partial_len, seg<uint32_t>(ws, pl.ws.dbase),
+                       pl.ws.dblocks};
+  return run_delta(a, s, st);
 }
 
 hipError_t launch_delta(const Plan& pl, const gs_params& cur, const gs_params& base, uint32_t mask, float tau,
@@ -556,6 +574,64 @@ hipError_t launch_delta_encode(const Plan& pl, const gs_params& cur, const gs_pa
   a.epoch = epoch;
   a.out = out;
   return run_delta(pl, a, ws, st);
+}
+
+// ---- the delta encoder without a workspace ----------------------------------
+// Scratch of gs_delta_encode_noalloc in a file-scope device array: each GPU
+// that the library runs on holds its own copy until the process ends.  Its
+// address is looked up once per device (noalloc_scratch_init, called by
+// gs_create with the device current); host code uses only that address,
+// never the array's name, which on the host is a stand-in and not a device
+// address.
+namespace {
+constexpr int64_t kNaBlocks = kNoAllocMaxN / 256;
+constexpr int64_t kNaPartial = (6 * kNaBlocks + kSortChunk - 1) / kSortChunk + 2;
+constexpr size_t na_round(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNaFlagsAt = 0;
+constexpr size_t kNaCountAt = na_round(kNaFlagsAt + (size_t)kNoAllocMaxN);
+constexpr size_t kNaPartialAt = na_round(kNaCountAt + (size_t)(6 * kNaBlocks) * 4);
+constexpr size_t kNaBaseAt = na_round(kNaPartialAt + (size_t)kNaPartial * 4);
+constexpr size_t kNaBytes = kNaBaseAt + 16 * 4;
+static_assert(kNaCountAt % 256 == 0 && kNaPartialAt % 256 == 0 && kNaBaseAt % 256 == 0, "scratch alignment");
+constexpr int kNaMaxDevices = 64;
+
+void* g_scratch_ptr[kNaMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kNaBytes];
+
+size_t noalloc_scratch_bytes() { return kNaBytes; }
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kNaMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+hipError_t launch_delta_encode_noalloc(int device, const gs_params& cur, const gs_params& base, const gs_codec* codecs,
+                                       uint32_t mask, const uint32_t* epoch, uint32_t* out, hipStream_t st) {
+  if (device < 0 || device >= kNaMaxDevices || !g_scratch_ptr[device]) return hipErrorNotInitialized;
+  if (cur.n > kNoAllocMaxN) return hipErrorInvalidValue;
+  char* p = static_cast<char*>(g_scratch_ptr[device]);
+  const DeltaScratch s{reinterpret_cast<uint8_t*>(p + kNaFlagsAt), reinterpret_cast<uint32_t*>(p + kNaCountAt),
+                       reinterpret_cast<uint32_t*>(p + kNaPartialAt), kNaPartial,
+                       reinterpret_cast<uint32_t*>(p + kNaBaseAt), (int32_t)kNaBlocks};
+  DeltaArgs a;
+  float* rows[6];
+  group_rows(base, rows);
+  set_groups(cur, rows, a.g);
+  a.c = codec_dev(codecs, a.g.width);
+  a.n = cur.n;
+  a.mask = mask;
+  a.hdr = 9;
+  a.epoch = epoch;
+  a.out = out;
+  return run_delta(a, s, st);
 }
 
 hipError_t launch_delta_apply(const gs_params& model, const gs_codec* codecs, const uint32_t* packet,

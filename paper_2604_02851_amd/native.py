@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS
 
 EXPORTED = ("gs_create", "gs_destroy", "gs_last_error", "gs_plan", "gs_frame_layout", "gs_workspace_init", "gs_project",
             "gs_build_tile_lists", "gs_composite", "gs_backward", "gs_adam_step", "gs_delta_extract",
-            "gs_delta_reset_baseline", "gs_codec_capacity_words", "gs_delta_encode", "gs_delta_apply", "gs_object_transform", "gs_relight_dc", "gs_append", "gs_freeze", "gs_sort_cells", "gs_assign_cells", "gs_visible_cells", "gs_set_precull",
+            "gs_delta_reset_baseline", "gs_codec_capacity_words", "gs_delta_encode", "gs_delta_encode_noalloc", "gs_delta_apply", "gs_object_transform", "gs_relight_dc", "gs_append", "gs_freeze", "gs_sort_cells", "gs_assign_cells", "gs_visible_cells", "gs_set_precull",
             "gs_workspace_segment", "gs_read_counters", "gs_step", "gs_step_capture",
             "gs_step_launch", "gs_profile_enable", "gs_profile_read", "gs_profile_reset")
 STAGES = ("project", "tile_lists", "composite", "composite_bwd", "project_bwd", "adam", "delta")
@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
         L.gs_codec_capacity_words.argtypes = [c_int32, c_int32, POINTER(GsCodec), c_uint32]
         L.gs_delta_encode.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), POINTER(GsCodec), c_uint32, c_void_p,
                                       c_void_p, c_int64, c_void_p, c_void_p]
+        L.gs_delta_encode_noalloc.argtypes = [ctx, POINTER(GsParams), POINTER(GsParams), POINTER(GsCodec), c_uint32,
+                                              c_void_p, c_void_p, c_int64, c_void_p]
         L.gs_delta_apply.argtypes = [ctx, POINTER(GsParams), POINTER(GsCodec), c_void_p, c_int64, c_void_p, c_void_p,
                                      c_void_p]
         L.gs_object_transform.argtypes = [ctx, POINTER(GsParams), c_void_p, c_void_p, c_int32, c_void_p]
@@ -309,6 +311,12 @@ class Context:
         c, b = cur.struct(), baseline.struct()
         self._chk(self.L.gs_delta_encode(self.h, ctypes.byref(c), ctypes.byref(b), codec_array(codecs), group_mask,
                                          ptr(dev_epoch), ptr(out), out.numel(), ptr(ws), stream_handle(stream)))
+
+    def delta_encode_noalloc(self, cur, baseline, codecs, group_mask, dev_epoch, out, stream=None):
+        c, b = cur.struct(), baseline.struct()
+        self._chk(self.L.gs_delta_encode_noalloc(self.h, ctypes.byref(c), ctypes.byref(b), codec_array(codecs),
+                                                 group_mask, ptr(dev_epoch), ptr(out), out.numel(),
+                                                 stream_handle(stream)))
 
     def delta_apply(self, model, codecs, packet, packet_words, dev_epoch, dev_status, stream=None):
         m = model.struct()
