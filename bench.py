@@ -32,6 +32,55 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_TEST = 12
 FLOPS_FWD_COMPOSITED = 12
 FLOPS_BWD_COMPOSITED = 55
+# The plain path: the same kernels, one view per launch, eager, 16x16 tiles,
+# batch depth 64, one pixel per thread, one workgroup per tile.
+PLAIN_SHAPE = dict(tile=(16, 16), batch_depth=64, pixels_per_thread=1, wave_w=16, schedule=0)
+
+
+def stage_floors(u: dict) -> dict:
+    """Algorithmic bytes and FP32 operations of each stage of one optimize
+    step, from the counts measured in the run (u: gaussians, pairs = views x
+    Gaussians, visible pairs, keys, examined and composited pairs, pixels,
+    trainable scalars, SH coefficient floats per Gaussian), and the stage's
+    time floor max(bytes / 8 TB/s, ops / 157.3 TFLOP/s) in ms.
+      project      params read once (4 B x floats per Gaussian); per visible
+                   pair a 48 B splat record and 16 B of depth key, tile
+                   rectangle and tile count; 4 B tile count per (view,
+                   Gaussian) pair; 8 B view mask per Gaussian
+      tile_lists   12 B read per visible pair; 12 B per key emitted and one
+                   permutation of the keys (24 B per key)
+      composite    40 B per key (index and splat record); 24 B written per
+                   pixel; 12 ops per examined and 12 per composited pair
+      composite_bwd 40 B per key; 32 B read per pixel; 12 ops per examined
+                   and 55 per composited pair (gradient atomics not counted)
+      project_bwd  36 B read per visible pair; params read and gradients
+                   written once per Gaussian
+      adam         28 B per trainable scalar"""
+    fl = u["floats_per_gaussian"]
+    st = {
+        "project": (4 * fl * u["gaussians"] + 64 * u["visible"] + 4 * u["pairs"] + 8 * u["gaussians"], 0),
+        "tile_lists": (12 * u["visible"] + 36 * u["keys"], 0),
+        "composite": (40 * u["keys"] + 24 * u["pixels"], FLOPS_TEST * u["examined"] + FLOPS_FWD_COMPOSITED * u["composited"]),
+        "composite_bwd": (40 * u["keys"] + 32 * u["pixels"],
+                          FLOPS_TEST * u["examined"] + FLOPS_BWD_COMPOSITED * u["composited"]),
+        "project_bwd": (36 * u["visible"] + 8 * fl * u["gaussians"], 0),
+        "adam": (28 * u["trainable"], 0),
+    }
+    out = {}
+    for k, (b, ops) in st.items():
+        t_b = b / (PEAK_HBM_GBS * 1e9) * 1e3
+        t_o = ops / (PEAK_FP32_TFLOPS * 1e12) * 1e3
+        out[k] = {"bytes": int(b), "ops": int(ops), "floor_ms": round(max(t_b, t_o), 5),
+                  "bound": "hbm" if t_b >= t_o else "alu"}
+    return out
+
+
+def roofline_fractions(floors: dict, stage_ms: dict, step_ms: float) -> dict:
+    """Per stage: floor / measured stage time; per step: sum of the floors /
+    measured step time."""
+    per = {k: round(f["floor_ms"] / stage_ms[k], 4) for k, f in floors.items() if stage_ms.get(k)}
+    total = sum(f["floor_ms"] for f in floors.values())
+    return {"per_stage": per, "step": round(total / step_ms, 4), "step_floor_ms": round(total, 4)}
 
 
 def log(*a):
@@ -63,11 +112,58 @@ def pair_counts(r, torch):
     return E, C
 
 
+def cpu_info() -> dict:
+    """Host CPU of this run: model name, logical CPUs and the ones this
+    process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "logical_cpus": os.cpu_count()}
+
+
+def single_core_oracle(cfgs=(1, 2), timeout: float = 120.0) -> dict:
+    """The oracle's optimize step (forward, L1 backward with projection
+    adjoint, Adam) on whole small workloads with one OpenMP thread, in a
+    child process (the thread count is fixed when the oracle library
+    loads)."""
+    import subprocess
+    code = ("import sys, time, numpy as np; sys.path.insert(0, %r)\n"
+            "from oracle import oracle as O\nfrom paper_2604_02851_amd import scenes as S\nO.lib()\n"
+            "for cfg in %r:\n"
+            "    w = S.workload(cfg); t = time.perf_counter()\n"
+            "    O.backward(w.scene, w.cams, np.full(3 * w.n_pixels, 0.5, np.float32), mode=1, loss_mode=1)\n"
+            "    for name, a in w.scene.tensors():\n"
+            "        z = np.zeros_like(a); O.adam(a, z, z, z, 1e-3, 0.9, 0.999, 1e-15, 1)\n"
+            "    print(cfg, time.perf_counter() - t, flush=True)\n") % (ROOT, tuple(cfgs))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=timeout)
+    except subprocess.TimeoutExpired:
+        return {}
+    out = {}
+    for line in r.stdout.split("\n"):
+        if line.strip():
+            cfg, sec = line.split()
+            out[f"cfg{cfg}"] = {"steps_per_s": round(1.0 / float(sec), 4), "seconds": round(float(sec), 3)}
+    return out
+
+
 def cpu_baseline(w, min_seconds: float):
     """Times the FP64 oracle's optimize step on whole views of the workload,
     in view order, until at least `min_seconds` have passed (forward,
     L1 backward with its projection adjoint, then Adam over all parameters),
-    and scales the view part to the step by pixel count."""
+    and scales the view part to the step by pixel count.  The oracle as it
+    stands: its backward also computes the tolerance bookkeeping the parity
+    tests use (magnitude and transmittance scales, decision slack)."""
     import numpy as np
     from oracle import oracle as O
     O.lib()
@@ -91,12 +187,16 @@ def cpu_baseline(w, min_seconds: float):
     t_adam = time.perf_counter() - t
     total_px = sum(int(c["width"]) * int(c["height"]) for c in w.cams)
     t_step = t_views * total_px / done_px + t_adam
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    info = cpu_info()
+    # the oracle's OpenMP loops run on OMP_NUM_THREADS threads when it is set,
+    # else on every usable CPU
+    cores = int(os.environ.get("OMP_NUM_THREADS") or info["nproc"] or 1)
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": cores, "kind": "oracle",
             "sample": (f"FP64 oracle step on views 0-{views - 1} of {len(w.cams)} ({done_px} of {total_px} px: "
-                       f"forward, L1 backward, projection adjoint of all {w.scene.n} Gaussians per view) "
-                       f"in {t_views:.1f} s, Adam over all parameters in {t_adam:.1f} s; view part scaled "
-                       f"by pixel count to {t_step:.1f} s per step")}
+                       f"forward, L1 backward, projection adjoint of all {w.scene.n} Gaussians per view, "
+                       f"including the oracle's tolerance bookkeeping) in {t_views:.1f} s, Adam over all "
+                       f"parameters in {t_adam:.1f} s; view part scaled by pixel count to {t_step:.1f} s per step"),
+            **info}
 
 
 def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log, frozen: float = 0.0) -> dict:
@@ -157,7 +257,8 @@ def stream_rate(shape: dict, steps: int, torch, log) -> dict:
     optimize step (graph replay), the sender encodes the groups due in that
     frame with the default codecs and schedule, and a receiver on the same
     GPU replays the packet (the full buffer is handed over: the header's
-    total bounds it).  Encode and replay are timed with events of their own."""
+    total bounds it).  Encode and replay are timed with events of their own,
+    after the step has finished."""
     from paper_2604_02851_amd import scenes as S
     from paper_2604_02851_amd import stream as ST
     from paper_2604_02851_amd.native import DeviceParams
@@ -184,6 +285,10 @@ def stream_rate(shape: dict, steps: int, torch, log) -> dict:
     words = []
     for k in range(steps):
         opt.replay()
+        # an event recorded right behind a graph launch can take its time
+        # stamp before the graph's last kernels end: wait for the step, so
+        # the events bracket the encoder and the replay alone
+        stream.synchronize()
         ev[k][0].record(stream)
         pk = snd.frame()
         ev[k][1].record(stream)
@@ -257,21 +362,28 @@ def dynamics_rate(shape: dict, steps: int, torch, log) -> dict:
     opt.step()
     torch.cuda.synchronize()
     opt.capture()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for k in range(steps):
-        ev[k][0].record(stream)
         r.ctx.object_transform(params, obj_dev, tfs[k], len(pivots), stream)
         r.ctx.relight_dc(params, gains[k], 1, stream)
-        ev[k][1].record(stream)
         opt.replay()
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    dyn_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
     if r.counters().overflow_any:
         raise SystemExit("dynamics: key capacity overflowed during the timed steps")
+    # the two dynamics kernels alone (after the timed steps, each call on an
+    # idle stream so that its events bracket only these kernels)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    for k in range(steps):
+        stream.synchronize()
+        ev[k][0].record(stream)
+        r.ctx.object_transform(params, obj_dev, tfs[k], len(pivots), stream)
+        r.ctx.relight_dc(params, gains[k], 1, stream)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    dyn_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
     add = DeviceParams.from_scene(S.draw_scene(rng, 100_000, 5.0, w.scene.sh_degree))
     n, na, k = params.n, opt.n_active, add.n
     new_p = DeviceParams.zeros(n + k, w.scene.sh_degree)
@@ -364,7 +476,8 @@ def main():
     ap.add_argument("--batch-depth", type=int, default=None)
     ap.add_argument("--ppt", type=int, default=None, help="pixels per thread (default: autotuned)")
     ap.add_argument("--wave-w", type=int, default=None, help="wave sub-tile width (default: autotuned)")
-    ap.add_argument("--schedule", type=int, default=None, help="tile schedule 0/1 (default: autotuned)")
+    ap.add_argument("--schedule", type=int, default=None,
+                    help="tile schedule 0-3 (2, 3: persistent work queue; default: autotuned)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time of the CPU baseline sample")
@@ -443,20 +556,22 @@ def main():
     log(f"[bench] batched graph: {ms_batched:.3f} ms/step ({1000 / ms_batched:.2f} steps/s), "
         f"wall {t_wall / args.steps * 1000:.3f} ms/step, loss {opt.loss.item():.5f}")
 
-    # ---- plain: same kernels, one view per launch, eager ----------------------
-    ms_plain = None
-    if args.plain_steps > 0:
-        opt.step(plain=True)
+    def time_plain(o, label):
+        o.step(plain=True)
         torch.cuda.synchronize()
         ev0.record(stream)
         for _ in range(args.plain_steps):
-            opt.step(plain=True)
+            o.step(plain=True)
         ev1.record(stream)
         torch.cuda.synchronize()
-        ms_plain = ev0.elapsed_time(ev1) / args.plain_steps
-        if r.counters().overflow_any:
+        ms = ev0.elapsed_time(ev1) / args.plain_steps
+        if o.r.counters().overflow_any:
             raise SystemExit("key capacity overflowed in the plain path")
-        log(f"[bench] plain eager: {ms_plain:.3f} ms/step ({1000 / ms_plain:.2f} steps/s)")
+        log(f"[bench] plain eager ({label}): {ms:.3f} ms/step ({1000 / ms:.2f} steps/s)")
+        return ms
+
+    # ---- plain with the tuned launch shape: one view per launch, eager -------
+    ms_plain_tuned = time_plain(opt, "tuned shape") if args.plain_steps > 0 else None
 
     # ---- stage timers (eager batched steps) -------------------------------
     r.ctx.profile(True)
@@ -470,6 +585,14 @@ def main():
     log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
     E, C = pair_counts(r, torch)
     c = r.counters()
+    floats = 14 + 3 * ((w.scene.sh_degree + 1) ** 2 - 1)
+    units = {"gaussians": w.scene.n, "pairs": w.scene.n * len(w.cams), "visible": int(c.visible),
+             "keys": int(c.keys), "examined": E, "composited": C, "pixels": w.n_pixels,
+             "trainable": floats * w.scene.n, "floats_per_gaussian": floats}
+    floors = stage_floors(units)
+    fractions = roofline_fractions(floors, stage_ms, ms_batched)
+    log("[bench] roofline fraction per stage: " + ", ".join(f"{k} {v:.3f}" for k, v in fractions["per_stage"].items())
+        + f"; step {fractions['step']:.3f} (sum of floors {fractions['step_floor_ms']:.3f} ms)")
     # dominant kernel and its roofline position
     dom = max(("composite", "composite_bwd"), key=lambda k: stage_ms.get(k, 0.0))
     per_c = FLOPS_FWD_COMPOSITED if dom == "composite" else FLOPS_BWD_COMPOSITED
@@ -490,16 +613,35 @@ def main():
                       "flops_per_examined": FLOPS_TEST, "flops_per_composited": per_c},
             "avg_ms": round(stage_ms[dom], 4)}
 
+    wave_w, schedule = r.wave_w, r.schedule
+    # ---- plain as defined for the metric: 16x16 tiles, batch depth 64 ----------
+    ms_plain = None
+    if args.plain_steps > 0:
+        plain_params = params.clone()
+        del opt, r
+        torch.cuda.empty_cache()
+        rp = Renderer(w.cams, w.scene.n, w.scene.sh_degree, loss_mode=1, **PLAIN_SHAPE)
+        rp.fit_capacity(pert)
+        rp.fit_capacity(plain_params)
+        # images do not depend on the launch shape: the same targets serve
+        optp = Optimizer(rp, plain_params, targets, stream=stream)
+        ms_plain = time_plain(optp, "16x16 tiles, batch depth 64")
+        del optp, rp, plain_params
+        torch.cuda.empty_cache()
+    else:
+        del opt, r
+
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         cpu = cpu_baseline(w, args.cpu_seconds)
-        log(f"[bench] cpu baseline {cpu['value']:.3g} steps/s ({time.perf_counter() - t:.1f} s)")
+        cpu["single_core"] = single_core_oracle()
+        log(f"[bench] cpu baseline {cpu['value']:.3g} steps/s on {cpu['cores']} threads ({cpu['cpu_model']}, "
+            f"nproc {cpu['nproc']}); single core: {cpu['single_core']} ({time.perf_counter() - t:.1f} s)")
 
-    wave_w, schedule = r.wave_w, r.schedule
     others = None
     if not args.no_configs:
-        del opt, r, targets, params, pert
+        del targets, params, pert
         torch.cuda.empty_cache()
         others = {f"cfg{k}": config_rate(k, shape, 10, 2, torch, log) for k in (1, 2, 3, 5)}
         # Gaussian freezing: cfg4 with half of the model in the frozen pool
@@ -528,9 +670,14 @@ def main():
                    "keys": int(c.keys), "visible_pairs": int(c.visible), "parallelism": "1 GPU"},
         "views_per_s": round(len(w.cams) * 1000.0 / ms_batched, 2),
         "plain": None if ms_plain is None else {"value": round(1000.0 / ms_plain, 3), "unit": "steps/s",
-                                                "ms_per_step": round(ms_plain, 4)},
+                                                "ms_per_step": round(ms_plain, 4),
+                                                "shape": "16x16 tiles, batch depth 64, 1 px/thread, eager, "
+                                                         "one view per launch"},
         "batched_over_plain": None if ms_plain is None else round(ms_plain / ms_batched, 3),
+        "plain_tuned_shape": None if ms_plain_tuned is None else {
+            "value": round(1000.0 / ms_plain_tuned, 3), "unit": "steps/s", "ms_per_step": round(ms_plain_tuned, 4)},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "roofline_stages": dict(fractions, floors=floors, units=units),
         "roofline": roof,
         "cpu_baseline": cpu,
         "other_workloads": others,

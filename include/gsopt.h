@@ -89,13 +89,21 @@ typedef struct {
 
 /* Rendering options fixed at plan time.
  *  tile_w, tile_h    : tile size in pixels, one of 8x8, 16x8, 16x16, 32x16, 32x32
- *  batch_depth       : splat records staged in LDS per batch: 32, 64 or 128
+ *  batch_depth       : splat records staged in LDS per batch: 32, 64, 128 or 256
  *  pixels_per_thread : 1, 2 or 4 (0 means 1); a workgroup has
  *                      tile_w*tile_h/pixels_per_thread threads
  *  wave_w            : width of the sub-tile one wavefront owns (0 = tile_w;
  *                      16 is also built for 32-wide tiles)
- *  schedule          : 0 = workgroups take tiles in row-major order;
- *                      1 = each XCD takes a contiguous run of tiles
+ *  schedule          : how the compositing kernels and their adjoint take
+ *                      the call's tiles (all views of the call together):
+ *                      0 = one workgroup per tile, tiles in row-major order;
+ *                      1 = one workgroup per tile, each XCD a contiguous run;
+ *                      2 = persistent: as many workgroups as are resident
+ *                          at once, each taking tiles from a work queue in
+ *                          row-major order until it is empty;
+ *                      3 = persistent, the queue handing out the tiles with
+ *                          the longest lists first (bucketed by the bit
+ *                          length of the list length)
  *  Unsupported combinations give GS_ERR_UNSUPPORTED; results do not depend on
  *  tile size, batch depth, pixels per thread, wave shape or schedule.
  *  bg                : background colour added with the final transmittance
@@ -438,8 +446,10 @@ gs_status gs_delta_reset_baseline(gs_ctx ctx, const gs_params* cur, const gs_par
  *   GS_SEG_RECORD  12 x f32 splat record (u_hi, w_hi, u_lo, w_lo, a, r, s, o,
  *                  red, green, blue, 0) with conic
  *                  P = -1/2 (a (dx + r dy)^2 + s dy^2)
- *   GS_SEG_GRAD2D  12 x f32, first 9 = dL/d(u, w, a, b, c, o, red, green, blue)
- *                  where (a, b, c) is the conic [[a, b], [b, c]]
+ *   GS_SEG_GRAD2D  9 planes of [VN] f32 (field f of pair v*n + i at
+ *                  f * VN + v*n + i, VN = n * planned views):
+ *                  dL/d(u, w, a, b, c, o, red, green, blue) where (a, b, c)
+ *                  is the conic [[a, b], [b, c]]; zero between steps
  * Per key / tile / pixel:
  *   GS_SEG_SORTED_VALUES  u32 v*n + i in (tile, depth, index) order for the
  *                         tile lists last built over [view_begin, +view_count)

@@ -133,7 +133,7 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   L.count = take(4 * vn);
   L.rect = take(8 * vn);
   L.rec = take(sizeof(float) * kRecFloats * vn);
-  L.g2 = take(sizeof(float) * kG2Stride * vn);
+  L.g2 = take(sizeof(float) * kG2Fields * vn);
   L.vis_a = take(4 * vn);
   L.vis_b = take(4 * vn);
   L.vkey_a = take(4 * vn);
@@ -148,6 +148,8 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   L.hist = take(4 * (256 * L.hist_blocks + 1));
   L.partial = take(4 * L.partial_len);
   L.ranges = take(8 * tiles);
+  L.order = take(4 * tiles);
+  L.obucket = take(4 * 128);
   L.last = take(4 * pixels);
   L.vmask = take(8 * n);
   L.dflags = take(n);
@@ -257,15 +259,15 @@ gs_status gs_plan(gs_ctx c, int32_t n, int32_t sh_degree, int32_t n_views, const
   if (!tile_ok(opts->tile_w, opts->tile_h))
     return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: tile %dx%d not built", opts->tile_w, opts->tile_h);
   const int bd = opts->batch_depth;
-  if (bd != 32 && bd != 64 && bd != 128)
-    return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: batch_depth=%d not in {32,64,128}", bd);
+  if (bd != 32 && bd != 64 && bd != 128 && bd != 256)
+    return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: batch_depth=%d not in {32,64,128,256}", bd);
   const int ppt = opts->pixels_per_thread == 0 ? 1 : opts->pixels_per_thread;
   const int wave_w = opts->wave_w == 0 ? opts->tile_w : opts->wave_w;
   if (!raster_variant_built(opts->tile_w, opts->tile_h, ppt, wave_w))
     return fail(c, GS_ERR_UNSUPPORTED, "gs_plan: %d pixels per thread with %d-wide wave tiles not built for %dx%d tiles",
                 ppt, wave_w, opts->tile_w, opts->tile_h);
-  if (opts->schedule != 0 && opts->schedule != 1)
-    return fail(c, GS_ERR_INVALID, "gs_plan: schedule=%d not in {0,1}", opts->schedule);
+  if (opts->schedule < 0 || opts->schedule > 3)
+    return fail(c, GS_ERR_INVALID, "gs_plan: schedule=%d not in {0,1,2,3}", opts->schedule);
   if (opts->loss_mode != 0 && opts->loss_mode != 1)
     return fail(c, GS_ERR_INVALID, "gs_plan: loss_mode=%d", opts->loss_mode);
   if (key_capacity < 1 || key_capacity > (int64_t)0x7fffffff)
@@ -345,7 +347,7 @@ gs_status gs_workspace_init(gs_ctx c, void* ws, hipStream_t st) {
   if (!c->plan.valid) return fail(c, GS_ERR_INVALID, "gs_workspace_init: no plan");
   if (!ws) return fail(c, GS_ERR_INVALID, "gs_workspace_init: null workspace");
   const Plan& pl = c->plan;
-  GS_HIP(c, launch_fill_u32(seg<uint32_t>(ws, pl.ws.g2), 0u, (int64_t)kG2Stride * pl.ws.vn, st));
+  GS_HIP(c, launch_fill_u32(seg<uint32_t>(ws, pl.ws.g2), 0u, (int64_t)kG2Fields * pl.ws.vn, st));
   GS_HIP(c, launch_fill_u32(seg<uint32_t>(ws, pl.ws.counters), 0u, (int64_t)(sizeof(Counters) / 4), st));
   return GS_OK;
 }
@@ -746,7 +748,7 @@ gs_status gs_workspace_segment(gs_ctx c, int32_t which, int32_t v0, int32_t nv, 
     case GS_SEG_COUNT: *offset = L.count; *bytes = 4 * vn; break;
     case GS_SEG_RECT: *offset = L.rect; *bytes = 8 * vn; break;
     case GS_SEG_RECORD: *offset = L.rec; *bytes = sizeof(float) * kRecFloats * vn; break;
-    case GS_SEG_GRAD2D: *offset = L.g2; *bytes = sizeof(float) * kG2Stride * vn; break;
+    case GS_SEG_GRAD2D: *offset = L.g2; *bytes = sizeof(float) * kG2Fields * vn; break;
     case GS_SEG_SORTED_VALUES:
       if (v0 < 0 || nv < 1 || v0 + nv > pl.n_views) return fail(c, GS_ERR_INVALID, "gs_workspace_segment: range");
       *offset = sorted_values_in_b(pl, v0, nv) ? L.vals_b : L.vals_a;

@@ -11,7 +11,7 @@ namespace gs {
 
 constexpr int kMaxViews = 256;
 constexpr int kRecFloats = 12;    // splat record: 3 x float4
-constexpr int kG2Stride = 12;     // screen-space gradient slots per (view, Gaussian)
+constexpr int kG2Fields = 9;      // screen-space gradient fields per (view, Gaussian), one plane each
 constexpr int kSortBlock = 256;   // threads of the sort / scan kernels
 constexpr int kSortItems = 16;    // keys per thread per chunk
 constexpr int kSortChunk = kSortBlock * kSortItems;
@@ -41,7 +41,7 @@ struct Counters {
   uint32_t key_cap;
   uint32_t kept;          // active count kept by the last freeze
   uint32_t overflow_any;  // set with overflow, cleared only by gs_read_counters / gs_workspace_init
-  uint32_t pad[2];
+  uint32_t queue[2];      // work queue of the persistent compositing kernels (zero between launches)
 };
 
 // Byte offsets of the workspace segments (computed by the host at plan time).
@@ -51,7 +51,7 @@ struct WsLayout {
   size_t count;       // u32 [VN]   tiles touched (0 = culled)
   size_t rect;        // u16x4 [VN] tile rectangle (tx0, ty0, tx1, ty1)
   size_t rec;         // float4x3 [VN] splat record
-  size_t g2;          // float x12 [VN] screen-space gradients
+  size_t g2;          // float [9][VN] screen-space gradients, field-major (one plane per field)
   size_t vis_a, vis_b, vkey_a, vkey_b;  // u32 [VN] visible ids / depth keys (sort ping-pong)
   size_t vrect_a, vrect_b;              // u16x4 [VN] tile rectangles carried through the depth sort
   size_t koff;        // u32 [VN+1] key offsets in depth order
@@ -59,6 +59,8 @@ struct WsLayout {
   size_t hist;        // u32 [256 * max_blocks + 1]
   size_t partial;     // u32 [scan partials]
   size_t ranges;      // u32x2 [tiles]
+  size_t order;       // u32 [tiles] compositing order of the tiles (longest lists first)
+  size_t obucket;     // u32 [64] list-length histogram and cursors of that order
   size_t last;        // u32 [pixels]
   size_t vmask;       // u64 [n] views of the last projection call that see the Gaussian
                       // (bit v - v0 when the call has at most 64 views, else all ones)

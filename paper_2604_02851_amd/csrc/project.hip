@@ -7,11 +7,12 @@
 // over the wavefronts through LDS.  One wavefront measured fastest: the
 // FP64 per-Gaussian set-up is then not repeated.
 //
-// The screen-space gradient slots are all zero between steps: the
-// workspace is cleared once (gs_workspace_init), the compositing adjoint
-// adds into the slots of visible pairs only, and the colour part of the
-// projection adjoint, which reads each visible pair's slots last, clears
-// them again.  Geometry (camera-space mean,
+// The screen-space gradients are nine field-major planes (field f of pair o
+// at f * VN + o), all zero between steps: the workspace is cleared once
+// (gs_workspace_init), the compositing adjoint adds into the fields of
+// visible pairs only, and each part of the projection adjoint clears the
+// fields it has read (the geometric part fields 0-5, the colour part 6-8),
+// so every field is read once and written back once.  Geometry (camera-space mean,
 // covariance, screen-space conic, projected mean, tile rectangle) is
 // evaluated in FP64: the projected mean feeds every pixel test at up to
 // 1920 px, where FP32 leaves ~1e-4 px of error; FP64 costs little here
@@ -351,8 +352,8 @@ struct ProjBwdArgs {
   int v0, nv;
   const uint32_t* count;
   const uint64_t* vmask;
-  const float4* g2;
-  float4* g2z;   // the same slots, cleared by k_color_bwd after reading
+  float* g2;          // field f of pair o at g2[f * g2_plane + o]
+  size_t g2_plane;
   float* gmean; float* glsc; float* gquat; float* gopac; float* gsh;
   int64_t n_active;   // gradients for Gaussians i < n_active, rows strided by n_active
   int accumulate;
@@ -376,8 +377,11 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
   const double iqn = g.ok ? 1.0 / g.qn : 0.0;
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
   for_seen_views(a.v0, a.nv, n, i, g.ok ? vm : 0ull, a.count, [&](int v, int64_t o) {
-    const float4 t0 = a.g2[o * 3 + 0], t1 = a.g2[o * 3 + 1];
-    const double gu = t0.x, gw = t0.y, ga = t0.z, gb = t0.w, gc = t1.x, gop = t1.y;
+    float* gp = a.g2 + o;
+    const size_t P = a.g2_plane;
+    const double gu = gp[0], gw = gp[P], ga = gp[2 * P], gb = gp[3 * P], gc = gp[4 * P], gop = gp[5 * P];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) gp[f * P] = 0.f;
     const gs_camera cam = a.cams[v];
     ViewGeom vg;
     view_geom(g, cam, vg);
@@ -504,11 +508,10 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
     }
 #define SH(k) sh_col[(k) * 64]
     for_seen_views(a.v0, a.nv, n, i, vm, a.count, [&](int v, int64_t o) {
-      const float* g2 = reinterpret_cast<const float*>(a.g2) + o * kG2Stride;
-      const float gcol[3] = {g2[6], g2[7], g2[8]};
-      static_assert(kG2Stride == 12, "three float4 slots per pair");
-      float4* slot = a.g2z + o * 3;
-      slot[0] = slot[1] = slot[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+      float* gp = a.g2 + o;
+      const size_t P = a.g2_plane;
+      const float gcol[3] = {gp[6 * P], gp[7 * P], gp[8 * P]};
+      gp[6 * P] = gp[7 * P] = gp[8 * P] = 0.f;
       float d[3], len;
       view_dir(a.cams[v], mu, d, &len);
       float Y[16];
@@ -595,8 +598,8 @@ hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camer
   a.nv = nv;
   a.count = seg<uint32_t>(ws, pl.ws.count);
   a.vmask = seg<uint64_t>(ws, pl.ws.vmask);
-  a.g2 = seg<float4>(ws, pl.ws.g2);
-  a.g2z = seg<float4>(ws, pl.ws.g2);
+  a.g2 = seg<float>(ws, pl.ws.g2);
+  a.g2_plane = (size_t)pl.ws.vn;
   a.gmean = grads.mean;
   a.glsc = grads.log_scale;
   a.gquat = grads.quat;

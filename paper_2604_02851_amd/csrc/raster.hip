@@ -196,6 +196,39 @@ __device__ __forceinline__ int reduce8_field(int lane, bool lo8) {
   return __builtin_ctz(bits | 256u) & 7;
 }
 
+// Work queue of the persistent compositing kernels.  head[0] counts the
+// positions handed out, head[1] the workgroups that found the queue empty;
+// the last of those resets both, so that the next launch starts from zero
+// (they start at zero when the workspace is initialised).  Position k is
+// tile order[k] of the call (longest lists first, schedule 3) or tile k.
+struct TileQueue {
+  uint32_t* head;
+  const uint32_t* order;
+};
+constexpr uint32_t kQueueDone = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t queue_next(const TileQueue& q, uint32_t ntiles, uint32_t* s_next) {
+  // every thread is done with the previous tile (its LDS and its position)
+  __syncthreads();
+  if (threadIdx.x == 0) *s_next = atomicAdd(q.head, 1u);
+  __syncthreads();
+  // uniform across the workgroup: kept in scalar registers, like blockIdx
+  const uint32_t k = __builtin_amdgcn_readfirstlane(*s_next);
+  if (k >= ntiles) return kQueueDone;
+  return q.order ? __builtin_amdgcn_readfirstlane(q.order[k]) : k;
+}
+
+__device__ __forceinline__ void queue_exit(const TileQueue& q) {
+  if (threadIdx.x == 0) {
+    // this workgroup's last atomicAdd on head[0] has returned: once every
+    // workgroup has counted itself here, nobody reads head[0] again
+    if (atomicAdd(q.head + 1, 1u) == gridDim.x - 1u) {
+      atomicExch(q.head, 0u);
+      atomicExch(q.head + 1, 0u);
+    }
+  }
+}
+
 struct CompArgs {
   const ViewInfo* views;
   const int32_t* tile_view;
@@ -211,15 +244,24 @@ struct CompArgs {
   uint32_t* last;
   uint32_t cap;
   float bg0, bg1, bg2;
+  TileQueue q;
 };
 
+// LDS of one compositing workgroup (forward).
+template <int BATCH, uint32_t H>
+struct FwdShared {
+  float4 rec[BATCH * 3];
+  uint32_t mask[BATCH * H];
+};
+
+// Forward compositing of tile `slot` of the call by the whole workgroup.
 template <int TW, int TH, int PPT, int SW, int BATCH>
-__global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
+__device__ __forceinline__ void composite_tile(const CompArgs& a, uint32_t slot,
+                                               FwdShared<BATCH, (Geom<TW, TH, PPT, SW>::NWAVES >= 2 ? 2u : 1u)>& sm) {
   using G = Geom<TW, TH, PPT, SW>;
   constexpr uint32_t kHalves = G::NWAVES >= 2 ? 2 : 1;
-  __shared__ float4 s_rec[BATCH * 3];
-  __shared__ uint32_t s_mask[BATCH * kHalves];
-  const uint32_t slot = tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule);
+  float4* s_rec = sm.rec;
+  uint32_t* s_mask = sm.mask;
   const int t = a.tile_begin + (int)slot;
   const ViewInfo view = a.views[a.tile_view[t]];
   const int local = t - view.tile_base;
@@ -328,6 +370,31 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
   }
 }
 
+// One workgroup per tile (schedules 0 and 1).
+template <int TW, int TH, int PPT, int SW, int BATCH>
+__global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
+  __shared__ FwdShared<BATCH, (Geom<TW, TH, PPT, SW>::NWAVES >= 2 ? 2u : 1u)> sm;
+  composite_tile<TW, TH, PPT, SW, BATCH>(a, tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule), sm);
+}
+
+// Persistent (schedules 2 and 3): as many workgroups as fit on the chip at
+// once, each taking the call's tiles from the work queue until it is empty.
+// The loop around the tile body costs the compiler a few registers; held to
+// the grid kernel's seven wavefronts per SIMD (a few bytes spilled) it
+// measured faster than at six.
+template <int TW, int TH, int PPT, int SW, int BATCH>
+__global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(7))) void k_composite_persistent(
+    CompArgs a) {
+  __shared__ FwdShared<BATCH, (Geom<TW, TH, PPT, SW>::NWAVES >= 2 ? 2u : 1u)> sm;
+  __shared__ uint32_t s_next;
+  for (;;) {
+    const uint32_t slot = queue_next(a.q, (uint32_t)a.ntiles, &s_next);
+    if (slot == kQueueDone) break;
+    composite_tile<TW, TH, PPT, SW, BATCH>(a, slot, sm);
+  }
+  queue_exit(a.q);
+}
+
 struct BwdArgs {
   const ViewInfo* views;
   const int32_t* tile_view;
@@ -343,12 +410,24 @@ struct BwdArgs {
   const float* up;
   int mode;
   int loss_mode;
-  float* g2;
+  float* g2;           // field f of pair o at g2[f * g2_plane + o]
+  size_t g2_plane;
   float* loss;
   uint32_t cap;
   float bg0, bg1, bg2;
   uint32_t n_gauss;    // Gaussians per view in the value index v * n_gauss + i
   uint32_t n_active;   // Gaussians i < n_active are trainable; the rest are frozen
+  TileQueue q;
+};
+
+// LDS of one compositing workgroup (adjoint).
+template <int BATCH, uint32_t H, bool MW>
+struct BwdShared {
+  float4 rec[BATCH * 3];
+  uint32_t mask[BATCH * H];
+  uint32_t id[BATCH];
+  float g[MW ? BATCH * 9 : 1];   // the batch's splat sums over the tile's wavefronts
+  uint32_t max_last;
 };
 
 // Adjoint of the compositing of one pixel, walked back to front from the
@@ -365,16 +444,19 @@ struct BwdArgs {
 // and 1 - alpha), which stays inside the same E_p = sum 1/(1 - alpha) bound
 // as the forward product's own rounding.
 template <int TW, int TH, int PPT, int SW, int BATCH>
-__global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
+using BwdSharedOf = BwdShared<BATCH, (Geom<TW, TH, PPT, SW>::NWAVES >= 2 ? 2u : 1u), (Geom<TW, TH, PPT, SW>::NWAVES > 1)>;
+
+// Adjoint of the compositing of tile `slot` of the call by the whole workgroup.
+template <int TW, int TH, int PPT, int SW, int BATCH>
+__device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t slot, BwdSharedOf<TW, TH, PPT, SW, BATCH>& sm) {
   using G = Geom<TW, TH, PPT, SW>;
   constexpr bool kMultiWave = G::NWAVES > 1;
   constexpr uint32_t kHalves = G::NWAVES >= 2 ? 2 : 1;
-  __shared__ float4 s_rec[BATCH * 3];
-  __shared__ uint32_t s_mask[BATCH * kHalves];
-  __shared__ uint32_t s_id[BATCH];
-  __shared__ float s_g[kMultiWave ? BATCH * 9 : 1];   // the batch's splat sums over the tile's wavefronts
-  __shared__ uint32_t s_max;
-  const uint32_t slot = tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule);
+  float4* s_rec = sm.rec;
+  uint32_t* s_mask = sm.mask;
+  uint32_t* s_id = sm.id;
+  float* s_g = sm.g;
+  uint32_t& s_max = sm.max_last;
   const int t = a.tile_begin + (int)slot;
   const ViewInfo view = a.views[a.tile_view[t]];
   const int local = t - view.tile_base;
@@ -535,9 +617,9 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
         if (writer && tot8 != 0.f) atomicAdd(dst + my_field, tot8);
         if (lane == 63 && tot9 != 0.f) atomicAdd(dst + 8, tot9);
       } else {
-        float* dst = a.g2 + (size_t)s_id[j] * kG2Stride;
-        if (writer && tot8 != 0.f) atomicAdd(dst + my_field, tot8);
-        if (lane == 63 && tot9 != 0.f) atomicAdd(dst + 8, tot9);
+        float* dst = a.g2 + s_id[j];
+        if (writer && tot8 != 0.f) atomicAdd(dst + (size_t)my_field * a.g2_plane, tot8);
+        if (lane == 63 && tot9 != 0.f) atomicAdd(dst + 8 * a.g2_plane, tot9);
       }
      }
     }
@@ -545,7 +627,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
     if (kMultiWave) {
       for (uint32_t q = threadIdx.x; q < cnt * 9; q += G::NT) {
         const float v = s_g[q];
-        if (v != 0.f) atomicAdd(&a.g2[(size_t)s_id[q / 9] * kG2Stride + (q % 9)], v);
+        if (v != 0.f) atomicAdd(&a.g2[(size_t)(q % 9) * a.g2_plane + s_id[q / 9]], v);
       }
       __syncthreads();
     }
@@ -555,6 +637,27 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
     lossv = wave_total_lane63(lossv);
     if (lane == 63 && lossv != 0.f) atomicAdd(a.loss, lossv);
   }
+}
+
+// One workgroup per tile (schedules 0 and 1).
+template <int TW, int TH, int PPT, int SW, int BATCH>
+__global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
+  __shared__ BwdSharedOf<TW, TH, PPT, SW, BATCH> sm;
+  composite_bwd_tile<TW, TH, PPT, SW, BATCH>(a, tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule), sm);
+}
+
+// Persistent (schedules 2 and 3), as k_composite_persistent.
+template <int TW, int TH, int PPT, int SW, int BATCH>
+__global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(7))) void k_composite_bwd_persistent(
+    BwdArgs a) {
+  __shared__ BwdSharedOf<TW, TH, PPT, SW, BATCH> sm;
+  __shared__ uint32_t s_next;
+  for (;;) {
+    const uint32_t slot = queue_next(a.q, (uint32_t)a.ntiles, &s_next);
+    if (slot == kQueueDone) break;
+    composite_bwd_tile<TW, TH, PPT, SW, BATCH>(a, slot, sm);
+  }
+  queue_exit(a.q);
 }
 
 // ---- dispatch over the built (tile, pixels-per-thread, batch) variants ----
@@ -576,28 +679,88 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_composite_bwd(BwdArgs a) {
   X(32, 32, 2, 16)        \
   X(32, 32, 4, 16)
 
-template <int TW, int TH, int PPT, int SW, typename Args>
-hipError_t launch_fwd(int batch, dim3 grid, hipStream_t st, const Args& a) {
-  constexpr int NT = TW * TH / PPT;
-  switch (batch) {
-    case 32: hipLaunchKernelGGL((k_composite<TW, TH, PPT, SW, 32>), grid, dim3(NT), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((k_composite<TW, TH, PPT, SW, 64>), grid, dim3(NT), 0, st, a); break;
-    case 128: hipLaunchKernelGGL((k_composite<TW, TH, PPT, SW, 128>), grid, dim3(NT), 0, st, a); break;
-    default: return hipErrorInvalidValue;
+// Workgroups of `kernel` (NT threads) resident on the whole device at once:
+// the grid of a persistent launch.  Queried once per kernel.
+template <typename K>
+hipError_t resident_workgroups(K kernel, int nt, int* out) {
+  static int cached = 0;
+  if (cached > 0) {
+    *out = cached;
+    return hipSuccess;
   }
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0);
+  if (e != hipSuccess) return e;
+  cached = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  *out = cached;
+  return hipSuccess;
+}
+
+template <typename K, typename Args>
+hipError_t launch_grid_or_persistent(K grid_kernel, K persistent_kernel, int nt, uint32_t ntiles, bool persistent,
+                                     hipStream_t st, const Args& a) {
+  if (!persistent) {
+    hipLaunchKernelGGL(grid_kernel, dim3(ntiles), dim3(nt), 0, st, a);
+    return hipGetLastError();
+  }
+  int res = 0;
+  const hipError_t e = resident_workgroups(persistent_kernel, nt, &res);
+  if (e != hipSuccess) return e;
+  const uint32_t g = ntiles < (uint32_t)res ? ntiles : (uint32_t)res;
+  hipLaunchKernelGGL(persistent_kernel, dim3(g), dim3(nt), 0, st, a);
   return hipGetLastError();
 }
 
 template <int TW, int TH, int PPT, int SW, typename Args>
-hipError_t launch_bwd(int batch, dim3 grid, hipStream_t st, const Args& a) {
+hipError_t launch_fwd(int batch, uint32_t ntiles, bool persistent, hipStream_t st, const Args& a) {
   constexpr int NT = TW * TH / PPT;
   switch (batch) {
-    case 32: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, SW, 32>), grid, dim3(NT), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, SW, 64>), grid, dim3(NT), 0, st, a); break;
-    case 128: hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPT, SW, 128>), grid, dim3(NT), 0, st, a); break;
+    case 32:
+      return launch_grid_or_persistent(k_composite<TW, TH, PPT, SW, 32>, k_composite_persistent<TW, TH, PPT, SW, 32>,
+                                       NT, ntiles, persistent, st, a);
+    case 64:
+      return launch_grid_or_persistent(k_composite<TW, TH, PPT, SW, 64>, k_composite_persistent<TW, TH, PPT, SW, 64>,
+                                       NT, ntiles, persistent, st, a);
+    case 128:
+      return launch_grid_or_persistent(k_composite<TW, TH, PPT, SW, 128>,
+                                       k_composite_persistent<TW, TH, PPT, SW, 128>, NT, ntiles, persistent, st, a);
+    case 256:
+      return launch_grid_or_persistent(k_composite<TW, TH, PPT, SW, 256>,
+                                       k_composite_persistent<TW, TH, PPT, SW, 256>, NT, ntiles, persistent, st, a);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+}
+
+template <int TW, int TH, int PPT, int SW, typename Args>
+hipError_t launch_bwd(int batch, uint32_t ntiles, bool persistent, hipStream_t st, const Args& a) {
+  constexpr int NT = TW * TH / PPT;
+  switch (batch) {
+    case 32:
+      return launch_grid_or_persistent(k_composite_bwd<TW, TH, PPT, SW, 32>,
+                                       k_composite_bwd_persistent<TW, TH, PPT, SW, 32>, NT, ntiles, persistent, st, a);
+    case 64:
+      return launch_grid_or_persistent(k_composite_bwd<TW, TH, PPT, SW, 64>,
+                                       k_composite_bwd_persistent<TW, TH, PPT, SW, 64>, NT, ntiles, persistent, st, a);
+    case 128:
+      return launch_grid_or_persistent(k_composite_bwd<TW, TH, PPT, SW, 128>,
+                                       k_composite_bwd_persistent<TW, TH, PPT, SW, 128>, NT, ntiles, persistent, st,
+                                       a);
+    case 256:
+      return launch_grid_or_persistent(k_composite_bwd<TW, TH, PPT, SW, 256>,
+                                       k_composite_bwd_persistent<TW, TH, PPT, SW, 256>, NT, ntiles, persistent, st,
+                                       a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// The work queue of a persistent launch (schedules 2 and 3) in the workspace.
+TileQueue tile_queue(const Plan& pl, void* ws) {
+  TileQueue q;
+  q.head = seg<Counters>(ws, pl.ws.counters)->queue;
+  q.order = pl.schedule == 3 ? seg<uint32_t>(ws, pl.ws.order) : nullptr;
+  return q;
 }
 
 void tile_span(const Plan& pl, int v0, int nv, int32_t* tb, int32_t* ntiles) {
@@ -645,11 +808,12 @@ hipError_t launch_composite(const Plan& pl, int v0, int nv, void* ws, float* img
   a.bg0 = pl.bg[0];
   a.bg1 = pl.bg[1];
   a.bg2 = pl.bg[2];
+  a.q = tile_queue(pl, ws);
   if (ntiles <= 0) return hipSuccess;
-  const dim3 grid(ntiles);
+  const bool persistent = pl.schedule >= 2;
   const int tw = pl.tile_w, th = pl.tile_h, ppt = pl.ppt, sw = pl.wave_w, b = pl.batch_depth;
 #define GS_FWD(W, H, P, S) \
-  if (tw == W && th == H && ppt == P && sw == S) return launch_fwd<W, H, P, S>(b, grid, st, a);
+  if (tw == W && th == H && ppt == P && sw == S) return launch_fwd<W, H, P, S>(b, (uint32_t)ntiles, persistent, st, a);
   GS_RASTER_LIST(GS_FWD)
 #undef GS_FWD
   return hipErrorInvalidValue;
@@ -676,16 +840,18 @@ hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const 
   a.mode = mode;
   a.loss_mode = pl.loss_mode;
   a.g2 = seg<float>(ws, pl.ws.g2);
+  a.g2_plane = (size_t)pl.ws.vn;
   a.loss = loss;
   a.cap = (uint32_t)pl.cap;
   a.bg0 = pl.bg[0];
   a.bg1 = pl.bg[1];
   a.bg2 = pl.bg[2];
+  a.q = tile_queue(pl, ws);
   if (ntiles <= 0) return hipSuccess;
-  const dim3 grid(ntiles);
+  const bool persistent = pl.schedule >= 2;
   const int tw = pl.tile_w, th = pl.tile_h, ppt = pl.ppt, sw = pl.wave_w, b = pl.batch_depth;
 #define GS_BWD(W, H, P, S) \
-  if (tw == W && th == H && ppt == P && sw == S) return launch_bwd<W, H, P, S>(b, grid, st, a);
+  if (tw == W && th == H && ppt == P && sw == S) return launch_bwd<W, H, P, S>(b, (uint32_t)ntiles, persistent, st, a);
   GS_RASTER_LIST(GS_BWD)
 #undef GS_BWD
   return hipErrorInvalidValue;

@@ -547,6 +547,52 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys, const uint
   }
 }
 
+// ---- longest-first tile order (persistent compositing, schedule 3) ----------
+// Tiles are bucketed by the bit length of their list length (0 for an empty
+// list), longer buckets first; within a bucket a workgroup's tiles keep
+// their row-major neighbourhood.  Only the order in which tiles are handed
+// out depends on it, never a result.
+constexpr int kOrderBuckets = 33;
+
+__device__ __forceinline__ uint32_t list_bucket(uint2 r) {
+  const uint32_t n = r.y > r.x ? r.y - r.x : 0u;
+  return 32u - (uint32_t)__clz(n);
+}
+
+__global__ __launch_bounds__(256) void k_order_hist(const uint2* ranges, uint32_t ntiles, uint32_t* bkt) {
+  __shared__ uint32_t h[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t < ntiles) atomicAdd(&h[list_bucket(ranges[t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && h[threadIdx.x] != 0u) atomicAdd(&bkt[threadIdx.x], h[threadIdx.x]);
+}
+
+// bkt[0..32]: tiles per bucket (complete); bkt[33..65]: cursors, zero at start
+__global__ __launch_bounds__(256) void k_order_scatter(const uint2* ranges, uint32_t ntiles, uint32_t* bkt,
+                                                       uint32_t* order) {
+  __shared__ uint32_t h[kOrderBuckets];
+  __shared__ uint32_t base[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  uint32_t b = 0, r = 0;
+  if (t < ntiles) {
+    b = list_bucket(ranges[t]);
+    r = atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && h[threadIdx.x] != 0u) {
+    const uint32_t me = threadIdx.x;
+    uint32_t start = 0;
+    for (uint32_t q = me + 1; q < (uint32_t)kOrderBuckets; ++q) start += bkt[q];
+    base[me] = start + atomicAdd(&bkt[kOrderBuckets + me], h[me]);
+  }
+  __syncthreads();
+  if (t < ntiles) order[base[b] + r] = t;
+}
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -673,6 +719,16 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   const uint32_t* sk = in_b ? keys_b : keys_a;
   const int64_t rblocks = cdiv(pl.cap, 1024) < 8192 ? cdiv(pl.cap, 1024) : 8192;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)rblocks), dim3(256), 0, st, sk, &ctr->keys, cap, tile_begin, ranges);
+  // 7. longest-first order of the call's tiles for the persistent compositing kernels
+  if (pl.schedule == 3 && ntiles > 0) {
+    uint32_t* bkt = seg<uint32_t>(ws, pl.ws.obucket);
+    e = launch_fill_u32(bkt, 0u, 2 * kOrderBuckets, st);
+    if (e != hipSuccess) return e;
+    const unsigned ob = (unsigned)cdiv(ntiles, 256);
+    hipLaunchKernelGGL(k_order_hist, dim3(ob), dim3(256), 0, st, ranges + tile_begin, (uint32_t)ntiles, bkt);
+    hipLaunchKernelGGL(k_order_scatter, dim3(ob), dim3(256), 0, st, ranges + tile_begin, (uint32_t)ntiles, bkt,
+                       seg<uint32_t>(ws, pl.ws.order));
+  }
   return hipGetLastError();
 }
 

@@ -359,15 +359,46 @@ class Optimizer:
 
 
 # ---------------------------------------------------------------------------
-# Autotuner: tile shape x batch depth, timed on the actual workload and cached
-# by (device arch, Gaussian-count bucket, view-set signature).
+# Autotuner: launch shape of the compositing kernels, timed on the actual
+# workload and cached by (device arch, Gaussian-count bucket, view-set
+# signature).
 # ---------------------------------------------------------------------------
-# (tile, batch depth, pixels per thread, wave sub-tile width, tile schedule)
-TUNE_CANDIDATES = [((16, 16), 64, 2, 16, 0), ((16, 16), 64, 4, 16, 0), ((32, 16), 128, 4, 32, 0),
-                   ((32, 16), 128, 4, 16, 0), ((32, 32), 64, 4, 32, 0), ((32, 32), 128, 4, 32, 0),
-                   ((32, 32), 128, 2, 16, 0), ((32, 32), 128, 4, 16, 0), ((32, 32), 64, 4, 16, 0),
-                   ((32, 32), 128, 4, 32, 1), ((32, 32), 128, 4, 16, 1)]
+# Built (tile, pixels per thread, wave sub-tile width) combinations, batch
+# depths and tile schedules (0/1: one workgroup per tile, row-major or
+# XCD-contiguous; 2/3: persistent workgroups on a work queue, row-major or
+# longest lists first).
+TUNE_SHAPES = (((8, 8), 1, 8), ((16, 8), 1, 16), ((16, 8), 2, 16), ((16, 16), 1, 16), ((16, 16), 2, 16),
+               ((16, 16), 4, 16), ((32, 16), 1, 32), ((32, 16), 2, 32), ((32, 16), 4, 32), ((32, 16), 2, 16),
+               ((32, 16), 4, 16), ((32, 32), 1, 32), ((32, 32), 2, 32), ((32, 32), 4, 32), ((32, 32), 2, 16),
+               ((32, 32), 4, 16))
+TUNE_BATCHES = (32, 64, 128, 256)
+TUNE_SCHEDULES = (0, 1, 2, 3)
 SHAPE_KEYS = ("tile", "batch_depth", "pixels_per_thread", "wave_w", "schedule")
+
+
+def tune_search(time_of, shapes=TUNE_SHAPES, batches=TUNE_BATCHES, schedules=TUNE_SCHEDULES, start_batch=64,
+                start_schedule=0, recheck: int = 3):
+    """Coordinate search over the launch shape: every (tile, pixels per
+    thread, wave width) at the starting batch depth and schedule, then every
+    batch depth for the best of those, then every schedule, then the
+    runners-up of the first stage again with the chosen batch depth and
+    schedule.  time_of(candidate) -> ms per step, candidate = (tile, batch
+    depth, pixels per thread, wave width, schedule); each candidate is timed
+    once.  Returns (best candidate, {candidate: ms})."""
+    times = {}
+
+    def t(c):
+        if c not in times:
+            times[c] = time_of(c)
+        return times[c]
+
+    stage1 = sorted(((tile, start_batch, ppt, sw, start_schedule) for tile, ppt, sw in shapes), key=t)
+    best = stage1[0]
+    best = min(((best[0], b, best[2], best[3], best[4]) for b in batches), key=t)
+    best = min(((best[0], best[1], best[2], best[3], sc) for sc in schedules), key=t)
+    for c in stage1[1:1 + recheck]:
+        t((c[0], best[1], c[2], c[3], best[4]))
+    return min(times, key=times.get), times
 
 
 def _tune_key(cams, n, sh_degree, device=0):
@@ -382,11 +413,11 @@ def _cache_path():
     return os.environ.get("GSOPT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "gsopt", "tune.json"))
 
 
-def autotune(cams, params: DeviceParams, target_params: DeviceParams, candidates=TUNE_CANDIDATES,
-             stream=None, steps: int = 2, log=print, use_cache: bool = True) -> dict:
-    """Times the batched optimize step for each launch shape and returns the
-    fastest as Renderer keyword arguments; the parameters given are not
-    modified."""
+def autotune(cams, params: DeviceParams, target_params: DeviceParams, stream=None, steps: int = 3, log=print,
+             use_cache: bool = True, **search) -> dict:
+    """Times the batched optimize step (eager, `steps` steps after one
+    warm-up) for the launch shapes tune_search visits and returns the fastest
+    as Renderer keyword arguments; the parameters given are not modified."""
     import json
     key = _tune_key(cams, params.n, params.sh_degree)
     path = _cache_path()
@@ -401,12 +432,12 @@ def autotune(cams, params: DeviceParams, target_params: DeviceParams, candidates
         res = {k: hit[k] for k in SHAPE_KEYS}
         res["tile"] = tuple(res["tile"])
         return dict(res, cached=True, times=hit.get("times"))
-    times = {}
-    ctx = None
-    for cand in candidates:
+    state = {"ctx": None}
+
+    def time_of(cand):
         shape = dict(zip(SHAPE_KEYS, cand))
-        r = Renderer(cams, params.n, params.sh_degree, loss_mode=1, ctx=ctx, **shape)
-        ctx = r.ctx
+        r = Renderer(cams, params.n, params.sh_degree, loss_mode=1, ctx=state["ctx"], **shape)
+        state["ctx"] = r.ctx
         r.fit_capacity(target_params)
         r.fit_capacity(params)
         targets = r.forward(target_params)[0].clone()
@@ -421,12 +452,14 @@ def autotune(cams, params: DeviceParams, target_params: DeviceParams, candidates
         e1.record(s)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        name = "{}x{}/{}/{}/{}/{}".format(*cand[0], *cand[1:])
-        times[name] = round(ms, 3)
-        log(f"[autotune] tile/batch/px-per-thread/wave-width/schedule {name}: {ms:.3f} ms/step")
+        log(f"[autotune] tile/batch/px-per-thread/wave-width/schedule {_shape_name(cand)}: {ms:.3f} ms/step")
         del opt, r, targets
-    best = candidates[min(range(len(candidates)), key=lambda i: list(times.values())[i])]
+        torch.cuda.empty_cache()
+        return ms
+
+    best, times = tune_search(time_of, **search)
     res = dict(zip(SHAPE_KEYS, best))
+    times = {_shape_name(c): round(ms, 3) for c, ms in times.items()}
     if use_cache:
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -435,3 +468,7 @@ def autotune(cams, params: DeviceParams, target_params: DeviceParams, candidates
         except OSError:
             pass
     return dict(res, cached=False, times=times)
+
+
+def _shape_name(c) -> str:
+    return "{}x{}/{}/{}/{}/{}".format(*c[0], *c[1:])

@@ -97,7 +97,7 @@ def test_tile_batch_and_thread_shape_invariance_bit_identical():
     P = DeviceParams.from_scene(w.scene)
     base = None
     for tile, ppt, sw in VARIANTS:
-        for batch, schedule in [(32, 0), (64, 1), (128, 0)]:
+        for batch, schedule in [(32, 0), (64, 1), (128, 2), (64, 3)]:
             r = renderer_for(w, tile=tile, batch=batch, ppt=ppt, wave_w=sw, schedule=schedule)
             img, T, nc = r.forward(P)
             cur = (img.cpu().numpy(), T.cpu().numpy(), nc.cpu().numpy())
@@ -111,13 +111,14 @@ def test_tile_batch_and_thread_shape_invariance_bit_identical():
 def test_unbuilt_launch_shape_is_refused():
     from paper_2604_02851_amd.native import GsError
     w = small(seed=104)
-    for kw in (dict(tile=(32, 32), ppt=8), dict(tile=(16, 16), ppt=4, wave_w=8), dict(tile=(16, 16), schedule=2)):
+    for kw in (dict(tile=(32, 32), ppt=8), dict(tile=(16, 16), ppt=4, wave_w=8), dict(tile=(16, 16), schedule=4)):
         with pytest.raises(GsError):
             renderer_for(w, **kw)
 
 
 @pytest.mark.parametrize("tile,ppt,sw,schedule", [((16, 16), 4, 16, 0), ((32, 32), 2, 32, 1), ((32, 16), 4, 32, 0),
-                                                   ((16, 8), 2, 16, 1), ((32, 32), 4, 16, 0), ((32, 16), 2, 16, 1)])
+                                                   ((16, 8), 2, 16, 1), ((32, 32), 4, 16, 0), ((32, 16), 2, 16, 1),
+                                                   ((32, 32), 4, 16, 2), ((16, 16), 2, 16, 3), ((8, 8), 1, 8, 3)])
 def test_backward_variants_match_oracle(oracle, tile, ppt, sw, schedule):
     w = small(seed=110, n=1200, sizes=((70, 50), (33, 64)))
     r = renderer_for(w, tile=tile, ppt=ppt, wave_w=sw, schedule=schedule)
@@ -167,11 +168,14 @@ def test_l1_backward_and_loss_match_oracle(oracle):
         assert abs(loss.item() - b.loss) <= 1e-5 * b.loss
 
 
-def test_batched_equals_plain(oracle):
+@pytest.mark.parametrize("schedule", [0, 3])
+def test_batched_equals_plain(oracle, schedule):
+    """One launch per stage for all views against one view per launch (for
+    the persistent schedules: a work queue drained and reset per launch)."""
     w = small(seed=107, n=1500)
     P = DeviceParams.from_scene(w.scene)
     G = torch.from_numpy(_up(w, 2)).cuda()
-    r = renderer_for(w)
+    r = renderer_for(w, schedule=schedule)
     img_b = r.forward(P)[0].clone()
     g_b = DeviceParams.zeros_like(P)
     r.backward(P, G, 0, g_b)

@@ -323,17 +323,22 @@ def test_config5_delta_after_dynamics_and_step(oracle):
         assert np.array_equal(a[1], b2[1])
 
 
-def test_graph_replay_matches_eager(oracle):
+@pytest.mark.parametrize("schedule", [0, 3])
+def test_graph_replay_matches_eager(oracle, schedule):
+    """Graph replays of the batched step against eager steps (schedule 3: the
+    persistent compositing kernels, whose work queue must be empty again at
+    the end of every replayed launch)."""
     w = S.small_workload(301, 3000, 1.0, 3, [(96, 64), (64, 96), (50, 50)], dist=3.0)
     pert = w.extra["perturbed"]
+    shape = dict(BENCH_SHAPE, schedule=schedule)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        r1 = Renderer(w.cams, w.scene.n, 3, loss_mode=1, **BENCH_SHAPE)
+        r1 = Renderer(w.cams, w.scene.n, 3, loss_mode=1, **shape)
         tgt = r1.forward(DeviceParams.from_scene(pert))[0].clone()
         Pe = DeviceParams.from_scene(w.scene)
         Pg = DeviceParams.from_scene(w.scene)
         r1.fit_capacity(Pe)
-        r2 = Renderer(w.cams, w.scene.n, 3, loss_mode=1, key_capacity=r1.key_capacity, **BENCH_SHAPE)
+        r2 = Renderer(w.cams, w.scene.n, 3, loss_mode=1, key_capacity=r1.key_capacity, **shape)
         eager = Optimizer(r1, Pe, tgt, stream=s)
         graph = Optimizer(r2, Pg, tgt, stream=s)
         graph.capture()
