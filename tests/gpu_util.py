@@ -8,13 +8,19 @@ IMG_TOL = 1e-5          # absolute per channel (FP32 image vs FP64 oracle)
 GRAD_REL = 1e-4         # relative
 GRAD_ABS = 1e-6         # absolute floor
 # FP32 accumulation allowance: |error| <= EPS_ACC * (sum of |terms|), the
-# oracle's magnitude scale; 2^-17 is ~128 units of FP32 rounding.
+# oracle's magnitude scale; 2^-17 is 128 units of FP32 rounding.  It covers
+# the per-term evaluation error (an alpha evaluated in FP32 is off by up to
+# ~14 units at the 3-sigma cut-off, where the exponent's argument is largest)
+# and the rounding of summing up to millions of terms in an order set by
+# atomics.
 EPS_ACC = 2.0 ** -17
-# FP32 transmittance allowance: alphas evaluated in FP32 carry a relative
-# error of up to ~16 units (exponent argument ~13.5 units at P = -4.5, exp and
-# product roundings), which the pixel's transmittance product amplifies by at
-# most E_p = sum 1/(1 - alpha); the oracle's depth-weighted scale carries E_p.
-EPS_T = 16 * 2.0 ** -24
+# FP32 transmittance allowance: the forward product of (1 - alpha) and the
+# adjoint's reciprocal chain leave each rebuilt transmittance within
+# c u E_p of its exact value, E_p = sum over the pixel's composited splats
+# of 1 / (1 - alpha); the float32 emulation of that arithmetic
+# (test_fp32_bounds) measures c <= 2.94, so 4 units are allowed.  The
+# oracle's depth-weighted scale carries E_p.
+EPS_T = 4 * 2.0 ** -24
 
 
 def renderer_for(w, tile=(16, 16), batch=64, bg=(0.0, 0.0, 0.0), loss_mode=0, cap=None, ppt=1, wave_w=0,
