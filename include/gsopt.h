@@ -506,6 +506,10 @@ typedef struct {
   float rel_tau;
   uint32_t* dev_delta_out;
   int64_t delta_cap_words;
+  const gs_adam_hparams* dev_hp;  /* optional (NULL: use hp): Adam hyper-parameters in device
+                                     memory, read by the update kernels each time the step runs,
+                                     so a captured step follows learning-rate changes the caller
+                                     writes there between replays (hp is then only validated) */
 } gs_step_args;
 
 /* Enqueues one optimize step: project, tile lists, composite, L1 backward
@@ -518,7 +522,9 @@ gs_status gs_step(gs_ctx ctx, const gs_step_args* args, hipStream_t stream);
 gs_status gs_step_capture(gs_ctx ctx, const gs_step_args* args, hipStream_t stream);
 
 /* Replays the captured graph.  Returns GS_ERR_STALE without launching if any
- * field of *args differs from the captured arguments or the plan changed. */
+ * field of *args differs from the captured arguments (hp excepted when
+ * dev_hp is set) or the plan changed.  Contents of device buffers (cameras,
+ * targets, dev_hp) may change between replays. */
 gs_status gs_step_launch(gs_ctx ctx, const gs_step_args* args, hipStream_t stream);
 
 #ifdef __cplusplus

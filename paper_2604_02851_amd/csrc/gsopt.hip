@@ -205,7 +205,8 @@ bool same_args(const gs_step_args& a, const gs_step_args& b) {
               same_params(a.adam_v, b.adam_v) && a.dev_cams == b.dev_cams && a.dev_target == b.dev_target &&
               a.dev_images == b.dev_images && a.dev_T_final == b.dev_T_final && a.dev_n_contrib == b.dev_n_contrib &&
               a.dev_loss == b.dev_loss && a.dev_step == b.dev_step && a.dev_workspace == b.dev_workspace &&
-              std::memcmp(&a.hp, &b.hp, sizeof(a.hp)) == 0 && a.plain == b.plain && a.do_delta == b.do_delta;
+              a.dev_hp == b.dev_hp && (a.dev_hp || std::memcmp(&a.hp, &b.hp, sizeof(a.hp)) == 0) &&
+              a.plain == b.plain && a.do_delta == b.do_delta;
   if (same && a.do_delta)
     same = same_params(a.baseline, b.baseline) && a.group_mask == b.group_mask && a.rel_tau == b.rel_tau &&
            a.dev_delta_out == b.dev_delta_out && a.delta_cap_words == b.delta_cap_words;
@@ -411,10 +412,11 @@ gs_status gs_backward(gs_ctx c, const gs_params* params, const gs_camera* cams, 
   return GS_OK;
 }
 
-gs_status gs_adam_step(gs_ctx c, const gs_params* p, const gs_params* g, const gs_params* m, const gs_params* v,
-                       int32_t* step, const gs_adam_hparams* hp, hipStream_t st) {
-  if (!c) return GS_ERR_INVALID;
-  c->err.clear();
+// Adam over the active pool; dev_hp (optional) makes the kernels read the
+// hyper-parameters from device memory when they run (hp is then only
+// validated as given).
+static gs_status adam_step(gs_ctx c, const gs_params* p, const gs_params* g, const gs_params* m, const gs_params* v,
+                           int32_t* step, const gs_adam_hparams* hp, const gs_adam_hparams* dev_hp, hipStream_t st) {
   if (!p || !g || !m || !v || !step || !hp) return fail(c, GS_ERR_INVALID, "gs_adam_step: null argument");
   const gs_params* all[4] = {p, g, m, v};
   for (int k = 0; k < 4; ++k) {
@@ -430,8 +432,15 @@ gs_status gs_adam_step(gs_ctx c, const gs_params* p, const gs_params* g, const g
   if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f && hp->eps >= 0.f))
     return fail(c, GS_ERR_INVALID, "gs_adam_step: betas must lie in [0,1) and eps >= 0");
   if (g->n == 0) return GS_OK;
-  GS_HIP(c, timed(c, ST_ADAM, st, [&] { return launch_adam(*p, *g, *m, *v, step, *hp, st); }));
+  GS_HIP(c, timed(c, ST_ADAM, st, [&] { return launch_adam(*p, *g, *m, *v, step, *hp, dev_hp, st); }));
   return GS_OK;
+}
+
+gs_status gs_adam_step(gs_ctx c, const gs_params* p, const gs_params* g, const gs_params* m, const gs_params* v,
+                       int32_t* step, const gs_adam_hparams* hp, hipStream_t st) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  return adam_step(c, p, g, m, v, step, hp, nullptr, st);
 }
 
 static gs_status check_grid(gs_ctx c, const gs_grid* g, const char* what) {
@@ -834,7 +843,7 @@ static gs_status run_step(gs_ctx c, const gs_step_args* a, hipStream_t st) {
                          a->dev_target, 1, &a->grads, k > 0 ? 1 : 0, a->dev_loss, st)) != GS_OK)
       return s;
   }
-  if ((s = gs_adam_step(c, &a->params, &a->grads, &a->adam_m, &a->adam_v, a->dev_step, &a->hp, st)) != GS_OK)
+  if ((s = adam_step(c, &a->params, &a->grads, &a->adam_m, &a->adam_v, a->dev_step, &a->hp, a->dev_hp, st)) != GS_OK)
     return s;
   if (a->do_delta) {
     if ((s = gs_delta_extract(c, &a->params, &a->baseline, a->group_mask, a->rel_tau, a->dev_delta_out,

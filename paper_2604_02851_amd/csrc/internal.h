@@ -168,7 +168,7 @@ hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const 
                                 const float* up, int mode, float* loss, int32_t n_active, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
 hipError_t launch_adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v,
-                       int32_t* step, const gs_adam_hparams& hp, hipStream_t st);
+                       int32_t* step, const gs_adam_hparams& hp, const gs_adam_hparams* dev_hp, hipStream_t st);
 hipError_t launch_assign_cells(const ParamPtrs& p, const gs_grid& g, uint32_t* cell_of, uint32_t* cell_sigma,
                                hipStream_t st);
 hipError_t launch_visible_cells(const gs_grid& g, const gs_camera* cams, int v0, int nv, const uint32_t* cell_sigma,

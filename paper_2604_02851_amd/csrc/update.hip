@@ -23,6 +23,7 @@ struct AdamArgs {
   int64_t row_chunks;  // chunks per row
   const int32_t* step;
   float beta1, beta2, eps;
+  const gs_adam_hparams* dev_hp;   // when set: hyper-parameters read here at run time instead
 };
 
 typedef float V4 __attribute__((ext_vector_type(4)));
@@ -43,19 +44,23 @@ __device__ __forceinline__ void adam_one(float& th, float g, float& m, float& v,
 // bias corrections are computed once per workgroup in FP64.
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   __shared__ float s_corr[2];
+  __shared__ float s_hp[4];   // this group's lr, beta1, beta2, eps
   int si = 0;
 #pragma unroll
   for (int q = 1; q < 6; ++q) si += (int64_t)blockIdx.x >= a.chunk0[q] ? 1 : 0;
   const AdamSeg s = a.seg[si];
   if (threadIdx.x == 0) {
+    const gs_adam_hparams* h = a.dev_hp;
+    const float lr = h ? h->lr[si] : s.lr, b1 = h ? h->beta1 : a.beta1, b2 = h ? h->beta2 : a.beta2;
+    s_hp[0] = lr, s_hp[1] = b1, s_hp[2] = b2, s_hp[3] = h ? h->eps : a.eps;
     const int t = *a.step + 1;
-    const double bc1 = 1.0 - pow((double)a.beta1, (double)t);
+    const double bc1 = 1.0 - pow((double)b1, (double)t);
     s_corr[0] = (float)bc1;
-    s_corr[1] = (float)(1.0 / sqrt(1.0 - pow((double)a.beta2, (double)t)));
+    s_corr[1] = (float)(1.0 / sqrt(1.0 - pow((double)b2, (double)t)));
   }
   __syncthreads();
-  const float step = s.lr / s_corr[0], rbc2 = s_corr[1];
-  const float b1 = a.beta1, b2 = a.beta2, c1 = 1.f - a.beta1, c2 = 1.f - a.beta2, eps = a.eps;
+  const float step = s_hp[0] / s_corr[0], rbc2 = s_corr[1];
+  const float b1 = s_hp[1], b2 = s_hp[2], c1 = 1.f - b1, c2 = 1.f - b2, eps = s_hp[3];
   const int64_t local = (int64_t)blockIdx.x - a.chunk0[si];
   const int64_t row = local / a.row_chunks, chunk = local - row * a.row_chunks;
   const int64_t k0 = chunk * kAdamChunk + (int64_t)threadIdx.x * kAdamVec;
@@ -393,7 +398,7 @@ __global__ void k_compact_words(const uint32_t* scratch, const uint32_t* pos, co
 }  // namespace
 
 hipError_t launch_adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v, int32_t* step,
-                       const gs_adam_hparams& hp, hipStream_t st) {
+                       const gs_adam_hparams& hp, const gs_adam_hparams* dev_hp, hipStream_t st) {
   const int64_t n = p.n, na = g.n;
   const int nk = (p.sh_degree + 1) * (p.sh_degree + 1);
   AdamArgs a;
@@ -413,6 +418,7 @@ hipError_t launch_adam(const gs_params& p, const gs_params& g, const gs_params& 
   a.beta1 = hp.beta1;
   a.beta2 = hp.beta2;
   a.eps = hp.eps;
+  a.dev_hp = dev_hp;
   a.chunk0[0] = 0;
   for (int q = 0; q < 6; ++q) a.chunk0[q + 1] = a.chunk0[q] + (int64_t)a.seg[q].rows * a.row_chunks;
   if (a.chunk0[6] > 0x7fffffffll) return hipErrorInvalidValue;

@@ -88,7 +88,7 @@ class GsStepArgs(ctypes.Structure):
                 ("dev_step", c_void_p), ("dev_workspace", c_void_p), ("hp", GsAdamHparams),
                 ("plain", c_int32), ("do_delta", c_int32), ("baseline", GsParams),
                 ("group_mask", c_uint32), ("rel_tau", c_float), ("dev_delta_out", c_void_p),
-                ("delta_cap_words", c_int64)]
+                ("delta_cap_words", c_int64), ("dev_hp", c_void_p)]
 
 
 _lib = None

@@ -232,8 +232,32 @@ class Optimizer:
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.lr, self.betas, self.eps = tuple(lr), tuple(betas), eps
         self.stream = stream
+        # the hyper-parameters also live in device memory (gs_adam_hparams
+        # layout), where the update kernels read them each time a step runs:
+        # set_hparams changes them without recapturing the step
+        self.hp_dev = torch.zeros(9, dtype=torch.float32, device=dev)
+        self._write_hparams()
         self.delta = None
         self._args_cache = {}
+
+    def _write_hparams(self):
+        host = torch.tensor(list(self.lr) + [self.betas[0], self.betas[1], self.eps], dtype=torch.float32)
+        with torch.cuda.stream(self.stream or torch.cuda.current_stream()):
+            self.hp_dev.copy_(host)
+
+    def set_hparams(self, lr=None, betas=None, eps=None):
+        """New learning rates (six groups), betas or eps for the following
+        steps, eager or replayed (enqueued on the optimizer's stream)."""
+        if lr is not None:
+            assert len(lr) == 6
+            self.lr = tuple(float(x) for x in lr)
+        if betas is not None:
+            self.betas = tuple(float(x) for x in betas)
+        if eps is not None:
+            self.eps = float(eps)
+        if not (all(0.0 <= b < 1.0 for b in self.betas) and self.eps >= 0.0):
+            raise ValueError("betas must lie in [0, 1) and eps >= 0")
+        self._write_hparams()
 
     def enable_delta(self, baseline: DeviceParams, group_mask: int = 0x3F, rel_tau: float = 1e-3):
         words = N.delta_capacity_words(self.params.n, self.params.sh_degree, group_mask)
@@ -256,6 +280,7 @@ class Optimizer:
         a.dev_step = N.ptr(self.step_count)
         a.dev_workspace = N.ptr(self.r.ws)
         a.hp = GsAdamHparams((N.c_float * 6)(*self.lr), self.betas[0], self.betas[1], self.eps)
+        a.dev_hp = N.ptr(self.hp_dev)
         a.plain = 1 if plain else 0
         if self.delta is not None:
             a.do_delta = 1

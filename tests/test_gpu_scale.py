@@ -367,3 +367,35 @@ def test_graph_replay_matches_eager(oracle, schedule):
         with pytest.raises(GsError) as e:
             graph.replay()
         assert e.value.status == GS_ERR_STALE
+
+
+def test_device_hparams_change_without_recapture():
+    """The captured step reads Adam's hyper-parameters from device memory:
+    after set_hparams with zero learning rates a replay leaves every
+    parameter bit-identical (and still advances the step counter), and
+    after restoring them a replay moves the model again, with no
+    recapture and no GS_ERR_STALE."""
+    from paper_2604_02851_amd.renderer import DEFAULT_LR
+    w = S.small_workload(302, 3000, 1.0, 3, [(96, 64), (50, 50)], dist=3.0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        r = Renderer(w.cams, w.scene.n, 3, loss_mode=1, **BENCH_SHAPE)
+        tgt = r.forward(DeviceParams.from_scene(w.extra["perturbed"]))[0].clone()
+        P = DeviceParams.from_scene(w.scene)
+        r.fit_capacity(P)
+        opt = Optimizer(r, P, tgt, stream=s)
+        opt.capture()
+        opt.replay()
+        s.synchronize()
+        before = [t.clone() for t in P.tensors()]
+        opt.set_hparams(lr=(0.0,) * 6)
+        opt.replay()
+        s.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(before, P.tensors()))
+        assert opt.step_count.item() == 2
+        opt.set_hparams(lr=DEFAULT_LR)
+        opt.replay()
+        s.synchronize()
+        assert opt.step_count.item() == 3
+        moved = sum(int((a != b).sum().item()) for a, b in zip(before, P.tensors()))
+        assert moved > 0.5 * sum(t.numel() for t in before)
