@@ -252,6 +252,113 @@ def config_rate(cfg: int, shape: dict, steps: int, warmup: int, torch, log, froz
     return out
 
 
+def oracle_step_seconds(w, runs: int) -> float:
+    """Median wall time of the FP64 oracle's whole optimize step on the
+    workload (forward, L1 backward against a constant target with the
+    projection adjoint, Adam over every parameter, and for the dynamics
+    workload the delta of all six groups), OpenMP on the host's cores."""
+    import numpy as np
+    from oracle import oracle as O
+    O.lib()
+    times = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        O.backward(w.scene, w.cams, np.full(3 * w.n_pixels, 0.5, np.float32), mode=1, loss_mode=1)
+        for name, a in w.scene.tensors():
+            z = np.zeros_like(a)
+            O.adam(a, z, z, z, 1e-3, 0.9, 0.999, 1e-15, 1)
+        if w.name == "cfg5":
+            O.delta(w.scene, w.scene, 0x3F, 1e-3)
+        times.append(time.perf_counter() - t)
+    return float(np.median(times))
+
+
+def table_row(cfg: int, shape: dict, torch, log, steps: int = 10, warmup: int = 2, plain_steps: int = 2,
+              oracle_runs: int = 1) -> dict:
+    """One row of the per-workload table: batched steps/s (graph replay,
+    `shape`), plain steps/s (one view per launch, eager, 16x16 tiles, batch
+    depth 64), views/s, the step's roofline fraction (sum of the stage
+    floors over the batched step time) and the oracle's steps/s."""
+    from paper_2604_02851_amd import scenes as S
+    from paper_2604_02851_amd.native import DeviceParams
+    from paper_2604_02851_amd.renderer import Optimizer, Renderer
+    import numpy as np
+    w = S.workload(cfg)
+    stream = torch.cuda.current_stream()
+    pert = w.extra.get("perturbed")
+    if cfg == 5:
+        S.Dynamics(w.extra["rng_dyn"], w.scene).step([w.scene, pert])
+    params = DeviceParams.from_scene(w.scene)
+
+    def setup(sh, p):
+        r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, loss_mode=1, **sh)
+        r.fit_capacity(p)
+        if pert is not None:
+            pdev = DeviceParams.from_scene(pert)
+            r.fit_capacity(pdev)
+            tg = r.forward(pdev)[0].clone()
+        else:
+            tg = torch.from_numpy(np.ascontiguousarray(w.extra["target"], np.float32).reshape(-1)).to(r.device)
+        o = Optimizer(r, p, tg, stream=stream)
+        if cfg == 5:
+            o.enable_delta(p.clone(), 0x3F, 1e-3)
+        return r, o
+
+    r, opt = setup(shape, params.clone())
+    opt.step()
+    torch.cuda.synchronize()
+    opt.capture()
+    for _ in range(warmup):
+        opt.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        opt.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / steps
+    r.ctx.profile(True)
+    r.ctx.profile_reset()
+    for _ in range(3):
+        opt.step()
+    stages = r.ctx.profile_read()
+    r.ctx.profile(False)
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1] > 0}
+    E, C = pair_counts(r, torch)
+    c = r.counters()
+    if c.overflow_any:
+        raise SystemExit(f"cfg{cfg}: key capacity overflowed")
+    floats = 14 + 3 * ((w.scene.sh_degree + 1) ** 2 - 1)
+    units = {"gaussians": w.scene.n, "pairs": w.scene.n * len(w.cams), "visible": int(c.visible),
+             "keys": int(c.keys), "examined": E, "composited": C, "pixels": w.n_pixels,
+             "trainable": floats * w.scene.n, "floats_per_gaussian": floats}
+    fr = roofline_fractions(stage_floors(units), stage_ms, ms_b)
+    del opt, r
+    torch.cuda.empty_cache()
+    rp, optp = setup(PLAIN_SHAPE, params.clone())
+    optp.step(plain=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(plain_steps):
+        optp.step(plain=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1) / plain_steps
+    if rp.counters().overflow_any:
+        raise SystemExit(f"cfg{cfg}: key capacity overflowed in the plain path")
+    del optp, rp
+    torch.cuda.empty_cache()
+    t_o = oracle_step_seconds(w, oracle_runs)
+    row = {"batched_steps_per_s": round(1000.0 / ms_b, 2), "plain_steps_per_s": round(1000.0 / ms_p, 2),
+           "batched_over_plain": round(ms_p / ms_b, 3), "views_per_s": round(len(w.cams) * 1000.0 / ms_b, 1),
+           "roofline_step": fr["step"], "roofline_per_stage": fr["per_stage"], "stages_ms": stage_ms,
+           "oracle_steps_per_s": round(1.0 / t_o, 5), "oracle_seconds": round(t_o, 2), "oracle_runs": oracle_runs,
+           "keys": int(c.keys), "visible_pairs": int(c.visible), "examined_pairs": E, "composited_pairs": C}
+    log(f"[table] cfg{cfg}: " + json.dumps(row))
+    return row
+
+
 def stream_rate(shape: dict, steps: int, torch, log) -> dict:
     """The streaming path on the 3M-Gaussian dynamics workload: after each
     optimize step (graph replay), the sender encodes the groups due in that
@@ -403,13 +510,18 @@ def dynamics_rate(shape: dict, steps: int, torch, log) -> dict:
     return out
 
 
-def rig_rate(precull: bool, grouped: bool, shape: dict, steps: int, warmup: int, torch, log) -> dict:
+def rig_rate(precull: bool, grouped: bool, shape: dict, steps: int, warmup: int, torch, log,
+             freeze_unseen: bool = False) -> dict:
     """Steps/s of a large-world workload: 2M Gaussians over an 80 x 8 x 80
     region seen from a rig of 8 outward-looking 1280x720 cameras at its
     centre spread over a 60-degree arc, with or without preculling by 4-unit
     grid cells (the cell assignment and per-view visibility are recomputed
     every step, inside the timed region), with the model in its generated
-    order or grouped by cell once before the timed steps."""
+    order or grouped by cell once before the timed steps.  freeze_unseen:
+    before the timed steps, the Gaussians of every cell that no view of the
+    rig can see move to the frozen pool (Gaussian freezing of the regions
+    away from the player), so Adam and the projection adjoint cover only the
+    part of the world in view."""
     from paper_2604_02851_amd import scenes as S
     from paper_2604_02851_amd.native import DeviceParams
     from paper_2604_02851_amd.renderer import Optimizer, Renderer
@@ -432,6 +544,19 @@ def rig_rate(precull: bool, grouped: bool, shape: dict, steps: int, warmup: int,
     s2 = torch.cuda.Stream()
     torch.cuda.synchronize()
     opt = Optimizer(r, params, targets, stream=s2)
+    frozen = 0
+    if freeze_unseen:
+        if r.precull is None:   # the cell mask of the current model, without preculling the steps
+            r.enable_precull(params, origin=(-40.0, -4.0, -40.0), cell_size=4.0, dims=(20, 2, 20))
+            r.disable_precull()
+        else:
+            r.update_precull(params)
+        seen = r.cell_mask.view(len(w.cams), -1).amax(0)
+        flags = (seen[r.cell_of[:params.n].long()] == 0).to(torch.uint8).contiguous()
+        torch.cuda.synchronize()
+        frozen = params.n - opt.freeze(flags)
+        if precull:
+            r.update_precull(params)
     opt.step()
     torch.cuda.synchronize()
     opt.capture()
@@ -455,11 +580,11 @@ def rig_rate(precull: bool, grouped: bool, shape: dict, steps: int, warmup: int,
     if r.counters().overflow_any:
         raise SystemExit("rig workload: key capacity overflowed during the timed steps")
     c = r.counters()
-    log(f"[bench] rig 2M/8 views/60deg, precull={precull}, grouped={grouped}: {ms:.3f} ms/step "
+    log(f"[bench] rig 2M/8 views/60deg, precull={precull}, grouped={grouped}, frozen {frozen}: {ms:.3f} ms/step "
         f"({1000 / ms:.2f} steps/s), visible pairs {int(c.visible)}")
     out = {"steps_per_s": round(1000.0 / ms, 3), "ms_per_step": round(ms, 4), "views": len(w.cams),
            "gaussians": w.scene.n, "precull": precull, "grouped_by_cell": grouped, "visible_pairs": int(c.visible),
-           "keys": int(c.keys)}
+           "keys": int(c.keys), "frozen_gaussians": frozen}
     del opt, r, params, targets
     torch.cuda.empty_cache()
     return out
@@ -483,6 +608,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time of the CPU baseline sample")
     ap.add_argument("--no-configs", action="store_true", help="skip the steps/s of the other workloads")
     ap.add_argument("--calib-copy", action="store_true", help="run only a plain 1 GiB device copy (PMC calibration)")
+    ap.add_argument("--table", action="store_true",
+                    help="instead of the benchmark line: one row per workload (batched and plain steps/s, views/s, "
+                         "step roofline fraction, oracle steps/s on the host cores)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the optimize step "
@@ -504,6 +632,18 @@ def main():
     from paper_2604_02851_amd import scenes as S
     from paper_2604_02851_amd.native import DeviceParams
     from paper_2604_02851_amd.renderer import SHAPE_KEYS, Optimizer, Renderer, autotune
+
+    if args.table:
+        stream = torch.cuda.Stream()      # graph capture needs a non-default stream
+        torch.cuda.set_stream(stream)
+        shape = dict(tile=(32, 32), batch_depth=64, pixels_per_thread=4, wave_w=16, schedule=0)
+        shape.update({k: v for k, v in dict(tile=args.tile and parse_tile(args.tile), batch_depth=args.batch_depth,
+                                            pixels_per_thread=args.ppt, wave_w=args.wave_w,
+                                            schedule=args.schedule).items() if v is not None})
+        rows = {f"cfg{k}": table_row(k, shape, torch, log, oracle_runs=3 if k <= 3 else 1) for k in (1, 2, 3, 4, 5)}
+        print(json.dumps({"table": rows, "shape": {k: (list(v) if k == "tile" else v) for k, v in shape.items()},
+                          "cpu": cpu_info(), "oracle_threads": os.environ.get("OMP_NUM_THREADS")}), flush=True)
+        return
 
     t0 = time.perf_counter()
     w = S.workload(args.config)
@@ -654,6 +794,9 @@ def main():
         others["rig2M"] = rig_rate(False, False, shape, 10, 2, torch, log)
         others["rig2M_grouped"] = rig_rate(False, True, shape, 10, 2, torch, log)
         others["rig2M_grouped_precull"] = rig_rate(True, True, shape, 10, 2, torch, log)
+        # the same with the Gaussians of the cells no view sees in the frozen pool
+        others["rig2M_grouped_frozen"] = rig_rate(False, True, shape, 10, 2, torch, log, freeze_unseen=True)
+        others["rig2M_grouped_frozen_precull"] = rig_rate(True, True, shape, 10, 2, torch, log, freeze_unseen=True)
 
     out = {
         "metric": METRIC, "value": round(1000.0 / ms_batched, 3), "unit": "steps/s", "n_gpus": 1,
