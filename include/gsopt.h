@@ -188,7 +188,8 @@ gs_status gs_build_tile_lists(gs_ctx ctx, int32_t view_begin, int32_t view_count
  * 1/255, stop once transmittance would fall below 1e-4.  Writes images
  * (planar CHW per view at 3*pixel_offsets[v]), final transmittance and
  * contributor count per pixel (at pixel_offsets[v]); keeps the last list
- * position internally for the backward pass. */
+ * position of each pixel and the strip bits of each list entry (which pixel
+ * strips its splat may reach) internally for the backward pass. */
 gs_status gs_composite(gs_ctx ctx, int32_t view_begin, int32_t view_count, void* dev_workspace,
                        float* dev_images, float* dev_T_final, uint32_t* dev_n_contrib,
                        hipStream_t stream);

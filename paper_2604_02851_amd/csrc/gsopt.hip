@@ -145,6 +145,7 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   L.keys_b = take(4 * cap);
   L.vals_a = take(4 * cap);
   L.vals_b = take(4 * cap);
+  L.strips = take(4 * (size_t)cap);
   L.hist = take(4 * (256 * L.hist_blocks + 1));
   L.partial = take(4 * L.partial_len);
   L.ranges = take(8 * tiles);

@@ -56,6 +56,7 @@ struct WsLayout {
   size_t vrect_a, vrect_b;              // u16x4 [VN] tile rectangles carried through the depth sort
   size_t koff;        // u32 [VN+1] key offsets in depth order
   size_t keys_a, keys_b, vals_a, vals_b;  // u32 [cap]
+  size_t strips;      // u32 [cap] strip bits of each list entry, stored by the forward compositing
   size_t hist;        // u32 [256 * max_blocks + 1]
   size_t partial;     // u32 [scan partials]
   size_t ranges;      // u32x2 [tiles]

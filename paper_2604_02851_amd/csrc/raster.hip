@@ -13,6 +13,10 @@
 // Forward: stops a pixel once its transmittance would fall below 1e-4 and
 // the workgroup once every pixel has stopped; saves T_final, the contributor
 // count and the last composited list position.
+// The forward stores each list entry's strip bits (which wavefront pixel
+// slots its splat may reach), and the backward stages them with the records
+// instead of testing the strips again: it only walks list positions before
+// the tile's largest last position, all of which the forward has staged.
 // Backward: walks the list back to front from each pixel's last position,
 // rebuilding the transmittance by division (FP32 reciprocal); a splat's screen-space
 // gradient is summed over the thread's pixels in registers, then over the
@@ -37,6 +41,10 @@ struct Geom {
                     NWAVES == WPR * (TH / WROWS),
                 "tile / pixels-per-thread / wave shape");
   static_assert(NWAVES * PPT <= 31, "one strip bit per wavefront and pixel slot, below the active bit");
+  // strip bits of the first half of the wavefronts (two threads share a
+  // splat's strip tests when the tile has several wavefronts)
+  static constexpr int HALF_BITS = (NWAVES >= 2 ? NWAVES / 2 : NWAVES) * PPT;
+  static_assert(HALF_BITS <= 16, "each half of the strip bits fits 16 bits");
 };
 
 // Workgroup -> tile.  Schedule 0: row-major tile order.  Schedule 1: each
@@ -242,6 +250,7 @@ struct CompArgs {
   float* T;
   uint32_t* ncontrib;
   uint32_t* last;
+  uint16_t* strips;   // per list position, two 16-bit halves: the staged splat's strip bits
   uint32_t cap;
   float bg0, bg1, bg2;
   TileQueue q;
@@ -298,8 +307,12 @@ __device__ __forceinline__ void composite_tile(const CompArgs& a, uint32_t slot,
         s_rec[j * 3 + 1] = halved_conic(r1);
         s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
       }
-      s_mask[u] = splat_strip_mask<G, SW, PPT>(r0, r1, tx * TW, ty * TH, (int)h * G::NWAVES / kHalves,
-                                               ((int)h + 1) * G::NWAVES / kHalves);
+      const uint32_t m = splat_strip_mask<G, SW, PPT>(r0, r1, tx * TW, ty * TH, (int)h * G::NWAVES / kHalves,
+                                                      ((int)h + 1) * G::NWAVES / kHalves);
+      s_mask[u] = m;
+      // for the adjoint: each half's bits, shifted to bit 0, in its own 16-bit slot
+      a.strips[2 * (b0 + j) + h] = (uint16_t)(m >> (h * G::HALF_BITS));
+      if (kHalves == 1) a.strips[2 * (b0 + j) + 1] = 0;
     }
     __syncthreads();
     // uniform: the splat walk below needs every lane (lane l reads splat
@@ -370,9 +383,11 @@ __device__ __forceinline__ void composite_tile(const CompArgs& a, uint32_t slot,
   }
 }
 
-// One workgroup per tile (schedules 0 and 1).
+// One workgroup per tile (schedules 0 and 1).  Held to seven wavefronts per
+// SIMD: the stores of the strip bits would otherwise cost the compiler the
+// few registers that take it to six.
 template <int TW, int TH, int PPT, int SW, int BATCH>
-__global__ __launch_bounds__(TW* TH / PPT) void k_composite(CompArgs a) {
+__global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(7))) void k_composite(CompArgs a) {
   __shared__ FwdShared<BATCH, (Geom<TW, TH, PPT, SW>::NWAVES >= 2 ? 2u : 1u)> sm;
   composite_tile<TW, TH, PPT, SW, BATCH>(a, tile_of_block(blockIdx.x, (uint32_t)a.ntiles, a.schedule), sm);
 }
@@ -408,6 +423,7 @@ struct BwdArgs {
   const float* T;
   const uint32_t* last;
   const float* up;
+  const uint32_t* strips;   // per list position: the forward's two 16-bit halves of the strip bits
   int mode;
   int loss_mode;
   float* g2;           // field f of pair o at g2[f * g2_plane + o]
@@ -421,10 +437,10 @@ struct BwdArgs {
 };
 
 // LDS of one compositing workgroup (adjoint).
-template <int BATCH, uint32_t H, bool MW>
+template <int BATCH, bool MW>
 struct BwdShared {
   float4 rec[BATCH * 3];
-  uint32_t mask[BATCH * H];
+  uint32_t mask[BATCH];
   uint32_t id[BATCH];
   float g[MW ? BATCH * 9 : 1];   // the batch's splat sums over the tile's wavefronts
   uint32_t max_last;
@@ -444,14 +460,13 @@ struct BwdShared {
 // and 1 - alpha), which stays inside the same E_p = sum 1/(1 - alpha) bound
 // as the forward product's own rounding.
 template <int TW, int TH, int PPT, int SW, int BATCH>
-using BwdSharedOf = BwdShared<BATCH, (Geom<TW, TH, PPT, SW>::NWAVES >= 2 ? 2u : 1u), (Geom<TW, TH, PPT, SW>::NWAVES > 1)>;
+using BwdSharedOf = BwdShared<BATCH, (Geom<TW, TH, PPT, SW>::NWAVES > 1)>;
 
 // Adjoint of the compositing of tile `slot` of the call by the whole workgroup.
 template <int TW, int TH, int PPT, int SW, int BATCH>
 __device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t slot, BwdSharedOf<TW, TH, PPT, SW, BATCH>& sm) {
   using G = Geom<TW, TH, PPT, SW>;
   constexpr bool kMultiWave = G::NWAVES > 1;
-  constexpr uint32_t kHalves = G::NWAVES >= 2 ? 2 : 1;
   float4* s_rec = sm.rec;
   uint32_t* s_mask = sm.mask;
   uint32_t* s_id = sm.id;
@@ -524,21 +539,16 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t sl
   for (uint32_t b_end = end_all; b_end > rg.x;) {
     const uint32_t b_begin = (b_end - rg.x > (uint32_t)BATCH) ? b_end - BATCH : rg.x;
     const uint32_t cnt = b_end - b_begin;
-    // two threads per splat share its strip tests (half the wavefronts each)
-    for (uint32_t u = threadIdx.x; u < cnt * kHalves; u += G::NT) {
-      const uint32_t j = u / kHalves, h = u % kHalves;
+    // records and the forward's strip bits; bit 31: the splat's Gaussian is
+    // trainable (frozen ones still shape T and S)
+    for (uint32_t j = threadIdx.x; j < cnt; j += G::NT) {
       const uint32_t id = a.vals[b_begin + j];
-      const float4 r0 = a.rec[(size_t)id * 3 + 0], r1 = a.rec[(size_t)id * 3 + 1];
-      if (h == 0) {
-        s_id[j] = id;
-        s_rec[j * 3 + 0] = r0;
-        s_rec[j * 3 + 1] = halved_conic(r1);
-        s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
-      }
-      // bit 31: the splat's Gaussian is trainable (frozen ones still shape T and S)
-      s_mask[u] = splat_strip_mask<G, SW, PPT>(r0, r1, tx * TW, ty * TH, (int)h * G::NWAVES / kHalves,
-                                               ((int)h + 1) * G::NWAVES / kHalves) |
-                  (h == 0 && id % a.n_gauss < a.n_active ? kActiveBit : 0u);
+      s_id[j] = id;
+      s_rec[j * 3 + 0] = a.rec[(size_t)id * 3 + 0];
+      s_rec[j * 3 + 1] = halved_conic(a.rec[(size_t)id * 3 + 1]);
+      s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
+      const uint32_t h2 = a.strips[b_begin + j];
+      s_mask[j] = (h2 & 0xffffu) | ((h2 >> 16) << G::HALF_BITS) | (id % a.n_gauss < a.n_active ? kActiveBit : 0u);
     }
     if (kMultiWave)
       for (uint32_t q = threadIdx.x; q < cnt * 9; q += G::NT) s_g[q] = 0.f;
@@ -549,7 +559,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t sl
     // the wavefront then visits only the splats that touch one of its strips
     for (int base = j_hi; base >= 0; base -= 64) {
      const int jl = base - lane;
-     const uint32_t mw = jl >= 0 ? strip_word<kHalves>(s_mask, (uint32_t)jl) : 0u;
+     const uint32_t mw = jl >= 0 ? s_mask[jl] : 0u;
      uint64_t pend = __ballot(((mw >> (wave * PPT)) & ((1u << PPT) - 1u)) != 0u);
      while (pend != 0ull) {
       const int l = __builtin_ctzll(pend);
@@ -804,6 +814,7 @@ hipError_t launch_composite(const Plan& pl, int v0, int nv, void* ws, float* img
   a.T = T;
   a.ncontrib = nc;
   a.last = seg<uint32_t>(ws, pl.ws.last);
+  a.strips = seg<uint16_t>(ws, pl.ws.strips);
   a.cap = (uint32_t)pl.cap;
   a.bg0 = pl.bg[0];
   a.bg1 = pl.bg[1];
@@ -837,6 +848,7 @@ hipError_t launch_composite_bwd(const Plan& pl, int v0, int nv, void* ws, const 
   a.T = T;
   a.last = seg<uint32_t>(ws, pl.ws.last);
   a.up = up;
+  a.strips = seg<uint32_t>(ws, pl.ws.strips);
   a.mode = mode;
   a.loss_mode = pl.loss_mode;
   a.g2 = seg<float>(ws, pl.ws.g2);
