@@ -273,15 +273,16 @@ def oracle_step_seconds(w, runs: int) -> float:
     return float(np.median(times))
 
 
-def table_row(cfg: int, shape: dict, torch, log, steps: int = 10, warmup: int = 2, plain_steps: int = 2,
+def table_row(cfg: int, shape: dict | None, torch, log, steps: int = 10, warmup: int = 2, plain_steps: int = 2,
               oracle_runs: int = 1) -> dict:
     """One row of the per-workload table: batched steps/s (graph replay,
-    `shape`), plain steps/s (one view per launch, eager, 16x16 tiles, batch
-    depth 64), views/s, the step's roofline fraction (sum of the stage
-    floors over the batched step time) and the oracle's steps/s."""
+    `shape`, or the autotuner's shape for this workload when None), plain
+    steps/s (one view per launch, eager, 16x16 tiles, batch depth 64),
+    views/s, the step's roofline fraction (sum of the stage floors over the
+    batched step time) and the oracle's steps/s."""
     from paper_2604_02851_amd import scenes as S
     from paper_2604_02851_amd.native import DeviceParams
-    from paper_2604_02851_amd.renderer import Optimizer, Renderer
+    from paper_2604_02851_amd.renderer import SHAPE_KEYS, Optimizer, Renderer, autotune
     import numpy as np
     w = S.workload(cfg)
     stream = torch.cuda.current_stream()
@@ -289,6 +290,11 @@ def table_row(cfg: int, shape: dict, torch, log, steps: int = 10, warmup: int = 
     if cfg == 5:
         S.Dynamics(w.extra["rng_dyn"], w.scene).step([w.scene, pert])
     params = DeviceParams.from_scene(w.scene)
+    if shape is None:
+        tgt_params = DeviceParams.from_scene(pert) if pert is not None else params
+        tuned = autotune(w.cams, params, tgt_params, stream=stream, log=log)
+        shape = {k: tuned[k] for k in SHAPE_KEYS}
+        del tgt_params
 
     def setup(sh, p):
         r = Renderer(w.cams, w.scene.n, w.scene.sh_degree, loss_mode=1, **sh)
@@ -350,7 +356,8 @@ def table_row(cfg: int, shape: dict, torch, log, steps: int = 10, warmup: int = 
     del optp, rp
     torch.cuda.empty_cache()
     t_o = oracle_step_seconds(w, oracle_runs)
-    row = {"batched_steps_per_s": round(1000.0 / ms_b, 2), "plain_steps_per_s": round(1000.0 / ms_p, 2),
+    row = {"shape": {k: (list(v) if k == "tile" else v) for k, v in shape.items()},
+           "batched_steps_per_s": round(1000.0 / ms_b, 2), "plain_steps_per_s": round(1000.0 / ms_p, 2),
            "batched_over_plain": round(ms_p / ms_b, 3), "views_per_s": round(len(w.cams) * 1000.0 / ms_b, 1),
            "roofline_step": fr["step"], "roofline_per_stage": fr["per_stage"], "stages_ms": stage_ms,
            "oracle_steps_per_s": round(1.0 / t_o, 5), "oracle_seconds": round(t_o, 2), "oracle_runs": oracle_runs,
@@ -636,13 +643,16 @@ def main():
     if args.table:
         stream = torch.cuda.Stream()      # graph capture needs a non-default stream
         torch.cuda.set_stream(stream)
-        shape = dict(tile=(32, 32), batch_depth=64, pixels_per_thread=4, wave_w=16, schedule=0)
-        shape.update({k: v for k, v in dict(tile=args.tile and parse_tile(args.tile), batch_depth=args.batch_depth,
-                                            pixels_per_thread=args.ppt, wave_w=args.wave_w,
-                                            schedule=args.schedule).items() if v is not None})
+        manual = {k: v for k, v in dict(tile=args.tile and parse_tile(args.tile), batch_depth=args.batch_depth,
+                                        pixels_per_thread=args.ppt, wave_w=args.wave_w,
+                                        schedule=args.schedule).items() if v is not None}
+        shape = None   # each workload with its own autotuned launch shape
+        if manual or args.no_autotune:
+            shape = dict(tile=(32, 32), batch_depth=64, pixels_per_thread=4, wave_w=16, schedule=0)
+            shape.update(manual)
         rows = {f"cfg{k}": table_row(k, shape, torch, log, oracle_runs=3 if k <= 3 else 1) for k in (1, 2, 3, 4, 5)}
-        print(json.dumps({"table": rows, "shape": {k: (list(v) if k == "tile" else v) for k, v in shape.items()},
-                          "cpu": cpu_info(), "oracle_threads": os.environ.get("OMP_NUM_THREADS")}), flush=True)
+        print(json.dumps({"table": rows, "cpu": cpu_info(), "oracle_threads": os.environ.get("OMP_NUM_THREADS")}),
+              flush=True)
         return
 
     t0 = time.perf_counter()
