@@ -119,14 +119,19 @@ struct SplatGeom {
 };
 
 // The compositing kernels stage each record with the conic's a and s already
-// multiplied by -1/2 (halved_conic), so that P = (-a/2 e) e + (-s/2) dy^2 needs
-// no final scaling: multiplying by -1/2 is exact and commutes with every
-// rounding here, so P is bit for bit the value of -1/2 (a e^2 + s dy^2).
+// multiplied by -log2(e)/2 (halved_conic), so that the power comes out in
+// base 2, P2 = (-L a/2 e) e + (-L s/2) dy^2 = log2(e) P up to rounding, which
+// the hardware exp2 takes directly.  The 3-sigma test compares P2 with
+// fl(-4.5 log2(e)); it can decide differently from P >= -4.5 only where P lies
+// within a few units of rounding of the cut-off.
+constexpr float kLog2e = 1.44269504088896341f;
+constexpr float kHalfLog2e = -0.5f * kLog2e;   // exact: a power-of-two multiple
+constexpr float kCutoff2 = kCutoff * kLog2e;
 __device__ __forceinline__ float4 halved_conic(const float4& r1) {
-  return make_float4(-0.5f * r1.x, r1.y, -0.5f * r1.z, r1.w);
+  return make_float4(kHalfLog2e * r1.x, r1.y, kHalfLog2e * r1.z, r1.w);
 }
 
-// r1h: the record's second float4 after halved_conic
+// r1h: the record's second float4 after halved_conic; P is the base-2 power
 __device__ __forceinline__ SplatGeom splat_power(float pxc, float pyc, const float4& r0, const float4& r1h) {
 #pragma clang fp contract(off)
   SplatGeom g;
@@ -137,11 +142,11 @@ __device__ __forceinline__ SplatGeom splat_power(float pxc, float pyc, const flo
   return g;
 }
 
-// Opacity part, for a pixel that passed the 3-sigma test (P >= kCutoff):
-// returns whether alpha reaches the 1/255 skip threshold.
-__device__ __forceinline__ bool splat_alpha(float P, float opacity, float& G, float& alpha, bool& clamped) {
+// Opacity part, for a pixel that passed the 3-sigma test (base-2 power
+// P2 >= kCutoff2): returns whether alpha reaches the 1/255 skip threshold.
+__device__ __forceinline__ bool splat_alpha(float P2, float opacity, float& G, float& alpha, bool& clamped) {
 #pragma clang fp contract(off)
-  G = __builtin_amdgcn_exp2f(P * 1.44269504088896341f);
+  G = __builtin_amdgcn_exp2f(P2);
   const float oG = opacity * G;
   clamped = oG >= kAlphaMax;
   alpha = clamped ? kAlphaMax : oG;

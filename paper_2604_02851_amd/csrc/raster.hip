@@ -341,7 +341,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& a, uint32_t slot,
           if (!((qb >> q) & 1u)) continue;   // uniform: the splat misses this pixel slot's strip
           const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
           const SplatGeom sg = splat_power(pxc, pyc, r0, r1);
-          const bool cand = T[q] > 0.f && sg.P >= kCutoff;
+          const bool cand = T[q] > 0.f && sg.P >= kCutoff2;
           if (__ballot(cand) == 0ull) continue;   // uniform: no lane of this row slot is near the splat
           float Gs, al;
           bool clamped;
@@ -486,10 +486,12 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t sl
   const bool lo8 = (lane & 8) == 0;
   const int my_field = reduce8_field(lane, lo8);
   const bool writer = (lane & 7) == 0;
-  // constant factors left out of the per-pixel sums, powers of two (exact):
-  // fields 0, 1 were summed with the halved conic, fields 2-4 without
-  // d P / d conic's factors -1/2, -1, -1/2
-  const float unhalve = my_field < 2 ? -2.f : my_field == 3 ? -1.f : my_field < 5 ? -0.5f : 1.f;
+  // constant factors left out of the per-pixel sums: fields 0, 1 were summed
+  // with the staged conic, which carries -log2(e)/2 (undone by -2 ln 2, one
+  // rounding of the total), fields 2-4 without d P / d conic's factors -1/2,
+  // -1, -1/2 (powers of two, exact)
+  constexpr float kMinus2Ln2 = -1.38629436111989061f;
+  const float unhalve = my_field < 2 ? kMinus2Ln2 : my_field == 3 ? -1.f : my_field < 5 ? -0.5f : 1.f;
   if (threadIdx.x == 0) s_max = rg.x;
   __syncthreads();
   float G0[PPT], G1[PPT], G2[PPT], SG[PPT];
@@ -582,7 +584,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t sl
         if (!((qb >> q) & 1u) || pos >= qlast[q]) continue;
         const float pyc = (float)(py0 + q * G::LROWS) + 0.5f;
         const SplatGeom sg = splat_power(pxc, pyc, r0, r1);
-        const bool cand = pos < last[q] && sg.P >= kCutoff;
+        const bool cand = pos < last[q] && sg.P >= kCutoff2;
         if (__ballot(cand) == 0ull) continue;   // uniform
         float Gs, al;
         bool clamped;
@@ -607,7 +609,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t sl
         SG[q] = fmaf(alt, diff, SG[q]);
         const float dLdP = dLda * alt;
         g[5] = fmaf(dLda, Gs, g[5]);
-        // with the halved conic, fields 0 and 1 collect -1/2 of their sums
+        // with the staged conic, fields 0 and 1 collect -log2(e)/2 of their sums
         const float ae = r1.x * sg.e;
         g[0] = fmaf(dLdP, ae, g[0]);
         g[1] = fmaf(dLdP, fmaf(ae, r1.y, r1.z * sg.dy), g[1]);
