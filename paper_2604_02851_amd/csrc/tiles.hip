@@ -1,5 +1,6 @@
-// Tile lists: visible compaction, depth pre-sort, key emission, radix sort by
-// tile, per-tile ranges.
+// Tile lists: depth pre-sort of the visible pairs (its first pass takes them
+// from the dense (view, Gaussian) arrays, compacting as it sorts), key
+// emission, radix sort by tile, per-tile ranges.
 //
 // Order required by the compositing rule: within a tile, splats ascend by
 // (FP32 depth bits, Gaussian index).  Instead of sorting one 64-bit
@@ -217,22 +218,6 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
   if (i < count) p[i] = value;
 }
 
-// ---- visible compaction -----------------------------------------------------
-__global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* count, const uint32_t* depth,
-                                                         const uint2* rect, const uint32_t* pos, int64_t base,
-                                                         int64_t len, uint32_t* vis_ids, uint32_t* vis_keys,
-                                                         uint2* vis_rect) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= len) return;
-  if (count[base + k] != 0u) {
-    const uint32_t p = pos[k];
-    vis_ids[p] = (uint32_t)(base + k);
-    vis_keys[p] = __builtin_nontemporal_load(depth + base + k);
-    const uint32_t* rp = reinterpret_cast<const uint32_t*>(rect + base + k);
-    vis_rect[p] = make_uint2(__builtin_nontemporal_load(rp), __builtin_nontemporal_load(rp + 1));
-  }
-}
-
 // ---- radix sort (LSD, 8-bit digits, stable) ---------------------------------
 // Digit counts of kHistChunks consecutive chunks per workgroup, one chunk
 // after the other; each thread loads its kSortItems keys of a chunk with
@@ -243,8 +228,11 @@ __global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* count, 
 // digit's kHistChunks counts as one contiguous run.
 constexpr int kHistChunks = 4;
 
-__global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, int64_t max_count, const uint32_t* dcount,
-                                                  int shift, int64_t nblocks, uint32_t* hist) {
+// With `valid` (the first depth pass, reading the dense (view, Gaussian)
+// arrays), key k counts only where valid[k] != 0: the pass then compacts the
+// visible pairs as it sorts them.
+__global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, const uint32_t* valid, int64_t max_count,
+                                                  const uint32_t* dcount, int shift, int64_t nblocks, uint32_t* hist) {
   __shared__ uint32_t h[NW][kHistChunks][256];
 #pragma unroll
   for (int q = 0; q < NW * kHistChunks; ++q) (&h[0][0][0])[q * 256 + threadIdx.x] = 0;
@@ -256,13 +244,15 @@ __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, int64_t 
   for (int cc = 0; cc < kHistChunks; ++cc) {
     const uint64_t begin = (uint64_t)(c0 + cc) * kSortChunk;
     if (c0 + cc >= nblocks || begin >= n) break;
-    uint32_t v[kRounds][4];
+    uint32_t v[kRounds][4], ok[kRounds][4];
     load_chunk(src, begin, n, v);
+    if (valid) load_chunk(ScanSrc{valid, nullptr, 1}, begin, n, ok);
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        if (begin + (uint64_t)r * 4 * B + 4u * threadIdx.x + c < n) atomicAdd(&h[w][cc][(v[r][c] >> shift) & 255u], 1u);
+        if (begin + (uint64_t)r * 4 * B + 4u * threadIdx.x + c < n && (!valid || ok[r][c]))
+          atomicAdd(&h[w][cc][(v[r][c] >> shift) & 255u], 1u);
     }
   }
   __syncthreads();
@@ -290,15 +280,21 @@ constexpr int kWaveKeys = kSortChunk / NW;
 constexpr int kWaveRounds = kWaveKeys / 64;
 constexpr int kOutRounds = kSortChunk / B;
 
-template <bool kPay>
+// kDense (the first depth pass): the input is the dense (view, Gaussian)
+// range, key k is taken only where valid[k] != 0, and its value is
+// value_base + k (the pair's index), so the pass compacts the visible pairs
+// in (view, Gaussian) order as it sorts them.
+template <bool kPay, bool kDense = false>
 __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                                                      uint32_t* vout, const uint2* pin, uint2* pout,
                                                      int64_t max_count, const uint32_t* dcount, int shift,
-                                                     int64_t nblocks, const uint32_t* hist_scanned) {
+                                                     int64_t nblocks, const uint32_t* hist_scanned,
+                                                     const uint32_t* valid = nullptr, uint32_t value_base = 0) {
   __shared__ __align__(16) uint32_t s_kv[2 * kSortChunk];   // keys | values, later the payload
   __shared__ uint32_t s_wc[NW][256];
   __shared__ uint32_t s_gbase[256];
   __shared__ uint32_t s_tmp[NW];
+  __shared__ uint32_t s_taken;   // keys of the chunk that take part (all but invalid dense entries)
   uint32_t* s_key = s_kv;
   uint32_t* s_val = s_kv + kSortChunk;
   const uint32_t n = dev_count(dcount, max_count);
@@ -311,15 +307,21 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
   for (int q = 0; q < NW; ++q) s_wc[q][threadIdx.x] = 0;
   uint32_t key[kWaveRounds], val[kWaveRounds], lr[kWaveRounds];
   uint2 pay[kPay ? kWaveRounds : 1];
+  uint32_t in_mask = 0;   // bit r: this lane's key of round r takes part
 #pragma unroll
   for (int r = 0; r < kWaveRounds; ++r) {
     const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
+    const bool in = li < cnt && (!kDense || __builtin_nontemporal_load(valid + begin + li) != 0u);
+    in_mask |= in ? 1u << r : 0u;
     // each pass reads its input once: streaming loads leave the cache to the
     // histogram, the offsets and the output being assembled
-    key[r] = li < cnt ? __builtin_nontemporal_load(kin + begin + li) : 0u;
-    val[r] = li < cnt ? __builtin_nontemporal_load(vin + begin + li) : 0u;
+    key[r] = in ? __builtin_nontemporal_load(kin + begin + li) : 0u;
+    if constexpr (kDense)
+      val[r] = value_base + (uint32_t)(begin + li);
+    else
+      val[r] = in ? __builtin_nontemporal_load(vin + begin + li) : 0u;
     if constexpr (kPay) {
-      if (li < cnt) {
+      if (in) {
         const uint32_t* pp = reinterpret_cast<const uint32_t*>(pin + begin + li);
         pay[r] = make_uint2(__builtin_nontemporal_load(pp), __builtin_nontemporal_load(pp + 1));
       } else {
@@ -331,10 +333,9 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
   // 1. stable ranks within (wavefront, digit)
 #pragma unroll
   for (int r = 0; r < kWaveRounds; ++r) {
-    const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
-    const bool valid = li < cnt;
+    const bool taking = (in_mask >> r) & 1u;
     const uint32_t digit = (key[r] >> shift) & 255u;
-    uint64_t match = __ballot(valid);
+    uint64_t match = __ballot(taking);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const bool bit = (digit >> b) & 1u;
@@ -342,10 +343,10 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
       match &= bit ? bb : ~bb;
     }
     const uint32_t below = (uint32_t)__popcll(match & lt_mask);
-    const uint32_t before = valid ? s_wc[w][digit] : 0u;
+    const uint32_t before = taking ? s_wc[w][digit] : 0u;
     __builtin_amdgcn_wave_barrier();
     lr[r] = before + below;
-    if (valid && below == 0) s_wc[w][digit] = before + (uint32_t)__popcll(match);
+    if (taking && below == 0) s_wc[w][digit] = before + (uint32_t)__popcll(match);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
@@ -360,6 +361,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
     }
     uint32_t all;
     const uint32_t lstart = block_excl_scan(tot, s_tmp, &all);
+    if (d == 0) s_taken = all;
     uint32_t run = lstart;
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
@@ -373,20 +375,20 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
   uint32_t pos[kWaveRounds];
 #pragma unroll
   for (int r = 0; r < kWaveRounds; ++r) {
-    const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
     pos[r] = s_wc[w][(key[r] >> shift) & 255u] + lr[r];
-    if (li < cnt) {
+    if ((in_mask >> r) & 1u) {
       s_key[pos[r]] = key[r];
       s_val[pos[r]] = val[r];
     }
   }
   __syncthreads();
   // 4. coalesced write-out
+  const uint32_t taken = s_taken;
   uint32_t dst[kPay ? kOutRounds : 1];
 #pragma unroll
   for (int r = 0; r < kOutRounds; ++r) {
     const uint32_t i = (uint32_t)r * B + threadIdx.x;
-    if (i < cnt) {
+    if (i < taken) {
       const uint32_t k = s_key[i];
       const uint32_t d = s_gbase[(k >> shift) & 255u] + i;
       kout[d] = k;
@@ -398,15 +400,13 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
     uint2* s_pay = reinterpret_cast<uint2*>(s_kv);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kWaveRounds; ++r) {
-      const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
-      if (li < cnt) s_pay[pos[r]] = pay[r];
-    }
+    for (int r = 0; r < kWaveRounds; ++r)
+      if ((in_mask >> r) & 1u) s_pay[pos[r]] = pay[r];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kOutRounds; ++r) {
       const uint32_t i = (uint32_t)r * B + threadIdx.x;
-      if (i < cnt) pout[dst[r]] = s_pay[i];
+      if (i < taken) pout[dst[r]] = s_pay[i];
     }
   }
 }
@@ -621,39 +621,65 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t max_count, con
   return scan_src(ScanSrc{in, nullptr, 0}, out, max_count, dcount, partial, partial_len, total, st);
 }
 
+// Dense source of a sort's first pass: max_count keys key[k] with payload
+// pay[k], taken only where valid[k] != 0, with value value_base + k; the
+// number taken is written to *taken, which the later passes read as their
+// count.
+struct DenseSrc {
+  const uint32_t* key;
+  const uint32_t* valid;
+  const uint2* pay;
+  uint32_t value_base;
+  uint32_t* taken;
+};
+
 // Sorts (key, value) pairs on key bits [0, bits) in ping-pong buffers; returns
-// through *in_b whether the result landed in the second buffer.
+// through *in_b whether the result landed in the second buffer.  With `dense`,
+// the first pass reads the dense source instead of (ka, va, pa) and writes
+// the taken keys to (ka, va, pa), and the later passes sort *dense->taken of
+// them (dcount must then be dense->taken).
 static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
                              uint2* pa, uint2* pb, int64_t max_count, const uint32_t* dcount, int bits, bool* in_b,
-                             hipStream_t st) {
+                             hipStream_t st, const DenseSrc* dense = nullptr) {
   const int64_t nb = cdiv(max_count, kSortChunk);
   uint32_t* hist = seg<uint32_t>(ws, pl.ws.hist);
   uint32_t* partial = seg<uint32_t>(ws, pl.ws.partial);
   if (nb > pl.ws.hist_blocks) return hipErrorInvalidValue;
-  bool flip = false;
+  if (dense && (!pa || dcount != dense->taken)) return hipErrorInvalidValue;
+  bool cur_b = false;   // which buffer holds the data (before a dense first pass: neither)
   for (int shift = 0; shift < bits; shift += 8) {
-    uint32_t* ki = flip ? kb : ka;
-    uint32_t* vi = flip ? vb : va;
-    uint32_t* ko = flip ? ka : kb;
-    uint32_t* vo = flip ? va : vb;
-    uint2* pi = flip ? pb : pa;
-    uint2* po = flip ? pa : pb;
+    const bool from_dense = dense && shift == 0;
+    const bool out_b = from_dense ? false : !cur_b;
+    const uint32_t* ki = from_dense ? dense->key : cur_b ? kb : ka;
+    const uint32_t* vi = from_dense ? nullptr : cur_b ? vb : va;
+    const uint2* pi = from_dense ? dense->pay : cur_b ? pb : pa;
+    uint32_t* ko = out_b ? kb : ka;
+    uint32_t* vo = out_b ? vb : va;
+    uint2* po = out_b ? pb : pa;
     if (nb > 0) {
-      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)cdiv(nb, kHistChunks)), dim3(B), 0, st, ki, max_count, dcount,
-                         shift, nb, hist);
+      const uint32_t* dc = from_dense ? nullptr : dcount;
+      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)cdiv(nb, kHistChunks)), dim3(B), 0, st, ki,
+                         from_dense ? dense->valid : nullptr, max_count, dc, shift, nb, hist);
+      // a dense pass's digit counts total the taken keys
       hipError_t e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * nb, nullptr, partial, pl.ws.partial_len,
-                              nullptr, st);
+                              from_dense ? dense->taken : nullptr, st);
       if (e != hipSuccess) return e;
-      if (pa)
-        hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi, po,
-                           max_count, dcount, shift, nb, hist);
+      if (from_dense)
+        hipLaunchKernelGGL((k_radix_scatter<true, true>), dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi, po,
+                           max_count, dc, shift, nb, hist, dense->valid, dense->value_base);
+      else if (pa)
+        hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi,
+                           po, max_count, dc, shift, nb, hist, nullptr, 0u);
       else
-        hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi, po,
-                           max_count, dcount, shift, nb, hist);
+        hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi,
+                           po, max_count, dc, shift, nb, hist, nullptr, 0u);
+    } else if (from_dense) {
+      hipError_t e = launch_fill_u32(dense->taken, 0u, 1, st);
+      if (e != hipSuccess) return e;
     }
-    flip = !flip;
+    cur_b = out_b;
   }
-  *in_b = flip;
+  *in_b = cur_b;
   return hipGetLastError();
 }
 
@@ -684,14 +710,13 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   const uint32_t cap = (uint32_t)pl.cap;
   hipError_t e;
   if (len == 0) return hipSuccess;
-  // 1. visible compaction in (view, Gaussian) order: positions -> koff (scratch)
-  e = scan_src(ScanSrc{count + base, nullptr, 1}, koff, len, nullptr, partial, pl.ws.partial_len, &ctr->nvis, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compact_visible, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, count, depth,
-                     seg<uint2>(ws, pl.ws.rect), koff, base, len, vis_a, vkey_a, vrect_a);
-  // 2. stable depth sort of the visible pairs (ties keep (view, Gaussian) order)
+  // 1-2. stable depth sort of the visible pairs (ties keep (view, Gaussian)
+  // order); its first pass reads the dense (view, Gaussian) arrays and takes
+  // the visible pairs only, so it also compacts them and counts them into
+  // ctr->nvis
   bool in_b = false;
-  e = radix_sort(pl, ws, vkey_a, vis_a, vkey_b, vis_b, vrect_a, vrect_b, len, &ctr->nvis, 32, &in_b, st);
+  const DenseSrc dense{depth + base, count + base, seg<uint2>(ws, pl.ws.rect) + base, (uint32_t)base, &ctr->nvis};
+  e = radix_sort(pl, ws, vkey_a, vis_a, vkey_b, vis_b, vrect_a, vrect_b, len, &ctr->nvis, 32, &in_b, st, &dense);
   if (e != hipSuccess) return e;
   const uint32_t* sorted_vis = in_b ? vis_b : vis_a;
   const uint2* sorted_rect = in_b ? vrect_b : vrect_a;
