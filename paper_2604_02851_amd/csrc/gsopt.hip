@@ -147,6 +147,7 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   L.vals_b = take(4 * cap);
   L.strips = take(4 * (size_t)cap);
   L.hist = take(4 * (256 * L.hist_blocks + 1));
+  L.firsts = take(4 * L.hist_blocks);
   L.partial = take(4 * L.partial_len);
   L.ranges = take(8 * tiles);
   L.order = take(4 * tiles);

@@ -58,10 +58,11 @@ struct WsLayout {
   size_t keys_a, keys_b, vals_a, vals_b;  // u32 [cap]
   size_t strips;      // u32 [cap] strip bits of each list entry, stored by the forward compositing
   size_t hist;        // u32 [256 * max_blocks + 1]
+  size_t firsts;      // u32 [max_blocks] depth-order pair owning the first key slot of each sort chunk
   size_t partial;     // u32 [scan partials]
   size_t ranges;      // u32x2 [tiles]
   size_t order;       // u32 [tiles] compositing order of the tiles (longest lists first)
-  size_t obucket;     // u32 [64] list-length histogram and cursors of that order
+  size_t obucket;     // u32 [2 * 33] list-length histogram and cursors of that order
   size_t last;        // u32 [pixels]
   size_t vmask;       // u64 [n] views of the last projection call that see the Gaussian
                       // (bit v - v0 when the call has at most 64 views, else all ones)

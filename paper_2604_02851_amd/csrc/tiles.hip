@@ -166,8 +166,13 @@ __global__ __launch_bounds__(1024) void k_scan_partials(int64_t max_count, const
   }
 }
 
+// With `firsts` (the key-offset scan), element k, whose run of out[k] .. out[k]
+// + value - 1 slots it now knows, also records itself as the owner of every
+// chunk of kSortChunk slots that starts inside that run: firsts[m] = k for
+// m K in [out[k], out[k] + value), m < firsts_len.
 __global__ __launch_bounds__(B) void k_scan_down(ScanSrc src, uint32_t* out, int64_t max_count,
-                                                 const uint32_t* dcount, const uint32_t* partial) {
+                                                 const uint32_t* dcount, const uint32_t* partial,
+                                                 uint32_t* firsts, uint32_t firsts_len) {
   __shared__ uint32_t s_wave[kRounds][NW];
   const uint32_t n = dev_count(dcount, max_count);
   const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
@@ -202,6 +207,15 @@ __global__ __launch_bounds__(B) void k_scan_down(ScanSrc src, uint32_t* out, int
     for (int c = 0; c < 4; ++c) {
       o[c] = run;
       run += v[r][c];
+    }
+    if (firsts) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (k + c >= n) continue;
+        const uint64_t lo = o[c], hi = lo + v[r][c];
+        for (uint64_t m = (lo + kSortChunk - 1) / kSortChunk; m < firsts_len && m * kSortChunk < hi; ++m)
+          firsts[m] = (uint32_t)(k + c);
+      }
     }
     if (full) {
       *reinterpret_cast<uint4*>(out + k) = make_uint4(o[0], o[1], o[2], o[3]);
@@ -412,14 +426,21 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
 }
 
 // ---- key emission in depth order -----------------------------------------
-// One wavefront writes the keys of 64 consecutive depth-sorted visible pairs:
-// in each round lane l produces output slot S + l (coalesced stores).  The
-// pair owning a slot is found without searching: each pair whose first slot
-// falls in the round marks that slot with its index, and an inclusive max-scan
-// over the lanes (carried from the previous round) hands every slot the last
-// pair that started at or before it.  The slot's tile within the pair's
-// rectangle comes from a float-reciprocal quotient corrected to the exact
-// integer one.
+// Workgroup c writes the key slots [c K, (c+1) K) of one chunk of the tile
+// sort (K = kSortChunk), and with them the digit counts of that sort's first
+// pass for the chunk, in the layout k_radix_hist writes (hist[d * nblocks +
+// c]), so the first tile pass needs no histogram read of its own.  Its
+// wavefronts take the depth-sorted visible pairs from firsts[c], the pair
+// owning slot c K, onwards, 64 consecutive pairs at a time, until a group
+// starts past the chunk; a pair that straddles a chunk boundary is written
+// in part by both workgroups.  Within a group, lane l produces output slot
+// S + l in each round (coalesced stores).  The pair owning a slot is found
+// without searching: each pair whose first slot falls in the round marks that
+// slot with its index, and an inclusive max-scan over the lanes (carried from
+// the previous round, and started at the last pair that began at or before
+// the chunk) hands every slot the last pair that started at or before it.
+// The slot's tile within the pair's rectangle comes from a float-reciprocal
+// quotient corrected to the exact integer one.
 
 // Inclusive max-scan over the 64 lanes (values >= -1).
 template <int CTRL, int ROW_MASK>
@@ -436,71 +457,93 @@ __device__ __forceinline__ int wave_incl_max(int v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_emit(const uint32_t* sorted_vis, const uint32_t* koff, const uint32_t* nvis_p,
-                                              const uint32_t* total_keys, const ushort4* sorted_rect,
-                                              const ViewInfo* views,
-                                              int64_t n_gauss, int32_t tile_begin, uint32_t cap, uint32_t* keys,
-                                              uint32_t* vals) {
-  __shared__ uint32_t s_off[4][64];
-  __shared__ uint32_t s_vi[4][64];
-  __shared__ ushort4 s_rect[4][64];
-  __shared__ float s_rw[4][64];      // 1 / rectangle width
-  __shared__ int32_t s_row[4][64];   // first tile of the pair's view, relative to the call's first tile
-  __shared__ int32_t s_tx[4][64];    // tiles per row in the pair's view
-  __shared__ int32_t s_mark[4][64];
+__global__ __launch_bounds__(B) void k_emit_chunk(const uint32_t* sorted_vis, const uint32_t* koff,
+                                                  const uint32_t* firsts, const uint32_t* nvis_p,
+                                                  const uint32_t* total_keys, const ushort4* sorted_rect,
+                                                  const ViewInfo* views, int64_t n_gauss, int32_t tile_begin,
+                                                  uint32_t cap, int64_t nblocks, uint32_t* keys, uint32_t* vals,
+                                                  uint32_t* hist) {
+  __shared__ uint32_t h[NW][256];       // first-pass digit counts, one histogram per wavefront
+  __shared__ uint32_t s_off[NW][64];
+  __shared__ uint32_t s_vi[NW][64];
+  __shared__ ushort4 s_rect[NW][64];
+  __shared__ float s_rw[NW][64];        // 1 / rectangle width
+  __shared__ int32_t s_row[NW][64];     // first tile of the pair's view, relative to the call's first tile
+  __shared__ int32_t s_tx[NW][64];      // tiles per row in the pair's view
+  __shared__ int32_t s_mark[NW][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t nvis = *nvis_p;
-  const uint32_t k0 = (blockIdx.x * 4u + (uint32_t)w) * 64u;
-  const uint32_t nent = k0 < nvis ? min(64u, nvis - k0) : 0u;
-  const bool valid = (uint32_t)lane < nent;
-  uint32_t off = 0xffffffffu, end = 0;
-  if (valid) {
-    const uint32_t vi = sorted_vis[k0 + lane];
-    off = koff[k0 + lane];
-    end = k0 + lane + 1 < nvis ? koff[k0 + lane + 1] : *total_keys;
-    const int v = (int)(vi / (uint64_t)n_gauss);
-    const ushort4 r = sorted_rect[k0 + lane];
-    s_vi[w][lane] = vi;
-    s_rect[w][lane] = r;
-    s_rw[w][lane] = __builtin_amdgcn_rcpf((float)((uint32_t)r.z - r.x + 1u));
-    s_row[w][lane] = views[v].tile_base - tile_begin;
-    s_tx[w][lane] = views[v].tiles_x;
-  }
-  s_off[w][lane] = off;
-  __syncthreads();
-  if (nent == 0) return;
-  const uint32_t start = s_off[w][0];
-  uint32_t stop = end;
 #pragma unroll
-  for (int d = 32; d > 0; d >>= 1) stop = max(stop, (uint32_t)__shfl_xor((int)stop, d, 64));
-  int carry = -1;
-  for (uint32_t S = start; S < stop; S += 64) {
-    s_mark[w][lane] = -1;
-    __builtin_amdgcn_wave_barrier();
-    if (valid && off >= S && off - S < 64u) s_mark[w][off - S] = lane;
-    __builtin_amdgcn_wave_barrier();
-    const int own = wave_incl_max(max(s_mark[w][lane], carry));
-    carry = __builtin_amdgcn_readlane(own, 63);
-    __builtin_amdgcn_wave_barrier();
-    const uint32_t slot = S + (uint32_t)lane;
-    if (slot < stop && slot < cap) {
-      const ushort4 r = s_rect[w][own];
-      const uint32_t m = slot - s_off[w][own];
-      const uint32_t width = (uint32_t)r.z - r.x + 1u;
-      uint32_t q = (uint32_t)((float)m * s_rw[w][own]);
-      int32_t rem = (int32_t)(m - q * width);
-      if (rem < 0) {
-        q -= 1u;
-        rem += (int32_t)width;
-      } else if (rem >= (int32_t)width) {
-        q += 1u;
-        rem -= (int32_t)width;
+  for (int q = 0; q < NW; ++q) h[q][threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t all_keys = *total_keys;
+  const uint32_t n = min(all_keys, cap);
+  const uint64_t S0 = (uint64_t)blockIdx.x * kSortChunk;
+  if (S0 < n) {
+    const uint32_t S1 = (uint32_t)min((uint64_t)n, S0 + kSortChunk);
+    const uint32_t nvis = *nvis_p;
+    for (uint32_t g = firsts[blockIdx.x] + (uint32_t)w * 64u; g < nvis; g += NW * 64u) {
+      const uint32_t k = g + (uint32_t)lane;
+      const bool valid = k < nvis;
+      const uint32_t off = valid ? koff[k] : 0xffffffffu;
+      if ((uint32_t)__builtin_amdgcn_readfirstlane((int)off) >= S1) break;   // the group starts past the chunk
+      uint32_t end = 0;
+      if (valid) {
+        const uint32_t vi = sorted_vis[k];
+        end = k + 1 < nvis ? koff[k + 1] : all_keys;
+        const int v = (int)(vi / (uint64_t)n_gauss);
+        const ushort4 r = sorted_rect[k];
+        s_vi[w][lane] = vi;
+        s_rect[w][lane] = r;
+        s_rw[w][lane] = __builtin_amdgcn_rcpf((float)((uint32_t)r.z - r.x + 1u));
+        s_row[w][lane] = views[v].tile_base - tile_begin;
+        s_tx[w][lane] = views[v].tiles_x;
       }
-      const uint32_t ty = r.y + q, tx = r.x + (uint32_t)rem;
-      keys[slot] = (uint32_t)(s_row[w][own] + (int32_t)(ty * (uint32_t)s_tx[w][own] + tx));
-      vals[slot] = s_vi[w][own];
+      s_off[w][lane] = off;
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t start = max(s_off[w][0], (uint32_t)S0);
+      uint32_t stop = end;
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) stop = max(stop, (uint32_t)__shfl_xor((int)stop, d, 64));
+      stop = min(stop, S1);
+      // the last pair of the group that began at or before `start`
+      int carry = (int)__popcll(__ballot(valid && off <= start)) - 1;
+      for (uint32_t S = start; S < stop; S += 64) {
+        s_mark[w][lane] = -1;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && off >= S && off - S < 64u) s_mark[w][off - S] = lane;
+        __builtin_amdgcn_wave_barrier();
+        const int own = wave_incl_max(max(s_mark[w][lane], carry));
+        carry = __builtin_amdgcn_readlane(own, 63);
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t slot = S + (uint32_t)lane;
+        if (slot < stop) {
+          const ushort4 r = s_rect[w][own];
+          const uint32_t m = slot - s_off[w][own];
+          const uint32_t width = (uint32_t)r.z - r.x + 1u;
+          uint32_t q = (uint32_t)((float)m * s_rw[w][own]);
+          int32_t rem = (int32_t)(m - q * width);
+          if (rem < 0) {
+            q -= 1u;
+            rem += (int32_t)width;
+          } else if (rem >= (int32_t)width) {
+            q += 1u;
+            rem -= (int32_t)width;
+          }
+          const uint32_t ty = r.y + q, tx = r.x + (uint32_t)rem;
+          const uint32_t key = (uint32_t)(s_row[w][own] + (int32_t)(ty * (uint32_t)s_tx[w][own] + tx));
+          keys[slot] = key;
+          vals[slot] = s_vi[w][own];
+          atomicAdd(&h[w][key & 255u], 1u);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
   }
+  __syncthreads();
+  uint32_t t = 0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) t += h[q][threadIdx.x];
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = t;
 }
 
 __global__ void k_key_total(Counters* c, const uint32_t* total_keys, uint32_t cap) {
@@ -603,7 +646,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 }
 
 static hipError_t scan_src(ScanSrc src, uint32_t* out, int64_t max_count, const uint32_t* dcount, uint32_t* partial,
-                           int64_t partial_len, uint32_t* total, hipStream_t st) {
+                           int64_t partial_len, uint32_t* total, hipStream_t st, uint32_t* firsts = nullptr,
+                           uint32_t firsts_len = 0) {
   const int64_t nb = cdiv(max_count, kSortChunk);
   if (nb + 1 > partial_len) return hipErrorInvalidValue;
   if (nb > 0) {
@@ -611,7 +655,8 @@ static hipError_t scan_src(ScanSrc src, uint32_t* out, int64_t max_count, const 
   }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, max_count, dcount, partial, total);
   if (nb > 0) {
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(B), 0, st, src, out, max_count, dcount, partial);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(B), 0, st, src, out, max_count, dcount, partial, firsts,
+                       firsts_len);
   }
   return hipGetLastError();
 }
@@ -637,10 +682,12 @@ struct DenseSrc {
 // through *in_b whether the result landed in the second buffer.  With `dense`,
 // the first pass reads the dense source instead of (ka, va, pa) and writes
 // the taken keys to (ka, va, pa), and the later passes sort *dense->taken of
-// them (dcount must then be dense->taken).
+// them (dcount must then be dense->taken).  With first_hist_ready, the
+// kernel that wrote the keys has already stored the first pass's digit
+// counts in the histogram buffer.
 static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
                              uint2* pa, uint2* pb, int64_t max_count, const uint32_t* dcount, int bits, bool* in_b,
-                             hipStream_t st, const DenseSrc* dense = nullptr) {
+                             hipStream_t st, const DenseSrc* dense = nullptr, bool first_hist_ready = false) {
   const int64_t nb = cdiv(max_count, kSortChunk);
   uint32_t* hist = seg<uint32_t>(ws, pl.ws.hist);
   uint32_t* partial = seg<uint32_t>(ws, pl.ws.partial);
@@ -658,7 +705,8 @@ static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* v
     uint2* po = out_b ? pb : pa;
     if (nb > 0) {
       const uint32_t* dc = from_dense ? nullptr : dcount;
-      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)cdiv(nb, kHistChunks)), dim3(B), 0, st, ki,
+      if (!(first_hist_ready && shift == 0))
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)cdiv(nb, kHistChunks)), dim3(B), 0, st, ki,
                          from_dense ? dense->valid : nullptr, max_count, dc, shift, nb, hist);
       // a dense pass's digit counts total the taken keys
       hipError_t e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * nb, nullptr, partial, pl.ws.partial_len,
@@ -720,23 +768,30 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   if (e != hipSuccess) return e;
   const uint32_t* sorted_vis = in_b ? vis_b : vis_a;
   const uint2* sorted_rect = in_b ? vrect_b : vrect_a;
-  // 3. key offsets in depth order
+  // 3. key offsets in depth order, and the pair owning the first slot of
+  // each chunk of the tile sort
+  const int64_t key_chunks = cdiv(pl.cap, kSortChunk);
+  if (key_chunks > pl.ws.hist_blocks) return hipErrorInvalidValue;
+  uint32_t* firsts = seg<uint32_t>(ws, pl.ws.firsts);
   e = scan_src(ScanSrc{reinterpret_cast<const uint32_t*>(sorted_rect), nullptr, 3}, koff, len, &ctr->nvis, partial,
-               pl.ws.partial_len, &ctr->keys, st);
+               pl.ws.partial_len, &ctr->keys, st, firsts, (uint32_t)key_chunks);
   if (e != hipSuccess) return e;
   // ctr->keys holds the total; record it and the overflow flag
   hipLaunchKernelGGL(k_key_total, dim3(1), dim3(64), 0, st, ctr, &ctr->keys, cap);
-  // 4. emit (tile, value) pairs in depth order
+  // 4. emit (tile, value) pairs in depth order, one sort chunk per
+  // workgroup, with the digit counts of the tile sort's first pass
   const int32_t tile_begin = pl.views[v0].tile_base;
   const int32_t tile_end = (v0 + nv < pl.n_views) ? pl.views[v0 + nv].tile_base : pl.total_tiles;
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(len, 256)), dim3(256), 0, st, sorted_vis, koff, &ctr->nvis, &ctr->keys,
-                     reinterpret_cast<const ushort4*>(sorted_rect), pl.d_views, N, tile_begin, cap, keys_a, vals_a);
+  hipLaunchKernelGGL(k_emit_chunk, dim3((unsigned)key_chunks), dim3(B), 0, st, sorted_vis, koff, firsts, &ctr->nvis,
+                     &ctr->keys, reinterpret_cast<const ushort4*>(sorted_rect), pl.d_views, N, tile_begin, cap,
+                     key_chunks, keys_a, vals_a, seg<uint32_t>(ws, pl.ws.hist));
   // 5. stable sort by tile (relative to the first tile of the call)
   const int64_t ntiles = tile_end - tile_begin;
   int bits = 0;
   while ((1ll << bits) < ntiles) ++bits;
   bits = bits == 0 ? 8 : ((bits + 7) / 8) * 8;
-  e = radix_sort(pl, ws, keys_a, vals_a, keys_b, vals_b, nullptr, nullptr, pl.cap, &ctr->keys, bits, &in_b, st);
+  e = radix_sort(pl, ws, keys_a, vals_a, keys_b, vals_b, nullptr, nullptr, pl.cap, &ctr->keys, bits, &in_b, st, nullptr,
+                 true);
   if (e != hipSuccess) return e;
   // 6. ranges
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges + tile_begin), 0u, 2 * ntiles, st);
