@@ -232,7 +232,7 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
   if (i < count) p[i] = value;
 }
 
-// ---- radix sort (LSD, 8-bit digits, stable) ---------------------------------
+// ---- radix sort (LSD, digits of up to 8 bits, stable) -----------------------
 // Digit counts of kHistChunks consecutive chunks per workgroup, one chunk
 // after the other; each thread loads its kSortItems keys of a chunk with
 // 16-byte loads (the scan chunk layout) and counts them with LDS atomics
@@ -246,7 +246,8 @@ constexpr int kHistChunks = 4;
 // arrays), key k counts only where valid[k] != 0: the pass then compacts the
 // visible pairs as it sorts them.
 __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, const uint32_t* valid, int64_t max_count,
-                                                  const uint32_t* dcount, int shift, int64_t nblocks, uint32_t* hist) {
+                                                  const uint32_t* dcount, int shift, uint32_t dmask, int64_t nblocks,
+                                                  uint32_t* hist) {
   __shared__ uint32_t h[NW][kHistChunks][256];
 #pragma unroll
   for (int q = 0; q < NW * kHistChunks; ++q) (&h[0][0][0])[q * 256 + threadIdx.x] = 0;
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, const ui
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         if (begin + (uint64_t)r * 4 * B + 4u * threadIdx.x + c < n && (!valid || ok[r][c]))
-          atomicAdd(&h[w][cc][(v[r][c] >> shift) & 255u], 1u);
+          atomicAdd(&h[w][cc][(v[r][c] >> shift) & dmask], 1u);
     }
   }
   __syncthreads();
@@ -302,7 +303,7 @@ template <bool kPay, bool kDense = false>
 __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                                                      uint32_t* vout, const uint2* pin, uint2* pout,
                                                      int64_t max_count, const uint32_t* dcount, int shift,
-                                                     int64_t nblocks, const uint32_t* hist_scanned,
+                                                     uint32_t dmask, int64_t nblocks, const uint32_t* hist_scanned,
                                                      const uint32_t* valid = nullptr, uint32_t value_base = 0) {
   __shared__ __align__(16) uint32_t s_kv[2 * kSortChunk];   // keys | values, later the payload
   __shared__ uint32_t s_wc[NW][256];
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
 #pragma unroll
   for (int r = 0; r < kWaveRounds; ++r) {
     const bool taking = (in_mask >> r) & 1u;
-    const uint32_t digit = (key[r] >> shift) & 255u;
+    const uint32_t digit = (key[r] >> shift) & dmask;
     uint64_t match = __ballot(taking);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
   uint32_t pos[kWaveRounds];
 #pragma unroll
   for (int r = 0; r < kWaveRounds; ++r) {
-    pos[r] = s_wc[w][(key[r] >> shift) & 255u] + lr[r];
+    pos[r] = s_wc[w][(key[r] >> shift) & dmask] + lr[r];
     if ((in_mask >> r) & 1u) {
       s_key[pos[r]] = key[r];
       s_val[pos[r]] = val[r];
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
     const uint32_t i = (uint32_t)r * B + threadIdx.x;
     if (i < taken) {
       const uint32_t k = s_key[i];
-      const uint32_t d = s_gbase[(k >> shift) & 255u] + i;
+      const uint32_t d = s_gbase[(k >> shift) & dmask] + i;
       kout[d] = k;
       vout[d] = s_val[i];
       if constexpr (kPay) dst[r] = d;
@@ -461,8 +462,8 @@ __global__ __launch_bounds__(B) void k_emit_chunk(const uint32_t* sorted_vis, co
                                                   const uint32_t* firsts, const uint32_t* nvis_p,
                                                   const uint32_t* total_keys, const ushort4* sorted_rect,
                                                   const ViewInfo* views, int64_t n_gauss, int32_t tile_begin,
-                                                  uint32_t cap, int64_t nblocks, uint32_t* keys, uint32_t* vals,
-                                                  uint32_t* hist) {
+                                                  uint32_t cap, int64_t nblocks, uint32_t dmask0, uint32_t* keys,
+                                                  uint32_t* vals, uint32_t* hist) {
   __shared__ uint32_t h[NW][256];       // first-pass digit counts, one histogram per wavefront
   __shared__ uint32_t s_off[NW][64];
   __shared__ uint32_t s_vi[NW][64];
@@ -533,7 +534,7 @@ __global__ __launch_bounds__(B) void k_emit_chunk(const uint32_t* sorted_vis, co
           const uint32_t key = (uint32_t)(s_row[w][own] + (int32_t)(ty * (uint32_t)s_tx[w][own] + tx));
           keys[slot] = key;
           vals[slot] = s_vi[w][own];
-          atomicAdd(&h[w][key & 255u], 1u);
+          atomicAdd(&h[w][key & dmask0], 1u);
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -678,8 +679,9 @@ struct DenseSrc {
   uint32_t* taken;
 };
 
-// Sorts (key, value) pairs on key bits [0, bits) in ping-pong buffers; returns
-// through *in_b whether the result landed in the second buffer.  With `dense`,
+// Sorts (key, value) pairs on key bits [0, bits) in ping-pong buffers, the
+// first pass on the low first_bits bits and every later one on the next 8;
+// returns through *in_b whether the result landed in the second buffer.  With `dense`,
 // the first pass reads the dense source instead of (ka, va, pa) and writes
 // the taken keys to (ka, va, pa), and the later passes sort *dense->taken of
 // them (dcount must then be dense->taken).  With first_hist_ready, the
@@ -687,14 +689,16 @@ struct DenseSrc {
 // counts in the histogram buffer.
 static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
                              uint2* pa, uint2* pb, int64_t max_count, const uint32_t* dcount, int bits, bool* in_b,
-                             hipStream_t st, const DenseSrc* dense = nullptr, bool first_hist_ready = false) {
+                             hipStream_t st, const DenseSrc* dense = nullptr, bool first_hist_ready = false,
+                             int first_bits = 8) {
   const int64_t nb = cdiv(max_count, kSortChunk);
   uint32_t* hist = seg<uint32_t>(ws, pl.ws.hist);
   uint32_t* partial = seg<uint32_t>(ws, pl.ws.partial);
   if (nb > pl.ws.hist_blocks) return hipErrorInvalidValue;
   if (dense && (!pa || dcount != dense->taken)) return hipErrorInvalidValue;
   bool cur_b = false;   // which buffer holds the data (before a dense first pass: neither)
-  for (int shift = 0; shift < bits; shift += 8) {
+  for (int shift = 0; shift < bits; shift += (shift == 0 ? first_bits : 8)) {
+    const uint32_t dmask = (1u << (shift == 0 ? first_bits : 8)) - 1u;
     const bool from_dense = dense && shift == 0;
     const bool out_b = from_dense ? false : !cur_b;
     const uint32_t* ki = from_dense ? dense->key : cur_b ? kb : ka;
@@ -707,20 +711,20 @@ static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* v
       const uint32_t* dc = from_dense ? nullptr : dcount;
       if (!(first_hist_ready && shift == 0))
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)cdiv(nb, kHistChunks)), dim3(B), 0, st, ki,
-                         from_dense ? dense->valid : nullptr, max_count, dc, shift, nb, hist);
+                         from_dense ? dense->valid : nullptr, max_count, dc, shift, dmask, nb, hist);
       // a dense pass's digit counts total the taken keys
       hipError_t e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * nb, nullptr, partial, pl.ws.partial_len,
                               from_dense ? dense->taken : nullptr, st);
       if (e != hipSuccess) return e;
       if (from_dense)
         hipLaunchKernelGGL((k_radix_scatter<true, true>), dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi, po,
-                           max_count, dc, shift, nb, hist, dense->valid, dense->value_base);
+                           max_count, dc, shift, dmask, nb, hist, dense->valid, dense->value_base);
       else if (pa)
         hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi,
-                           po, max_count, dc, shift, nb, hist, nullptr, 0u);
+                           po, max_count, dc, shift, dmask, nb, hist, nullptr, 0u);
       else
         hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3((unsigned)nb), dim3(B), 0, st, ki, vi, ko, vo, pi,
-                           po, max_count, dc, shift, nb, hist, nullptr, 0u);
+                           po, max_count, dc, shift, dmask, nb, hist, nullptr, 0u);
     } else if (from_dense) {
       hipError_t e = launch_fill_u32(dense->taken, 0u, 1, st);
       if (e != hipSuccess) return e;
@@ -782,16 +786,19 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   // workgroup, with the digit counts of the tile sort's first pass
   const int32_t tile_begin = pl.views[v0].tile_base;
   const int32_t tile_end = (v0 + nv < pl.n_views) ? pl.views[v0 + nv].tile_base : pl.total_tiles;
-  hipLaunchKernelGGL(k_emit_chunk, dim3((unsigned)key_chunks), dim3(B), 0, st, sorted_vis, koff, firsts, &ctr->nvis,
-                     &ctr->keys, reinterpret_cast<const ushort4*>(sorted_rect), pl.d_views, N, tile_begin, cap,
-                     key_chunks, keys_a, vals_a, seg<uint32_t>(ws, pl.ws.hist));
-  // 5. stable sort by tile (relative to the first tile of the call)
+  // tile bits of the call, split into passes of 8 bits with the remainder
+  // taken first: fewer digits in the first pass
   const int64_t ntiles = tile_end - tile_begin;
   int bits = 0;
   while ((1ll << bits) < ntiles) ++bits;
-  bits = bits == 0 ? 8 : ((bits + 7) / 8) * 8;
+  if (bits == 0) bits = 1;
+  const int first_bits = bits - 8 * ((bits - 1) / 8);
+  hipLaunchKernelGGL(k_emit_chunk, dim3((unsigned)key_chunks), dim3(B), 0, st, sorted_vis, koff, firsts, &ctr->nvis,
+                     &ctr->keys, reinterpret_cast<const ushort4*>(sorted_rect), pl.d_views, N, tile_begin, cap,
+                     key_chunks, (1u << first_bits) - 1u, keys_a, vals_a, seg<uint32_t>(ws, pl.ws.hist));
+  // 5. stable sort by tile (relative to the first tile of the call)
   e = radix_sort(pl, ws, keys_a, vals_a, keys_b, vals_b, nullptr, nullptr, pl.cap, &ctr->keys, bits, &in_b, st, nullptr,
-                 true);
+                 true, first_bits);
   if (e != hipSuccess) return e;
   // 6. ranges
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges + tile_begin), 0u, 2 * ntiles, st);
