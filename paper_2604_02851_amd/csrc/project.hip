@@ -203,11 +203,27 @@ __device__ __forceinline__ void view_dir(const gs_camera& cam, const float* mu, 
   d[0] = vx * il; d[1] = vy * il; d[2] = vz * il;
 }
 
+// The cameras are not written while a projection kernel runs: read through
+// the constant address space, a wavefront-uniform view index makes them
+// scalar loads (the scalar cache, no vector registers, no wait at the top of
+// every view).
+typedef const uint32_t __attribute__((address_space(4))) ConstWord;
+static_assert(sizeof(gs_camera) == 21 * sizeof(uint32_t), "camera words");
+__device__ __forceinline__ gs_camera read_camera(const gs_camera* cams, int v) {
+  ConstWord* src = (ConstWord*)(cams + v);
+  gs_camera c;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&c);
+#pragma unroll
+  for (int k = 0; k < 21; ++k) dst[k] = src[k];
+  return c;
+}
+
 struct ProjArgs {
   ParamPtrs p;
   const gs_camera* cams;
   const ViewInfo* views;
-  int v0, nv, tile_w, tile_h;
+  int v0, nv;
+  int tile_sw, tile_sh;      // log2 of the tile width and height
   uint32_t* depth;
   uint32_t* count;
   ushort4* rect;
@@ -224,7 +240,8 @@ static_assert(kViewWaves == 1, "one wavefront writes a Gaussian's view mask");
 template <int DEG>
 __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int wave = threadIdx.x >> 6;
+  // uniform, so that the per-view camera is read with scalar loads
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t n = a.p.n;
   if (i >= n || wave >= a.nv) return;
   constexpr int nk = (DEG + 1) * (DEG + 1);
@@ -257,7 +274,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
 #pragma unroll 1
   for (int v = a.v0 + wave; v < a.v0 + a.nv; v += kViewWaves) {
     const int64_t o = (int64_t)v * n + i;
-    const gs_camera cam = a.cams[v];
+    const gs_camera cam = read_camera(a.cams, v);
     uint32_t cnt = 0;
     if (g.ok && (!a.cell_mask || a.cell_mask[(int64_t)v * a.cell_row + cell])) {
       const float z32 = depth_key(cam.R[6], cam.R[7], cam.R[8], cam.t[2], g.mu[0], g.mu[1], g.mu[2]);
@@ -270,8 +287,9 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
         lx = fmax(lx, 0.0); ly = fmax(ly, 0.0);
         ux = fmin(ux, (double)(cam.width - 1)); uy = fmin(uy, (double)(cam.height - 1));
         if (lx <= ux && ly <= uy) {
-          const int tx0 = (int)lx / a.tile_w, tx1 = (int)ux / a.tile_w;
-          const int ty0 = (int)ly / a.tile_h, ty1 = (int)uy / a.tile_h;
+          // the bounds are clamped to >= 0, so the shifts are floor divisions
+          const int tx0 = (int)lx >> a.tile_sw, tx1 = (int)ux >> a.tile_sw;
+          const int ty0 = (int)ly >> a.tile_sh, ty1 = (int)uy >> a.tile_sh;
           cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
           a.rect[o] = make_ushort4((unsigned short)tx0, (unsigned short)ty0, (unsigned short)tx1, (unsigned short)ty1);
           a.depth[o] = __float_as_uint(z32);
@@ -382,7 +400,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
     const double gu = gp[0], gw = gp[P], ga = gp[2 * P], gb = gp[3 * P], gc = gp[4 * P], gop = gp[5 * P];
 #pragma unroll
     for (int f = 0; f < 6; ++f) gp[f * P] = 0.f;
-    const gs_camera cam = a.cams[v];
+    const gs_camera cam = read_camera(a.cams, v);
     ViewGeom vg;
     view_geom(g, cam, vg);
     // opacity
@@ -513,7 +531,8 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_color_bwd(ProjBwdArgs a) {
       const float gcol[3] = {gp[6 * P], gp[7 * P], gp[8 * P]};
       gp[6 * P] = gp[7 * P] = gp[8 * P] = 0.f;
       float d[3], len;
-      view_dir(a.cams[v], mu, d, &len);
+      const gs_camera cam = read_camera(a.cams, v);
+      view_dir(cam, mu, d, &len);
       float Y[16];
       sh_basis(DEG, d[0], d[1], d[2], Y);
       float wk[16];
@@ -566,8 +585,8 @@ hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* c
   a.views = pl.d_views;
   a.v0 = v0;
   a.nv = nv;
-  a.tile_w = pl.tile_w;
-  a.tile_h = pl.tile_h;
+  a.tile_sw = __builtin_ctz((unsigned)pl.tile_w);
+  a.tile_sh = __builtin_ctz((unsigned)pl.tile_h);
   a.depth = seg<uint32_t>(ws, pl.ws.depth);
   a.count = seg<uint32_t>(ws, pl.ws.count);
   a.rect = seg<ushort4>(ws, pl.ws.rect);
