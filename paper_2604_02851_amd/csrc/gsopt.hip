@@ -153,6 +153,7 @@ WsLayout make_layout(int64_t n, int64_t nviews, int64_t tiles, int64_t pixels, i
   L.order = take(4 * tiles);
   L.obucket = take(4 * 128);
   L.last = take(4 * pixels);
+  L.vconst = take(sizeof(ViewD) * kMaxViews);
   L.vmask = take(8 * n);
   L.dflags = take(n);
   L.dcount = take(4 * (6ll * L.dblocks + 1));

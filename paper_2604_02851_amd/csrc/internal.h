@@ -44,6 +44,17 @@ struct Counters {
   uint32_t queue[2];      // work queue of the persistent compositing kernels (zero between launches)
 };
 
+// A view's camera in double precision for the projection kernels (every
+// member is the camera's float converted exactly, or the guard-band limit
+// computed from them in double), written by a one-thread-per-view kernel at
+// the start of each projection launch.
+struct ViewD {
+  double W[9];          // rotation, row-major
+  double t[3];
+  double fx, fy, cx, cy;
+  double limx, limy;    // guard band on x/z and y/z
+};
+
 // Byte offsets of the workspace segments (computed by the host at plan time).
 struct WsLayout {
   size_t counters;
@@ -64,6 +75,7 @@ struct WsLayout {
   size_t order;       // u32 [tiles] compositing order of the tiles (longest lists first)
   size_t obucket;     // u32 [2 * 33] list-length histogram and cursors of that order
   size_t last;        // u32 [pixels]
+  size_t vconst;      // ViewD [kMaxViews] per-view camera constants of the last projection launch
   size_t vmask;       // u64 [n] views of the last projection call that see the Gaussian
                       // (bit v - v0 when the call has at most 64 views, else all ones)
   size_t dflags;      // u8 [n] delta flags

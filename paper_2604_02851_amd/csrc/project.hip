@@ -153,12 +153,11 @@ struct ViewGeom {
   double u, w;
 };
 
-__device__ __forceinline__ bool view_geom(const Gauss& g, const gs_camera& cam, ViewGeom& vg) {
-  double W[9];
-  for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
+__device__ __forceinline__ bool view_geom(const Gauss& g, const ViewD& cam, ViewGeom& vg) {
+  const double* W = cam.W;
   for (int r = 0; r < 3; ++r)
     vg.x[r] = W[r * 3] * (double)g.mu[0] + W[r * 3 + 1] * (double)g.mu[1] + W[r * 3 + 2] * (double)g.mu[2] +
-              (double)cam.t[r];
+              cam.t[r];
   // T = W Sigma
   const double S[9] = {g.Sig[0], g.Sig[1], g.Sig[2], g.Sig[1], g.Sig[3], g.Sig[4], g.Sig[2], g.Sig[4], g.Sig[5]};
   double T[9];
@@ -170,8 +169,7 @@ __device__ __forceinline__ bool view_geom(const Gauss& g, const gs_camera& cam, 
     vg.M[t] = T[r * 3] * W[c * 3] + T[r * 3 + 1] * W[c * 3 + 1] + T[r * 3 + 2] * W[c * 3 + 2];
   }
   const double fx = cam.fx, fy = cam.fy, z = vg.x[2];
-  const double limx = (double)kGuard * (0.5 * (double)cam.width) / fx;
-  const double limy = (double)kGuard * (0.5 * (double)cam.height) / fy;
+  const double limx = cam.limx, limy = cam.limy;
   const double iz = 1.0 / z;   // one FP64 division per view; the rest multiply by it
   double tx = vg.x[0] * iz, ty = vg.x[1] * iz;
   vg.clx = tx < -limx || tx > limx;
@@ -190,8 +188,8 @@ __device__ __forceinline__ bool view_geom(const Gauss& g, const gs_camera& cam, 
   vg.B = s01;
   vg.C = s11 + (double)kDilation;
   vg.det = vg.A * vg.C - vg.B * vg.B;
-  vg.u = fx * vg.x[0] * iz + (double)cam.cx;
-  vg.w = fy * vg.x[1] * iz + (double)cam.cy;
+  vg.u = fx * vg.x[0] * iz + cam.cx;
+  vg.w = fy * vg.x[1] * iz + cam.cy;
   return vg.det > 0.0 && isfinite(vg.det) && isfinite(vg.u) && isfinite(vg.w);
 }
 
@@ -218,9 +216,39 @@ __device__ __forceinline__ gs_camera read_camera(const gs_camera* cams, int v) {
   return c;
 }
 
+typedef const double __attribute__((address_space(4))) ConstDouble;
+static_assert(sizeof(ViewD) == 18 * sizeof(double), "view constant words");
+__device__ __forceinline__ ViewD read_view_d(const ViewD* vds, int v) {
+  ConstDouble* src = (ConstDouble*)(vds + v);
+  ViewD d;
+  double* dst = reinterpret_cast<double*>(&d);
+#pragma unroll
+  for (int k = 0; k < 18; ++k) dst[k] = src[k];
+  return d;
+}
+
+// One thread per view of the launch: the camera in double precision and the
+// guard-band limits kGuard (width / 2) / fx, kGuard (height / 2) / fy.
+__global__ void k_view_consts(const gs_camera* cams, int v0, int nv, ViewD* out) {
+  const int v = v0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (v >= v0 + nv) return;
+  const gs_camera cam = cams[v];
+  ViewD d;
+  for (int k = 0; k < 9; ++k) d.W[k] = cam.R[k];
+  for (int k = 0; k < 3; ++k) d.t[k] = cam.t[k];
+  d.fx = cam.fx;
+  d.fy = cam.fy;
+  d.cx = cam.cx;
+  d.cy = cam.cy;
+  d.limx = (double)kGuard * (0.5 * (double)cam.width) / d.fx;
+  d.limy = (double)kGuard * (0.5 * (double)cam.height) / d.fy;
+  out[v] = d;
+}
+
 struct ProjArgs {
   ParamPtrs p;
   const gs_camera* cams;
+  const ViewD* vd;           // per-view constants of the same cameras
   const ViewInfo* views;
   int v0, nv;
   int tile_sw, tile_sh;      // log2 of the tile width and height
@@ -279,7 +307,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project(ProjArgs a) {
     if (g.ok && (!a.cell_mask || a.cell_mask[(int64_t)v * a.cell_row + cell])) {
       const float z32 = depth_key(cam.R[6], cam.R[7], cam.R[8], cam.t[2], g.mu[0], g.mu[1], g.mu[2]);
       ViewGeom vg;
-      if (z32 >= kNear && view_geom(g, cam, vg)) {
+      if (z32 >= kNear && view_geom(g, read_view_d(a.vd, v), vg)) {
         const double slack = 1.0 + 0x1p-10;
         const double hx = 3.0 * sqrt(vg.A) * slack, hy = 3.0 * sqrt(vg.C) * slack;
         double lx = ceil(vg.u - hx - 0.5), ux = floor(vg.u + hx - 0.5);
@@ -367,6 +395,7 @@ __device__ __forceinline__ void for_seen_views(int v0, int nv, int64_t n, int64_
 struct ProjBwdArgs {
   ParamPtrs p;
   const gs_camera* cams;
+  const ViewD* vd;    // per-view constants of the same cameras
   int v0, nv;
   const uint32_t* count;
   const uint64_t* vmask;
@@ -400,7 +429,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
     const double gu = gp[0], gw = gp[P], ga = gp[2 * P], gb = gp[3 * P], gc = gp[4 * P], gop = gp[5 * P];
 #pragma unroll
     for (int f = 0; f < 6; ++f) gp[f * P] = 0.f;
-    const gs_camera cam = read_camera(a.cams, v);
+    const ViewD cam = read_view_d(a.vd, v);
     ViewGeom vg;
     view_geom(g, cam, vg);
     // opacity
@@ -439,7 +468,7 @@ __global__ __launch_bounds__(64 * kViewWaves) void k_project_bwd(ProjBwdArgs a) 
     else { gx[2] += -GJ12 * j12 * iz; }
     // x = W mu + t ;  M = W Sigma W^T
     double W[9];
-    for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
+    for (int k = 0; k < 9; ++k) W[k] = cam.W[k];
     for (int c = 0; c < 3; ++c) gm[c] += W[c] * gx[0] + W[3 + c] * gx[1] + W[6 + c] * gx[2];
     const double G[9] = {GM[0], GM[1], GM[2], GM[1], GM[3], GM[4], GM[2], GM[4], GM[5]};
     double T[9], G3[9];   // G3 = W^T G W
@@ -582,6 +611,7 @@ hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* c
   ProjArgs a;
   a.p = p;
   a.cams = cams;
+  a.vd = seg<ViewD>(ws, pl.ws.vconst);
   a.views = pl.d_views;
   a.v0 = v0;
   a.nv = nv;
@@ -597,6 +627,8 @@ hipError_t launch_project(const Plan& pl, const ParamPtrs& p, const gs_camera* c
   a.cell_row = pl.cell_row;
   const int blocks = (p.n + 63) / 64;
   if (blocks == 0) return hipSuccess;
+  if (nv < 1 || v0 < 0 || v0 + nv > kMaxViews) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_view_consts, dim3(1), dim3(kMaxViews), 0, st, cams, v0, nv, seg<ViewD>(ws, pl.ws.vconst));
   const dim3 block(64 * kViewWaves);
   switch (p.deg) {
     case 0: hipLaunchKernelGGL(k_project<0>, dim3(blocks), block, 0, st, a); break;
@@ -613,6 +645,7 @@ hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camer
   ProjBwdArgs a;
   a.p = p;
   a.cams = cams;
+  a.vd = seg<ViewD>(ws, pl.ws.vconst);
   a.v0 = v0;
   a.nv = nv;
   a.count = seg<uint32_t>(ws, pl.ws.count);
@@ -628,6 +661,8 @@ hipError_t launch_project_bwd(const Plan& pl, const ParamPtrs& p, const gs_camer
   a.accumulate = accumulate;
   const int blocks = (grads.n + 63) / 64;
   if (blocks == 0) return hipSuccess;
+  if (nv < 1 || v0 < 0 || v0 + nv > kMaxViews) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_view_consts, dim3(1), dim3(kMaxViews), 0, st, cams, v0, nv, seg<ViewD>(ws, pl.ws.vconst));
   const dim3 block(64 * kViewWaves);
   switch (p.deg) {
     case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(blocks), block, 0, st, a); break;
