@@ -170,13 +170,21 @@ __global__ __launch_bounds__(1024) void k_scan_partials(int64_t max_count, const
 // + value - 1 slots it now knows, also records itself as the owner of every
 // chunk of kSortChunk slots that starts inside that run: firsts[m] = k for
 // m K in [out[k], out[k] + value), m < firsts_len.
+// With `direct`, partial holds the chunks' own sums (k_scan_partials has not
+// run): each block adds up those before it, and the last block writes the
+// total (block 0 writes 0 when there is nothing to scan).
 __global__ __launch_bounds__(B) void k_scan_down(ScanSrc src, uint32_t* out, int64_t max_count,
                                                  const uint32_t* dcount, const uint32_t* partial,
-                                                 uint32_t* firsts, uint32_t firsts_len) {
+                                                 uint32_t* firsts, uint32_t firsts_len, bool direct,
+                                                 uint32_t* total) {
   __shared__ uint32_t s_wave[kRounds][NW];
+  __shared__ uint32_t s_pre[NW];
   const uint32_t n = dev_count(dcount, max_count);
   const uint64_t begin = (uint64_t)blockIdx.x * kSortChunk;
-  if (begin >= n) return;
+  if (begin >= n) {
+    if (direct && total && blockIdx.x == 0 && threadIdx.x == 0) *total = 0u;
+    return;
+  }
   uint32_t v[kRounds][4];
   load_chunk(src, begin, n, v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -188,7 +196,14 @@ __global__ __launch_bounds__(B) void k_scan_down(ScanSrc src, uint32_t* out, int
     if (lane == 63) s_wave[r][w] = inc[r];
   }
   __syncthreads();
-  uint32_t carry = partial[blockIdx.x];
+  uint32_t carry;
+  if (direct) {
+    uint32_t x = 0;
+    for (uint32_t q = threadIdx.x; q < blockIdx.x; q += B) x += partial[q];
+    block_excl_scan(x, s_pre, &carry);
+  } else {
+    carry = partial[blockIdx.x];
+  }
   const bool full = begin + kSortChunk <= n && ((reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -225,6 +240,7 @@ __global__ __launch_bounds__(B) void k_scan_down(ScanSrc src, uint32_t* out, int
         if (k + c < n) out[k + c] = o[c];
     }
   }
+  if (direct && total && begin + kSortChunk >= n && threadIdx.x == 0) *total = carry;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
@@ -651,13 +667,18 @@ static hipError_t scan_src(ScanSrc src, uint32_t* out, int64_t max_count, const 
                            uint32_t firsts_len = 0) {
   const int64_t nb = cdiv(max_count, kSortChunk);
   if (nb + 1 > partial_len) return hipErrorInvalidValue;
+  // up to kDirectScanBlocks chunks, each down-sweep block adds up the chunk
+  // sums before it itself (at most that many reads per block) instead of a
+  // single-workgroup scan of them in a launch of its own
+  constexpr int64_t kDirectScanBlocks = 4096;
+  const bool direct = nb > 0 && nb <= kDirectScanBlocks;
   if (nb > 0) {
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(B), 0, st, src, max_count, dcount, partial);
   }
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, max_count, dcount, partial, total);
+  if (!direct) hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, max_count, dcount, partial, total);
   if (nb > 0) {
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(B), 0, st, src, out, max_count, dcount, partial, firsts,
-                       firsts_len);
+                       firsts_len, direct, total);
   }
   return hipGetLastError();
 }

@@ -69,6 +69,26 @@ def test_tile_lists_bit_exact(oracle, tile):
     assert np.array_equal(ranges, ranges_o)
 
 
+def test_tile_lists_with_pairs_spanning_sort_chunks_bit_exact(oracle):
+    # a few Gaussians as large as the view at 8x8 tiles: one (view, Gaussian)
+    # pair then emits more keys than one chunk of the tile sort holds (4096),
+    # so its keys straddle several chunks written by different workgroups
+    w = small(seed=131, n=1500, sizes=((1280, 720), (200, 120)))
+    w.scene.log_scale[:, :8] = 0.0
+    r = renderer_for(w, tile=(8, 8), cap=1 << 20)   # about 615k keys
+    P = DeviceParams.from_scene(w.scene)
+    r.forward(P)
+    c = r.counters()
+    cnt = seg_np(r, "count", np.uint32)
+    assert cnt.max() > 3 * 4096
+    vals_o, ranges_o = oracle.tile_lists(w.scene, w.cams, 8, 8)
+    assert c.overflow == 0 and c.keys == len(vals_o)
+    vals = seg_np(r, "sorted_values", np.uint32)[:c.keys]
+    assert np.array_equal(vals, vals_o)
+    ranges = seg_np(r, "ranges", np.uint32).reshape(-1, 2)
+    assert np.array_equal(ranges, ranges_o)
+
+
 @pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.3, 0.5, 0.1)])
 def test_composite_matches_oracle(oracle, bg):
     w = small(seed=103)
