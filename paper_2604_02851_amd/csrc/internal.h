@@ -132,19 +132,19 @@ struct SplatGeom {
 };
 
 // The compositing kernels stage each record with the conic's a and s already
-// multiplied by -log2(e)/2 (halved_conic), so that the power comes out in
+// multiplied by -log2(e)/2 (staged_conic), so that the power comes out in
 // base 2, P2 = (-L a/2 e) e + (-L s/2) dy^2 = log2(e) P up to rounding, which
 // the hardware exp2 takes directly.  The 3-sigma test compares P2 with
 // fl(-4.5 log2(e)); it can decide differently from P >= -4.5 only where P lies
 // within a few units of rounding of the cut-off.
 constexpr float kLog2e = 1.44269504088896341f;
-constexpr float kHalfLog2e = -0.5f * kLog2e;   // exact: a power-of-two multiple
+constexpr float kMinusHalfLog2e = -0.5f * kLog2e;   // exact: a power-of-two multiple
 constexpr float kCutoff2 = kCutoff * kLog2e;
-__device__ __forceinline__ float4 halved_conic(const float4& r1) {
-  return make_float4(kHalfLog2e * r1.x, r1.y, kHalfLog2e * r1.z, r1.w);
+__device__ __forceinline__ float4 staged_conic(const float4& r1) {
+  return make_float4(kMinusHalfLog2e * r1.x, r1.y, kMinusHalfLog2e * r1.z, r1.w);
 }
 
-// r1h: the record's second float4 after halved_conic; P is the base-2 power
+// r1h: the record's second float4 after staged_conic; P is the base-2 power
 __device__ __forceinline__ SplatGeom splat_power(float pxc, float pyc, const float4& r0, const float4& r1h) {
 #pragma clang fp contract(off)
   SplatGeom g;

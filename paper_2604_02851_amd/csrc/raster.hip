@@ -304,7 +304,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs& a, uint32_t slot,
       const float4 r0 = a.rec[(size_t)id * 3 + 0], r1 = a.rec[(size_t)id * 3 + 1];
       if (h == 0) {
         s_rec[j * 3 + 0] = r0;
-        s_rec[j * 3 + 1] = halved_conic(r1);
+        s_rec[j * 3 + 1] = staged_conic(r1);
         s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
       }
       const uint32_t m = splat_strip_mask<G, SW, PPT>(r0, r1, tx * TW, ty * TH, (int)h * G::NWAVES / kHalves,
@@ -491,7 +491,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t sl
   // rounding of the total), fields 2-4 without d P / d conic's factors -1/2,
   // -1, -1/2 (powers of two, exact)
   constexpr float kMinus2Ln2 = -1.38629436111989061f;
-  const float unhalve = my_field < 2 ? kMinus2Ln2 : my_field == 3 ? -1.f : my_field < 5 ? -0.5f : 1.f;
+  const float restore = my_field < 2 ? kMinus2Ln2 : my_field == 3 ? -1.f : my_field < 5 ? -0.5f : 1.f;
   if (threadIdx.x == 0) s_max = rg.x;
   __syncthreads();
   float G0[PPT], G1[PPT], G2[PPT], SG[PPT];
@@ -547,7 +547,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t sl
       const uint32_t id = a.vals[b_begin + j];
       s_id[j] = id;
       s_rec[j * 3 + 0] = a.rec[(size_t)id * 3 + 0];
-      s_rec[j * 3 + 1] = halved_conic(a.rec[(size_t)id * 3 + 1]);
+      s_rec[j * 3 + 1] = staged_conic(a.rec[(size_t)id * 3 + 1]);
       s_rec[j * 3 + 2] = a.rec[(size_t)id * 3 + 2];
       const uint32_t h2 = a.strips[b_begin + j];
       s_mask[j] = (h2 & 0xffffu) | ((h2 >> 16) << G::HALF_BITS) | (id % a.n_gauss < a.n_active ? kActiveBit : 0u);
@@ -621,7 +621,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs& a, uint32_t sl
         g[4] = fmaf(ty_, sg.dy, g[4]);
       }
       if (!act || __ballot(contrib > 0.f) == 0ull) continue;
-      const float tot8 = reduce8(g, lo8) * unhalve;
+      const float tot8 = reduce8(g, lo8) * restore;
       const float tot9 = wave_total_lane63(g[8]);
       if (kMultiWave) {
         // LDS float adds: one slot per (splat, field) for all wavefronts
