@@ -102,15 +102,19 @@ struct ScanSrc {
 constexpr int kRounds = kSortItems / 4;
 static_assert(kRounds * 4 * B == kSortChunk, "scan chunk layout");
 
+// The uniform choice between the whole-chunk and the ragged form is taken
+// once, outside the rounds, so that the whole-chunk form issues all of its
+// loads before waiting for any (chosen per round, the two forms' merged
+// registers made every round's load wait for the previous one).
 __device__ __forceinline__ void load_chunk(const ScanSrc& src, uint64_t begin, uint32_t n,
                                            uint32_t v[kRounds][4]) {
-  const bool full = begin + kSortChunk <= n && src.vec_ok();
+  if (begin + kSortChunk <= n && src.vec_ok()) {
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const uint64_t k = begin + (uint64_t)r * 4 * B + 4u * threadIdx.x;
-    if (full) {
-      src.four((uint32_t)k, v[r]);
-    } else {
+    for (int r = 0; r < kRounds; ++r) src.four((uint32_t)(begin + (uint64_t)r * 4 * B + 4u * threadIdx.x), v[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint64_t k = begin + (uint64_t)r * 4 * B + 4u * threadIdx.x;
 #pragma unroll
       for (int c = 0; c < 4; ++c) v[r][c] = k + c < n ? src((uint32_t)(k + c)) : 0u;
     }
@@ -338,27 +342,59 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
   for (int q = 0; q < NW; ++q) s_wc[q][threadIdx.x] = 0;
   uint32_t key[kWaveRounds], val[kWaveRounds], lr[kWaveRounds];
   uint2 pay[kPay ? kWaveRounds : 1];
+  // Each pass reads its input once: streaming loads leave the cache to the
+  // histogram, the offsets and the output being assembled.  Every load of
+  // the chunk is issued before any result is used (a whole chunk, the common
+  // case, loads without conditions; the validity flags of a dense pass are
+  // turned into the taken mask only afterwards), and a dense pass loads every
+  // entry's key and payload whether or not it takes it: taken and skipped
+  // entries share cache lines.
+  uint32_t flag[kDense ? kWaveRounds : 1];
+  const uint32_t lane0 = (uint32_t)w * kWaveKeys + (uint32_t)lane;
+  if (cnt == (uint32_t)kSortChunk) {   // uniform
+#pragma unroll
+    for (int r = 0; r < kWaveRounds; ++r) {
+      const uint64_t k = begin + lane0 + (uint32_t)r * 64u;
+      key[r] = __builtin_nontemporal_load(kin + k);
+      if constexpr (kDense)
+        flag[r] = __builtin_nontemporal_load(valid + k);
+      else
+        val[r] = __builtin_nontemporal_load(vin + k);
+      if constexpr (kPay) {
+        const uint32_t* pp = reinterpret_cast<const uint32_t*>(pin + k);
+        pay[r] = make_uint2(__builtin_nontemporal_load(pp), __builtin_nontemporal_load(pp + 1));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kWaveRounds; ++r) {
+      const uint32_t li = lane0 + (uint32_t)r * 64u;
+      const bool here = li < cnt;
+      key[r] = here ? __builtin_nontemporal_load(kin + begin + li) : 0u;
+      if constexpr (kDense)
+        flag[r] = here ? __builtin_nontemporal_load(valid + begin + li) : 0u;
+      else
+        val[r] = here ? __builtin_nontemporal_load(vin + begin + li) : 0u;
+      if constexpr (kPay) {
+        if (here) {
+          const uint32_t* pp = reinterpret_cast<const uint32_t*>(pin + begin + li);
+          pay[r] = make_uint2(__builtin_nontemporal_load(pp), __builtin_nontemporal_load(pp + 1));
+        } else {
+          pay[r] = make_uint2(0u, 0u);
+        }
+      }
+    }
+  }
   uint32_t in_mask = 0;   // bit r: this lane's key of round r takes part
 #pragma unroll
   for (int r = 0; r < kWaveRounds; ++r) {
-    const uint32_t li = (uint32_t)w * kWaveKeys + (uint32_t)r * 64u + (uint32_t)lane;
-    const bool in = li < cnt && (!kDense || __builtin_nontemporal_load(valid + begin + li) != 0u);
-    in_mask |= in ? 1u << r : 0u;
-    // each pass reads its input once: streaming loads leave the cache to the
-    // histogram, the offsets and the output being assembled
-    key[r] = in ? __builtin_nontemporal_load(kin + begin + li) : 0u;
-    if constexpr (kDense)
+    const uint32_t li = lane0 + (uint32_t)r * 64u;
+    bool in = li < cnt;
+    if constexpr (kDense) {
+      in = in && flag[r] != 0u;
       val[r] = value_base + (uint32_t)(begin + li);
-    else
-      val[r] = in ? __builtin_nontemporal_load(vin + begin + li) : 0u;
-    if constexpr (kPay) {
-      if (in) {
-        const uint32_t* pp = reinterpret_cast<const uint32_t*>(pin + begin + li);
-        pay[r] = make_uint2(__builtin_nontemporal_load(pp), __builtin_nontemporal_load(pp + 1));
-      } else {
-        pay[r] = make_uint2(0u, 0u);
-      }
     }
+    in_mask |= in ? 1u << r : 0u;
   }
   __syncthreads();
   // 1. stable ranks within (wavefront, digit)
