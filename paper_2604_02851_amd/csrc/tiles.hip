@@ -513,10 +513,11 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 __global__ __launch_bounds__(B) void k_emit_chunk(const uint32_t* sorted_vis, const uint32_t* koff,
                                                   const uint32_t* firsts, const uint32_t* nvis_p,
                                                   const uint32_t* total_keys, const ushort4* sorted_rect,
-                                                  const ViewInfo* views, int64_t n_gauss, int32_t tile_begin,
-                                                  uint32_t cap, int64_t nblocks, uint32_t dmask0, uint32_t* keys,
-                                                  uint32_t* vals, uint32_t* hist) {
+                                                  const ViewInfo* views, int32_t n_views, int64_t n_gauss,
+                                                  int32_t tile_begin, uint32_t cap, int64_t nblocks, uint32_t dmask0,
+                                                  uint32_t* keys, uint32_t* vals, uint32_t* hist) {
   __shared__ uint32_t h[NW][256];       // first-pass digit counts, one histogram per wavefront
+  __shared__ int2 s_view[kMaxViews];    // (first tile relative to the call's first tile, tiles per row)
   __shared__ uint32_t s_off[NW][64];
   __shared__ uint32_t s_vi[NW][64];
   __shared__ ushort4 s_rect[NW][64];
@@ -527,8 +528,11 @@ __global__ __launch_bounds__(B) void k_emit_chunk(const uint32_t* sorted_vis, co
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < NW; ++q) h[q][threadIdx.x] = 0u;
+  for (int v = threadIdx.x; v < n_views; v += B) s_view[v] = make_int2(views[v].tile_base - tile_begin, views[v].tiles_x);
   __syncthreads();
   const uint32_t all_keys = *total_keys;
+  const uint32_t ng = (uint32_t)n_gauss;
+  const float inv_ng = 1.f / (float)ng;
   const uint32_t n = min(all_keys, cap);
   const uint64_t S0 = (uint64_t)blockIdx.x * kSortChunk;
   if (S0 < n) {
@@ -537,19 +541,30 @@ __global__ __launch_bounds__(B) void k_emit_chunk(const uint32_t* sorted_vis, co
     for (uint32_t g = firsts[blockIdx.x] + (uint32_t)w * 64u; g < nvis; g += NW * 64u) {
       const uint32_t k = g + (uint32_t)lane;
       const bool valid = k < nvis;
-      const uint32_t off = valid ? koff[k] : 0xffffffffu;
-      if ((uint32_t)__builtin_amdgcn_readfirstlane((int)off) >= S1) break;   // the group starts past the chunk
-      uint32_t end = 0;
+      // the group's loads go out together; the test whether the group starts
+      // past the chunk waits for them
+      uint32_t off = 0xffffffffu, end = 0, vi = 0;
+      ushort4 r = make_ushort4(0, 0, 0, 0);
       if (valid) {
-        const uint32_t vi = sorted_vis[k];
+        off = koff[k];
         end = k + 1 < nvis ? koff[k + 1] : all_keys;
-        const int v = (int)(vi / (uint64_t)n_gauss);
-        const ushort4 r = sorted_rect[k];
+        vi = sorted_vis[k];
+        r = sorted_rect[k];
+      }
+      if ((uint32_t)__builtin_amdgcn_readfirstlane((int)off) >= S1) break;   // the group starts past the chunk
+      if (valid) {
+        // view = vi / n_gauss: a float estimate (off by at most one, as the
+        // quotient is below 2^8) corrected to the exact integer quotient
+        uint32_t v = (uint32_t)((float)vi * inv_ng);
+        const uint64_t lo = (uint64_t)v * ng;
+        if (lo > vi) v -= 1u;
+        else if (lo + ng <= vi) v += 1u;
+        const int2 vw = s_view[v];
         s_vi[w][lane] = vi;
         s_rect[w][lane] = r;
         s_rw[w][lane] = __builtin_amdgcn_rcpf((float)((uint32_t)r.z - r.x + 1u));
-        s_row[w][lane] = views[v].tile_base - tile_begin;
-        s_tx[w][lane] = views[v].tiles_x;
+        s_row[w][lane] = vw.x;
+        s_tx[w][lane] = vw.y;
       }
       s_off[w][lane] = off;
       __builtin_amdgcn_wave_barrier();
@@ -851,8 +866,8 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   if (bits == 0) bits = 1;
   const int first_bits = bits - 8 * ((bits - 1) / 8);
   hipLaunchKernelGGL(k_emit_chunk, dim3((unsigned)key_chunks), dim3(B), 0, st, sorted_vis, koff, firsts, &ctr->nvis,
-                     &ctr->keys, reinterpret_cast<const ushort4*>(sorted_rect), pl.d_views, N, tile_begin, cap,
-                     key_chunks, (1u << first_bits) - 1u, keys_a, vals_a, seg<uint32_t>(ws, pl.ws.hist));
+                     &ctr->keys, reinterpret_cast<const ushort4*>(sorted_rect), pl.d_views, pl.n_views, N, tile_begin,
+                     cap, key_chunks, (1u << first_bits) - 1u, keys_a, vals_a, seg<uint32_t>(ws, pl.ws.hist));
   // 5. stable sort by tile (relative to the first tile of the call)
   e = radix_sort(pl, ws, keys_a, vals_a, keys_b, vals_b, nullptr, nullptr, pl.cap, &ctr->keys, bits, &in_b, st, nullptr,
                  true, first_bits);
