@@ -876,7 +876,10 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges + tile_begin), 0u, 2 * ntiles, st);
   if (e != hipSuccess) return e;
   const uint32_t* sk = in_b ? keys_b : keys_a;
-  const int64_t rblocks = cdiv(pl.cap, 1024) < 8192 ? cdiv(pl.cap, 1024) : 8192;
+  // one quad of keys per thread (the loop in the kernel covers any size):
+  // every wavefront's loads are in flight at once instead of one quad after
+  // another per thread
+  const int64_t rblocks = cdiv(cdiv(pl.cap, 4), 256) < 0x7fffffffll ? cdiv(cdiv(pl.cap, 4), 256) : 0x7fffffffll;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)rblocks), dim3(256), 0, st, sk, &ctr->keys, cap, tile_begin, ranges);
   // 7. longest-first order of the call's tiles for the persistent compositing kernels
   if (pl.schedule == 3 && ntiles > 0) {
