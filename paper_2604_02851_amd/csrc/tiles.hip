@@ -253,14 +253,15 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
 }
 
 // ---- radix sort (LSD, digits of up to 8 bits, stable) -----------------------
-// Digit counts of kHistChunks consecutive chunks per workgroup, one chunk
-// after the other; each thread loads its kSortItems keys of a chunk with
-// 16-byte loads (the scan chunk layout) and counts them with LDS atomics
-// into its wavefront's own sub-histogram, which bounds the contention of
-// skewed digits (the exponent byte of depth keys) to one wavefront.  Counts
-// are stored digit-major, hist[d * nblocks + chunk]; a workgroup writes each
-// digit's kHistChunks counts as one contiguous run.
-constexpr int kHistChunks = 4;
+// Digit counts of one chunk per workgroup; each thread loads its kSortItems
+// keys with 16-byte loads (the scan chunk layout) and counts them with LDS
+// atomics into one of kHistCopies interleaved copies of its wavefront's
+// histogram (copy lane % kHistCopies; the copies of a digit are adjacent
+// words, so in different banks).  A skewed digit (the exponent byte of depth
+// keys) then meets at most 64 / kHistCopies lanes of one wavefront at each
+// address instead of 64.  Counts are stored digit-major, hist[d * nblocks +
+// chunk].
+constexpr int kHistCopies = 4;
 
 // With `valid` (the first depth pass, reading the dense (view, Gaussian)
 // arrays), key k counts only where valid[k] != 0: the pass then compacts the
@@ -268,37 +269,33 @@ constexpr int kHistChunks = 4;
 __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* keys, const uint32_t* valid, int64_t max_count,
                                                   const uint32_t* dcount, int shift, uint32_t dmask, int64_t nblocks,
                                                   uint32_t* hist) {
-  __shared__ uint32_t h[NW][kHistChunks][256];
+  __shared__ uint32_t h[NW][256][kHistCopies];
 #pragma unroll
-  for (int q = 0; q < NW * kHistChunks; ++q) (&h[0][0][0])[q * 256 + threadIdx.x] = 0;
+  for (int q = 0; q < NW * kHistCopies; ++q) (&h[0][0][0])[q * 256 + threadIdx.x] = 0;
   __syncthreads();
   const uint32_t n = dev_count(dcount, max_count);
-  const int w = threadIdx.x >> 6;
-  const int64_t c0 = (int64_t)blockIdx.x * kHistChunks;
-  const ScanSrc src{keys, nullptr, 0};
-  for (int cc = 0; cc < kHistChunks; ++cc) {
-    const uint64_t begin = (uint64_t)(c0 + cc) * kSortChunk;
-    if (c0 + cc >= nblocks || begin >= n) break;
+  const int w = threadIdx.x >> 6, copy = threadIdx.x & (kHistCopies - 1);
+  const int64_t chunk = blockIdx.x;
+  const uint64_t begin = (uint64_t)chunk * kSortChunk;
+  if (chunk < nblocks && begin < n) {
     uint32_t v[kRounds][4], ok[kRounds][4];
-    load_chunk(src, begin, n, v);
+    load_chunk(ScanSrc{keys, nullptr, 0}, begin, n, v);
     if (valid) load_chunk(ScanSrc{valid, nullptr, 1}, begin, n, ok);
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         if (begin + (uint64_t)r * 4 * B + 4u * threadIdx.x + c < n && (!valid || ok[r][c]))
-          atomicAdd(&h[w][cc][(v[r][c] >> shift) & dmask], 1u);
+          atomicAdd(&h[w][(v[r][c] >> shift) & dmask][copy], 1u);
     }
   }
   __syncthreads();
-  uint32_t* dst = hist + (int64_t)threadIdx.x * nblocks + c0;
+  uint32_t t = 0;
 #pragma unroll
-  for (int c = 0; c < kHistChunks; ++c) {
-    uint32_t t = 0;
+  for (int q = 0; q < NW; ++q)
 #pragma unroll
-    for (int q = 0; q < NW; ++q) t += h[q][c][threadIdx.x];
-    if (c0 + c < nblocks) dst[c] = t;
-  }
+    for (int k = 0; k < kHistCopies; ++k) t += h[q][threadIdx.x][k];
+  if (chunk < nblocks) hist[(int64_t)threadIdx.x * nblocks + chunk] = t;
 }
 
 // Scatter of one chunk (kSortChunk keys, split into NW contiguous wavefront
@@ -782,7 +779,7 @@ static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* v
     if (nb > 0) {
       const uint32_t* dc = from_dense ? nullptr : dcount;
       if (!(first_hist_ready && shift == 0))
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)cdiv(nb, kHistChunks)), dim3(B), 0, st, ki,
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(B), 0, st, ki,
                          from_dense ? dense->valid : nullptr, max_count, dc, shift, dmask, nb, hist);
       // a dense pass's digit counts total the taken keys
       hipError_t e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * nb, nullptr, partial, pl.ws.partial_len,
