@@ -348,6 +348,9 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
   // entries share cache lines.
   uint32_t flag[kDense ? kWaveRounds : 1];
   const uint32_t lane0 = (uint32_t)w * kWaveKeys + (uint32_t)lane;
+  // this chunk's global start of digit threadIdx.x, needed only after the
+  // ranking: loaded with the keys so that its latency overlaps theirs
+  const uint32_t digit_base = hist_scanned[(int64_t)threadIdx.x * nblocks + blockIdx.x];
   if (cnt == (uint32_t)kSortChunk) {   // uniform
 #pragma unroll
     for (int r = 0; r < kWaveRounds; ++r) {
@@ -432,7 +435,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
       s_wc[q][d] = run;
       run += c[q];
     }
-    s_gbase[d] = hist_scanned[(int64_t)d * nblocks + blockIdx.x] - lstart;
+    s_gbase[d] = digit_base - lstart;
   }
   __syncthreads();
   // 3. local placement in digit order
