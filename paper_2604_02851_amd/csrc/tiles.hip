@@ -312,6 +312,93 @@ constexpr int kWaveKeys = kSortChunk / NW;
 constexpr int kWaveRounds = kWaveKeys / 64;
 constexpr int kOutRounds = kSortChunk / B;
 
+// Steps 1-4 of a scatter for the keys a chunk's wavefronts hold (key[r] and
+// val[r] of lane l of wavefront w are chunk entry w kWaveKeys + r 64 + l;
+// bit r of in_mask says whether it takes part).  s_wc must be zero and
+// visible to the whole workgroup on entry.  pos[] (each key's local
+// position) and dst[] (with kPay: the global position of local entry
+// r B + threadIdx.x) serve a payload that follows the keys; returns the
+// number of keys taken.  With kBounded, positions at or past `limit` are not
+// written (a safeguard where the digit counts come from another kernel's
+// arithmetic rather than from the keys themselves).
+template <bool kPay, bool kBounded = false>
+__device__ __forceinline__ uint32_t rank_and_write(const uint32_t (&key)[kWaveRounds], const uint32_t (&val)[kWaveRounds],
+                                                   uint32_t in_mask, uint32_t digit_base, int shift, uint32_t dmask,
+                                                   uint32_t* s_key, uint32_t* s_val, uint32_t (*s_wc)[256],
+                                                   uint32_t* s_gbase, uint32_t* s_tmp, uint32_t& s_taken,
+                                                   uint32_t* kout, uint32_t* vout, uint32_t (&pos)[kWaveRounds],
+                                                   uint32_t (&dst)[kPay ? kOutRounds : 1], uint32_t limit = 0u) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t lr[kWaveRounds];
+  // 1. stable ranks within (wavefront, digit)
+#pragma unroll
+  for (int r = 0; r < kWaveRounds; ++r) {
+    const bool taking = (in_mask >> r) & 1u;
+    const uint32_t digit = (key[r] >> shift) & dmask;
+    uint64_t match = __ballot(taking);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (digit >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      match &= bit ? bb : ~bb;
+    }
+    const uint32_t below = (uint32_t)__popcll(match & lt_mask);
+    const uint32_t before = taking ? s_wc[w][digit] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    lr[r] = before + below;
+    if (taking && below == 0) s_wc[w][digit] = before + (uint32_t)__popcll(match);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // 2. chunk-local digit starts and per-wavefront group starts
+  {
+    const int d = threadIdx.x;
+    uint32_t c[NW], tot = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      c[q] = s_wc[q][d];
+      tot += c[q];
+    }
+    uint32_t all;
+    const uint32_t lstart = block_excl_scan(tot, s_tmp, &all);
+    if (d == 0) s_taken = all;
+    uint32_t run = lstart;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      s_wc[q][d] = run;
+      run += c[q];
+    }
+    s_gbase[d] = digit_base - lstart;
+  }
+  __syncthreads();
+  // 3. local placement in digit order
+#pragma unroll
+  for (int r = 0; r < kWaveRounds; ++r) {
+    pos[r] = s_wc[w][(key[r] >> shift) & dmask] + lr[r];
+    if ((in_mask >> r) & 1u) {
+      s_key[pos[r]] = key[r];
+      s_val[pos[r]] = val[r];
+    }
+  }
+  __syncthreads();
+  // 4. coalesced write-out
+  const uint32_t taken = s_taken;
+#pragma unroll
+  for (int r = 0; r < kOutRounds; ++r) {
+    const uint32_t i = (uint32_t)r * B + threadIdx.x;
+    if (i < taken) {
+      const uint32_t k = s_key[i];
+      const uint32_t d = s_gbase[(k >> shift) & dmask] + i;
+      if (kBounded && d >= limit) continue;
+      kout[d] = k;
+      vout[d] = s_val[i];
+      if constexpr (kPay) dst[r] = d;
+    }
+  }
+  return taken;
+}
+
 // kDense (the first depth pass): the input is the dense (view, Gaussian)
 // range, key k is taken only where valid[k] != 0, and its value is
 // value_base + k (the pair's index), so the pass compacts the visible pairs
@@ -334,10 +421,9 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
   if (begin >= n) return;
   const uint32_t cnt = (uint32_t)min((uint64_t)kSortChunk, (uint64_t)n - begin);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int q = 0; q < NW; ++q) s_wc[q][threadIdx.x] = 0;
-  uint32_t key[kWaveRounds], val[kWaveRounds], lr[kWaveRounds];
+  uint32_t key[kWaveRounds], val[kWaveRounds];
   uint2 pay[kPay ? kWaveRounds : 1];
   // Each pass reads its input once: streaming loads leave the cache to the
   // histogram, the offsets and the output being assembled.  Every load of
@@ -397,72 +483,10 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
     in_mask |= in ? 1u << r : 0u;
   }
   __syncthreads();
-  // 1. stable ranks within (wavefront, digit)
-#pragma unroll
-  for (int r = 0; r < kWaveRounds; ++r) {
-    const bool taking = (in_mask >> r) & 1u;
-    const uint32_t digit = (key[r] >> shift) & dmask;
-    uint64_t match = __ballot(taking);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (digit >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      match &= bit ? bb : ~bb;
-    }
-    const uint32_t below = (uint32_t)__popcll(match & lt_mask);
-    const uint32_t before = taking ? s_wc[w][digit] : 0u;
-    __builtin_amdgcn_wave_barrier();
-    lr[r] = before + below;
-    if (taking && below == 0) s_wc[w][digit] = before + (uint32_t)__popcll(match);
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-  // 2. chunk-local digit starts and per-wavefront group starts
-  {
-    const int d = threadIdx.x;
-    uint32_t c[NW], tot = 0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) {
-      c[q] = s_wc[q][d];
-      tot += c[q];
-    }
-    uint32_t all;
-    const uint32_t lstart = block_excl_scan(tot, s_tmp, &all);
-    if (d == 0) s_taken = all;
-    uint32_t run = lstart;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) {
-      s_wc[q][d] = run;
-      run += c[q];
-    }
-    s_gbase[d] = digit_base - lstart;
-  }
-  __syncthreads();
-  // 3. local placement in digit order
   uint32_t pos[kWaveRounds];
-#pragma unroll
-  for (int r = 0; r < kWaveRounds; ++r) {
-    pos[r] = s_wc[w][(key[r] >> shift) & dmask] + lr[r];
-    if ((in_mask >> r) & 1u) {
-      s_key[pos[r]] = key[r];
-      s_val[pos[r]] = val[r];
-    }
-  }
-  __syncthreads();
-  // 4. coalesced write-out
-  const uint32_t taken = s_taken;
   uint32_t dst[kPay ? kOutRounds : 1];
-#pragma unroll
-  for (int r = 0; r < kOutRounds; ++r) {
-    const uint32_t i = (uint32_t)r * B + threadIdx.x;
-    if (i < taken) {
-      const uint32_t k = s_key[i];
-      const uint32_t d = s_gbase[(k >> shift) & dmask] + i;
-      kout[d] = k;
-      vout[d] = s_val[i];
-      if constexpr (kPay) dst[r] = d;
-    }
-  }
+  const uint32_t taken = rank_and_write<kPay>(key, val, in_mask, digit_base, shift, dmask, s_key, s_val, s_wc, s_gbase,
+                                              s_tmp, s_taken, kout, vout, pos, dst);
   if constexpr (kPay) {
     uint2* s_pay = reinterpret_cast<uint2*>(s_kv);
     __syncthreads();
@@ -479,15 +503,15 @@ __global__ __launch_bounds__(B) void k_radix_scatter(const uint32_t* kin, const 
 }
 
 // ---- key emission in depth order -----------------------------------------
-// Workgroup c writes the key slots [c K, (c+1) K) of one chunk of the tile
-// sort (K = kSortChunk), and with them the digit counts of that sort's first
-// pass for the chunk, in the layout k_radix_hist writes (hist[d * nblocks +
-// c]), so the first tile pass needs no histogram read of its own.  Its
-// wavefronts take the depth-sorted visible pairs from firsts[c], the pair
-// owning slot c K, onwards, 64 consecutive pairs at a time, until a group
-// starts past the chunk; a pair that straddles a chunk boundary is written
-// in part by both workgroups.  Within a group, lane l produces output slot
-// S + l in each round (coalesced stores).  The pair owning a slot is found
+// Workgroup c produces the key slots [c K, (c+1) K) of one chunk of the tile
+// sort (K = kSortChunk), twice: k_emit_count counts the digits of the sort's
+// first pass over them, and after the scan of those counts k_emit_scatter
+// produces them again and performs that first pass, so the keys in slot
+// order are never stored.  Its wavefronts take the depth-sorted visible
+// pairs from firsts[c], the pair owning slot c K, onwards, 64 consecutive
+// pairs at a time, until a group starts past the chunk; a pair that
+// straddles a chunk boundary is produced in part by both workgroups.  Within
+// a group, lane l produces slot S + l in each round.  The pair owning a slot is found
 // without searching: each pair whose first slot falls in the round marks that
 // slot with its index, and an inclusive max-scan over the lanes (carried from
 // the previous round, and started at the last pair that began at or before
@@ -510,39 +534,136 @@ __device__ __forceinline__ int wave_incl_max(int v) {
   return v;
 }
 
-__global__ __launch_bounds__(B) void k_emit_chunk(const uint32_t* sorted_vis, const uint32_t* koff,
+// Per-wavefront staging of the walk: the current group of 64 pairs.
+struct WalkLds {
+  uint32_t off[NW][64];    // first key slot
+  uint32_t vi[NW][64];     // (view, Gaussian) index
+  ushort4 rect[NW][64];    // tile rectangle
+  uint32_t view[NW][64];
+  int32_t mark[NW][64];
+};
+
+// The walk over chunk blockIdx.x of the key slots, [S0, S1): every slot is
+// produced once, by one lane, which calls emit(slot, key, value).  s_view
+// holds each view's (first tile relative to the call's first tile, tiles
+// per row) and must be visible to the workgroup on entry.
+template <class Emit>
+__device__ __forceinline__ void emit_walk(WalkLds& L, const uint32_t* sorted_vis, const uint32_t* koff,
+                                          const uint32_t* firsts, uint32_t nvis, uint32_t all_keys,
+                                          const ushort4* sorted_rect, const int2* s_view, uint32_t ng, uint64_t S0,
+                                          uint32_t S1, Emit emit) {
+  uint32_t (&s_off)[NW][64] = L.off;
+  uint32_t (&s_vi)[NW][64] = L.vi;
+  ushort4 (&s_rect)[NW][64] = L.rect;
+  uint32_t (&s_v)[NW][64] = L.view;
+  int32_t (&s_mark)[NW][64] = L.mark;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const float inv_ng = 1.f / (float)ng;
+  for (uint32_t g = firsts[blockIdx.x] + (uint32_t)w * 64u; g < nvis; g += NW * 64u) {
+    const uint32_t k = g + (uint32_t)lane;
+    const bool valid = k < nvis;
+    // the group's loads go out together; the test whether the group starts
+    // past the chunk waits for them
+    uint32_t off = 0xffffffffu, end = 0, vi = 0;
+    ushort4 r = make_ushort4(0, 0, 0, 0);
+    if (valid) {
+      off = koff[k];
+      end = k + 1 < nvis ? koff[k + 1] : all_keys;
+      vi = sorted_vis[k];
+      r = sorted_rect[k];
+    }
+    if ((uint32_t)__builtin_amdgcn_readfirstlane((int)off) >= S1) break;   // the group starts past the chunk
+    if (valid) {
+      // view = vi / n_gauss: a float estimate (off by at most one, as the
+      // quotient is below 2^8) corrected to the exact integer quotient
+      uint32_t v = (uint32_t)((float)vi * inv_ng);
+      const uint64_t lo = (uint64_t)v * ng;
+      if (lo > vi) v -= 1u;
+      else if (lo + ng <= vi) v += 1u;
+      s_vi[w][lane] = vi;
+      s_rect[w][lane] = r;
+      s_v[w][lane] = v;
+    }
+    s_off[w][lane] = off;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t start = max(s_off[w][0], (uint32_t)S0);
+    uint32_t stop = end;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) stop = max(stop, (uint32_t)__shfl_xor((int)stop, d, 64));
+    stop = min(stop, S1);
+    // the last pair of the group that began at or before `start`
+    int carry = (int)__popcll(__ballot(valid && off <= start)) - 1;
+    for (uint32_t S = start; S < stop; S += 64) {
+      s_mark[w][lane] = -1;
+      __builtin_amdgcn_wave_barrier();
+      if (valid && off >= S && off - S < 64u) s_mark[w][off - S] = lane;
+      __builtin_amdgcn_wave_barrier();
+      const int own = wave_incl_max(max(s_mark[w][lane], carry));
+      carry = __builtin_amdgcn_readlane(own, 63);
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t slot = S + (uint32_t)lane;
+      if (slot < stop) {
+        const ushort4 r = s_rect[w][own];
+        const uint32_t m = slot - s_off[w][own];
+        const uint32_t width = (uint32_t)r.z - r.x + 1u;
+        uint32_t q = (uint32_t)((float)m * __builtin_amdgcn_rcpf((float)width));
+        int32_t rem = (int32_t)(m - q * width);
+        if (rem < 0) {
+          q -= 1u;
+          rem += (int32_t)width;
+        } else if (rem >= (int32_t)width) {
+          q += 1u;
+          rem -= (int32_t)width;
+        }
+        const uint32_t ty = r.y + q, tx = r.x + (uint32_t)rem;
+        const int2 vw = s_view[s_v[w][own]];
+        const uint32_t key = (uint32_t)(vw.x + (int32_t)(ty * (uint32_t)vw.y + tx));
+        emit(slot, key, s_vi[w][own]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Digit counts of the tile sort's first pass (key bits dmask0, a power of
+// two minus one) for every chunk, in the layout k_radix_hist writes
+// (hist[d * nblocks + c]), without producing the keys: the keys a pair has
+// in one tile row of its rectangle are consecutive integers, so the row adds
+// one to every digit len / (dmask0 + 1) times and to a cyclic range of
+// len % (dmask0 + 1) digits once.  Each lane takes one pair of the chunk
+// (clipped to the chunk's slots) row by row; the ranges go into a
+// difference array, whose prefix sums are the counts.
+__global__ __launch_bounds__(B) void k_emit_count(const uint32_t* sorted_vis, const uint32_t* koff,
                                                   const uint32_t* firsts, const uint32_t* nvis_p,
                                                   const uint32_t* total_keys, const ushort4* sorted_rect,
                                                   const ViewInfo* views, int32_t n_views, int64_t n_gauss,
                                                   int32_t tile_begin, uint32_t cap, int64_t nblocks, uint32_t dmask0,
-                                                  uint32_t* keys, uint32_t* vals, uint32_t* hist) {
-  __shared__ uint32_t h[NW][256];       // first-pass digit counts, one histogram per wavefront
-  __shared__ int2 s_view[kMaxViews];    // (first tile relative to the call's first tile, tiles per row)
-  __shared__ uint32_t s_off[NW][64];
-  __shared__ uint32_t s_vi[NW][64];
-  __shared__ ushort4 s_rect[NW][64];
-  __shared__ float s_rw[NW][64];        // 1 / rectangle width
-  __shared__ int32_t s_row[NW][64];     // first tile of the pair's view, relative to the call's first tile
-  __shared__ int32_t s_tx[NW][64];      // tiles per row in the pair's view
-  __shared__ int32_t s_mark[NW][64];
+                                                  uint32_t* hist) {
+  __shared__ int32_t s_diff[257];
+  __shared__ uint32_t s_full;
+  __shared__ uint32_t s_tmp[NW];
+  __shared__ int2 s_view[kMaxViews];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NW; ++q) h[q][threadIdx.x] = 0u;
+  s_diff[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    s_diff[256] = 0;
+    s_full = 0u;
+  }
   for (int v = threadIdx.x; v < n_views; v += B) s_view[v] = make_int2(views[v].tile_base - tile_begin, views[v].tiles_x);
   __syncthreads();
   const uint32_t all_keys = *total_keys;
-  const uint32_t ng = (uint32_t)n_gauss;
-  const float inv_ng = 1.f / (float)ng;
   const uint32_t n = min(all_keys, cap);
+  const uint32_t M = dmask0 + 1u;
+  const int bits0 = __popc(dmask0);
   const uint64_t S0 = (uint64_t)blockIdx.x * kSortChunk;
   if (S0 < n) {
     const uint32_t S1 = (uint32_t)min((uint64_t)n, S0 + kSortChunk);
     const uint32_t nvis = *nvis_p;
+    const uint32_t ng = (uint32_t)n_gauss;
+    const float inv_ng = 1.f / (float)ng;
     for (uint32_t g = firsts[blockIdx.x] + (uint32_t)w * 64u; g < nvis; g += NW * 64u) {
       const uint32_t k = g + (uint32_t)lane;
       const bool valid = k < nvis;
-      // the group's loads go out together; the test whether the group starts
-      // past the chunk waits for them
       uint32_t off = 0xffffffffu, end = 0, vi = 0;
       ushort4 r = make_ushort4(0, 0, 0, 0);
       if (valid) {
@@ -552,66 +673,109 @@ __global__ __launch_bounds__(B) void k_emit_chunk(const uint32_t* sorted_vis, co
         r = sorted_rect[k];
       }
       if ((uint32_t)__builtin_amdgcn_readfirstlane((int)off) >= S1) break;   // the group starts past the chunk
-      if (valid) {
-        // view = vi / n_gauss: a float estimate (off by at most one, as the
-        // quotient is below 2^8) corrected to the exact integer quotient
-        uint32_t v = (uint32_t)((float)vi * inv_ng);
-        const uint64_t lo = (uint64_t)v * ng;
-        if (lo > vi) v -= 1u;
-        else if (lo + ng <= vi) v += 1u;
+      const uint32_t lo = max(off, (uint32_t)S0), hi = min(end, S1);
+      if (valid && lo < hi) {
+        uint32_t v = (uint32_t)((float)vi * inv_ng);   // vi / n_gauss, corrected as in the walk
+        const uint64_t lv = (uint64_t)v * ng;
+        if (lv > vi) v -= 1u;
+        else if (lv + ng <= vi) v += 1u;
         const int2 vw = s_view[v];
-        s_vi[w][lane] = vi;
-        s_rect[w][lane] = r;
-        s_rw[w][lane] = __builtin_amdgcn_rcpf((float)((uint32_t)r.z - r.x + 1u));
-        s_row[w][lane] = vw.x;
-        s_tx[w][lane] = vw.y;
-      }
-      s_off[w][lane] = off;
-      __builtin_amdgcn_wave_barrier();
-      const uint32_t start = max(s_off[w][0], (uint32_t)S0);
-      uint32_t stop = end;
-#pragma unroll
-      for (int d = 32; d > 0; d >>= 1) stop = max(stop, (uint32_t)__shfl_xor((int)stop, d, 64));
-      stop = min(stop, S1);
-      // the last pair of the group that began at or before `start`
-      int carry = (int)__popcll(__ballot(valid && off <= start)) - 1;
-      for (uint32_t S = start; S < stop; S += 64) {
-        s_mark[w][lane] = -1;
-        __builtin_amdgcn_wave_barrier();
-        if (valid && off >= S && off - S < 64u) s_mark[w][off - S] = lane;
-        __builtin_amdgcn_wave_barrier();
-        const int own = wave_incl_max(max(s_mark[w][lane], carry));
-        carry = __builtin_amdgcn_readlane(own, 63);
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t slot = S + (uint32_t)lane;
-        if (slot < stop) {
-          const ushort4 r = s_rect[w][own];
-          const uint32_t m = slot - s_off[w][own];
-          const uint32_t width = (uint32_t)r.z - r.x + 1u;
-          uint32_t q = (uint32_t)((float)m * s_rw[w][own]);
-          int32_t rem = (int32_t)(m - q * width);
-          if (rem < 0) {
-            q -= 1u;
-            rem += (int32_t)width;
-          } else if (rem >= (int32_t)width) {
-            q += 1u;
-            rem -= (int32_t)width;
+        const uint32_t width = (uint32_t)r.z - r.x + 1u;
+        const uint32_t m0 = lo - off, m1 = hi - off;   // the pair's slots in the chunk, [m0, m1)
+        const uint32_t q0 = m0 / width, c0 = m0 - q0 * width;
+        const uint32_t q1 = (m1 - 1u) / width, c1 = (m1 - 1u) - q1 * width;
+        uint32_t full = 0;
+        for (uint32_t q = q0; q <= q1; ++q) {
+          const uint32_t cs = q == q0 ? c0 : 0u, ce = q == q1 ? c1 : width - 1u;
+          const uint32_t a = (uint32_t)(vw.x + (int32_t)(((uint32_t)r.y + q) * (uint32_t)vw.y + r.x + cs));
+          const uint32_t len = ce - cs + 1u;
+          full += len >> bits0;
+          const uint32_t rem = len & dmask0;
+          if (rem) {
+            const uint32_t s = a & dmask0, e = s + rem;
+            atomicAdd(&s_diff[s], 1);
+            if (e < M) {
+              atomicAdd(&s_diff[e], -1);
+            } else if (e > M) {
+              atomicAdd(&s_diff[0], 1);
+              atomicAdd(&s_diff[e - M], -1);
+            }
           }
-          const uint32_t ty = r.y + q, tx = r.x + (uint32_t)rem;
-          const uint32_t key = (uint32_t)(s_row[w][own] + (int32_t)(ty * (uint32_t)s_tx[w][own] + tx));
-          keys[slot] = key;
-          vals[slot] = s_vi[w][own];
-          atomicAdd(&h[w][key & dmask0], 1u);
         }
+        if (full) atomicAdd(&s_full, full);
       }
-      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
-  uint32_t t = 0;
+  const uint32_t d = threadIdx.x;
+  const int32_t x = d < M ? s_diff[d] : 0;
+  uint32_t total;
+  const uint32_t below = block_excl_scan((uint32_t)x, s_tmp, &total);
+  hist[(int64_t)d * nblocks + blockIdx.x] = d < M ? below + (uint32_t)x + s_full : 0u;
+}
+
+// The tile sort's first pass fused with the key emission: workgroup c walks
+// its chunk's slots again, places each (key, value) at its slot in LDS, and
+// then ranks and scatters them as k_radix_scatter does (digits key & dmask0,
+// hist_scanned the scanned counts of k_emit_count), so the emitted keys
+// never go through HBM in slot order.  Its LDS use is kept at 40 KB (the
+// walk's staging shares space with the ranking's counters) for four
+// workgroups per compute unit; with 48 KB and three it was no faster than
+// emitting and sorting in separate kernels.
+__global__ __launch_bounds__(B) void k_emit_scatter(const uint32_t* sorted_vis, const uint32_t* koff,
+                                                    const uint32_t* firsts, const uint32_t* nvis_p,
+                                                    const uint32_t* total_keys, const ushort4* sorted_rect,
+                                                    const ViewInfo* views, int32_t n_views, int64_t n_gauss,
+                                                    int32_t tile_begin, uint32_t cap, int64_t nblocks, uint32_t dmask0,
+                                                    const uint32_t* hist_scanned, uint32_t* kout, uint32_t* vout) {
+  __shared__ __align__(16) uint32_t s_kv[2 * kSortChunk];   // keys | values
+  __shared__ int2 s_view[kMaxViews];
+  __shared__ union {   // the walk's staging, then the ranking's counters
+    WalkLds walk;
+    struct {
+      uint32_t wc[NW][256];
+      uint32_t gbase[256];
+      uint32_t tmp[NW];
+      uint32_t taken;
+    } rank;
+  } u;
+  uint32_t* s_key = s_kv;
+  uint32_t* s_val = s_kv + kSortChunk;
+  const uint32_t all_keys = *total_keys;
+  const uint32_t n = min(all_keys, cap);
+  const uint64_t S0 = (uint64_t)blockIdx.x * kSortChunk;
+  if (S0 >= n) return;
+  const uint32_t S1 = (uint32_t)min((uint64_t)n, S0 + kSortChunk);
+  const uint32_t cnt = S1 - (uint32_t)S0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int v = threadIdx.x; v < n_views; v += B) s_view[v] = make_int2(views[v].tile_base - tile_begin, views[v].tiles_x);
+  const uint32_t digit_base = hist_scanned[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+  __syncthreads();
+  emit_walk(u.walk, sorted_vis, koff, firsts, *nvis_p, all_keys, sorted_rect, s_view, (uint32_t)n_gauss, S0, S1,
+            [&](uint32_t slot, uint32_t key, uint32_t val) {
+              s_key[slot - (uint32_t)S0] = key;
+              s_val[slot - (uint32_t)S0] = val;
+            });
+  __syncthreads();
+  uint32_t key[kWaveRounds], val[kWaveRounds];
+  uint32_t in_mask = 0;
+  const uint32_t lane0 = (uint32_t)w * kWaveKeys + (uint32_t)lane;
 #pragma unroll
-  for (int q = 0; q < NW; ++q) t += h[q][threadIdx.x];
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = t;
+  for (int r = 0; r < kWaveRounds; ++r) {
+    const uint32_t li = lane0 + (uint32_t)r * 64u;
+    const bool in = li < cnt;
+    key[r] = in ? s_key[li] : 0u;
+    val[r] = in ? s_val[li] : 0u;
+    in_mask |= in ? 1u << r : 0u;
+  }
+#pragma unroll
+  for (int q = 0; q < NW; ++q) u.rank.wc[q][threadIdx.x] = 0;
+  // the ranking places keys into the same LDS space
+  __syncthreads();
+  uint32_t pos[kWaveRounds];
+  uint32_t dst[1];
+  rank_and_write<false, true>(key, val, in_mask, digit_base, 0, dmask0, s_key, s_val, u.rank.wc, u.rank.gbase,
+                              u.rank.tmp, u.rank.taken, kout, vout, pos, dst, n);
 }
 
 __global__ void k_key_total(Counters* c, const uint32_t* total_keys, uint32_t cap) {
@@ -756,12 +920,11 @@ struct DenseSrc {
 // returns through *in_b whether the result landed in the second buffer.  With `dense`,
 // the first pass reads the dense source instead of (ka, va, pa) and writes
 // the taken keys to (ka, va, pa), and the later passes sort *dense->taken of
-// them (dcount must then be dense->taken).  With first_hist_ready, the
-// kernel that wrote the keys has already stored the first pass's digit
-// counts in the histogram buffer.
+// them (dcount must then be dense->taken).  With first_done, the caller has
+// already performed the first pass into (kb, vb, pb).
 static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
                              uint2* pa, uint2* pb, int64_t max_count, const uint32_t* dcount, int bits, bool* in_b,
-                             hipStream_t st, const DenseSrc* dense = nullptr, bool first_hist_ready = false,
+                             hipStream_t st, const DenseSrc* dense = nullptr, bool first_done = false,
                              int first_bits = 8) {
   const int64_t nb = cdiv(max_count, kSortChunk);
   uint32_t* hist = seg<uint32_t>(ws, pl.ws.hist);
@@ -779,11 +942,14 @@ static hipError_t radix_sort(const Plan& pl, void* ws, uint32_t* ka, uint32_t* v
     uint32_t* ko = out_b ? kb : ka;
     uint32_t* vo = out_b ? vb : va;
     uint2* po = out_b ? pb : pa;
+    if (first_done && shift == 0) {
+      cur_b = true;
+      continue;
+    }
     if (nb > 0) {
       const uint32_t* dc = from_dense ? nullptr : dcount;
-      if (!(first_hist_ready && shift == 0))
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(B), 0, st, ki,
-                         from_dense ? dense->valid : nullptr, max_count, dc, shift, dmask, nb, hist);
+      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(B), 0, st, ki, from_dense ? dense->valid : nullptr,
+                         max_count, dc, shift, dmask, nb, hist);
       // a dense pass's digit counts total the taken keys
       hipError_t e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * nb, nullptr, partial, pl.ws.partial_len,
                               from_dense ? dense->taken : nullptr, st);
@@ -854,8 +1020,8 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   if (e != hipSuccess) return e;
   // ctr->keys holds the total; record it and the overflow flag
   hipLaunchKernelGGL(k_key_total, dim3(1), dim3(64), 0, st, ctr, &ctr->keys, cap);
-  // 4. emit (tile, value) pairs in depth order, one sort chunk per
-  // workgroup, with the digit counts of the tile sort's first pass
+  // 4. digit counts of the tile sort's first pass over the (tile, value)
+  // pairs in depth order, one sort chunk per workgroup, and their scan
   const int32_t tile_begin = pl.views[v0].tile_base;
   const int32_t tile_end = (v0 + nv < pl.n_views) ? pl.views[v0 + nv].tile_base : pl.total_tiles;
   // tile bits of the call, split into passes of 8 bits with the remainder
@@ -865,10 +1031,18 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   while ((1ll << bits) < ntiles) ++bits;
   if (bits == 0) bits = 1;
   const int first_bits = bits - 8 * ((bits - 1) / 8);
-  hipLaunchKernelGGL(k_emit_chunk, dim3((unsigned)key_chunks), dim3(B), 0, st, sorted_vis, koff, firsts, &ctr->nvis,
-                     &ctr->keys, reinterpret_cast<const ushort4*>(sorted_rect), pl.d_views, pl.n_views, N, tile_begin,
-                     cap, key_chunks, (1u << first_bits) - 1u, keys_a, vals_a, seg<uint32_t>(ws, pl.ws.hist));
-  // 5. stable sort by tile (relative to the first tile of the call)
+  uint32_t* hist = seg<uint32_t>(ws, pl.ws.hist);
+  const ushort4* srect4 = reinterpret_cast<const ushort4*>(sorted_rect);
+  const uint32_t dmask0 = (1u << first_bits) - 1u;
+  hipLaunchKernelGGL(k_emit_count, dim3((unsigned)key_chunks), dim3(B), 0, st, sorted_vis, koff, firsts, &ctr->nvis,
+                     &ctr->keys, srect4, pl.d_views, pl.n_views, N, tile_begin, cap, key_chunks, dmask0, hist);
+  e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * key_chunks, nullptr, partial, pl.ws.partial_len, nullptr, st);
+  if (e != hipSuccess) return e;
+  // 5. stable sort by tile (relative to the first tile of the call): its
+  // first pass fused with the emission, into the second buffers
+  hipLaunchKernelGGL(k_emit_scatter, dim3((unsigned)key_chunks), dim3(B), 0, st, sorted_vis, koff, firsts, &ctr->nvis,
+                     &ctr->keys, srect4, pl.d_views, pl.n_views, N, tile_begin, cap, key_chunks, dmask0, hist, keys_b,
+                     vals_b);
   e = radix_sort(pl, ws, keys_a, vals_a, keys_b, vals_b, nullptr, nullptr, pl.cap, &ctr->keys, bits, &in_b, st, nullptr,
                  true, first_bits);
   if (e != hipSuccess) return e;
