@@ -534,11 +534,32 @@ __device__ __forceinline__ int wave_incl_max(int v) {
   return v;
 }
 
+// One lane's pair of a group of 64 depth-sorted visible pairs: first and
+// end key slot, (view, Gaussian) index and tile rectangle as two words
+// (x0 | y0 << 16, x1 | y1 << 16); past the last pair, off is 0xffffffff and
+// the rest zero.
+struct PairIn {
+  uint32_t off, end, vi;
+  uint2 r;
+};
+
+__device__ __forceinline__ PairIn load_pair(const uint32_t* koff, const uint32_t* sorted_vis, const uint2* sorted_rect,
+                                            uint32_t k, uint32_t nvis, uint32_t all_keys) {
+  PairIn p{0xffffffffu, 0u, 0u, make_uint2(0u, 0u)};
+  if (k < nvis) {
+    p.off = koff[k];
+    p.end = k + 1 < nvis ? koff[k + 1] : all_keys;
+    p.vi = sorted_vis[k];
+    p.r = sorted_rect[k];
+  }
+  return p;
+}
+
 // Per-wavefront staging of the walk: the current group of 64 pairs.
 struct WalkLds {
   uint32_t off[NW][64];    // first key slot
   uint32_t vi[NW][64];     // (view, Gaussian) index
-  ushort4 rect[NW][64];    // tile rectangle
+  uint2 rect[NW][64];      // tile rectangle, as loaded
   uint32_t view[NW][64];
   int32_t mark[NW][64];
 };
@@ -550,47 +571,46 @@ struct WalkLds {
 template <class Emit>
 __device__ __forceinline__ void emit_walk(WalkLds& L, const uint32_t* sorted_vis, const uint32_t* koff,
                                           const uint32_t* firsts, uint32_t nvis, uint32_t all_keys,
-                                          const ushort4* sorted_rect, const int2* s_view, uint32_t ng, uint64_t S0,
+                                          const uint2* sorted_rect, const int2* s_view, uint32_t ng, uint64_t S0,
                                           uint32_t S1, Emit emit) {
   uint32_t (&s_off)[NW][64] = L.off;
   uint32_t (&s_vi)[NW][64] = L.vi;
-  ushort4 (&s_rect)[NW][64] = L.rect;
+  uint2 (&s_rect)[NW][64] = L.rect;
   uint32_t (&s_v)[NW][64] = L.view;
   int32_t (&s_mark)[NW][64] = L.mark;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const float inv_ng = 1.f / (float)ng;
-  for (uint32_t g = firsts[blockIdx.x] + (uint32_t)w * 64u; g < nvis; g += NW * 64u) {
-    const uint32_t k = g + (uint32_t)lane;
-    const bool valid = k < nvis;
-    // the group's loads go out together; the test whether the group starts
-    // past the chunk waits for them
-    uint32_t off = 0xffffffffu, end = 0, vi = 0;
-    ushort4 r = make_ushort4(0, 0, 0, 0);
-    if (valid) {
-      off = koff[k];
-      end = k + 1 < nvis ? koff[k + 1] : all_keys;
-      vi = sorted_vis[k];
-      r = sorted_rect[k];
-    }
-    if ((uint32_t)__builtin_amdgcn_readfirstlane((int)off) >= S1) break;   // the group starts past the chunk
-    if (valid) {
-      // view = vi / n_gauss: a float estimate (off by at most one, as the
-      // quotient is below 2^8) corrected to the exact integer quotient
-      uint32_t v = (uint32_t)((float)vi * inv_ng);
-      const uint64_t lo = (uint64_t)v * ng;
-      if (lo > vi) v -= 1u;
-      else if (lo + ng <= vi) v += 1u;
-      s_vi[w][lane] = vi;
-      s_rect[w][lane] = r;
-      s_v[w][lane] = v;
-    }
+  // the wavefront takes every NW-th group of 64 pairs; each group's loads go
+  // out together, and before the group in hand is worked through, so that
+  // they are in flight meanwhile
+  uint32_t g = firsts[blockIdx.x] + (uint32_t)w * 64u;
+  PairIn nxt = load_pair(koff, sorted_vis, sorted_rect, g + (uint32_t)lane, nvis, all_keys);
+  for (; g < nvis; g += NW * 64u) {
+    const PairIn cur = nxt;
+    if ((uint32_t)__builtin_amdgcn_readfirstlane((int)cur.off) >= S1) break;   // the group starts past the chunk
+    const bool valid = g + (uint32_t)lane < nvis;
+    const uint32_t off = cur.off, vi = cur.vi;
+    // view = vi / n_gauss: a float estimate (off by at most one, as the
+    // quotient is below 2^8) corrected to the exact integer quotient (lanes
+    // past the last pair stage zeros, which no slot refers to)
+    uint32_t v = (uint32_t)((float)vi * inv_ng);
+    const uint64_t lv = (uint64_t)v * ng;
+    if (lv > vi) v -= 1u;
+    else if (lv + ng <= vi) v += 1u;
+    s_vi[w][lane] = vi;
+    s_rect[w][lane] = cur.r;
+    s_v[w][lane] = v;
     s_off[w][lane] = off;
-    __builtin_amdgcn_wave_barrier();
-    const uint32_t start = max(s_off[w][0], (uint32_t)S0);
-    uint32_t stop = end;
+    uint32_t stop = cur.end;
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) stop = max(stop, (uint32_t)__shfl_xor((int)stop, d, 64));
     stop = min(stop, S1);
+    // every use of this group's loads is above, so the next group's loads
+    // stay in flight while the group is worked through
+    __builtin_amdgcn_sched_barrier(0);
+    nxt = load_pair(koff, sorted_vis, sorted_rect, g + NW * 64u + (uint32_t)lane, nvis, all_keys);
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t start = max(s_off[w][0], (uint32_t)S0);
     // the last pair of the group that began at or before `start`
     int carry = (int)__popcll(__ballot(valid && off <= start)) - 1;
     for (uint32_t S = start; S < stop; S += 64) {
@@ -603,9 +623,10 @@ __device__ __forceinline__ void emit_walk(WalkLds& L, const uint32_t* sorted_vis
       __builtin_amdgcn_wave_barrier();
       const uint32_t slot = S + (uint32_t)lane;
       if (slot < stop) {
-        const ushort4 r = s_rect[w][own];
+        const uint2 rr = s_rect[w][own];
+        const uint32_t rx = rr.x & 0xffffu, ry = rr.x >> 16;
         const uint32_t m = slot - s_off[w][own];
-        const uint32_t width = (uint32_t)r.z - r.x + 1u;
+        const uint32_t width = (rr.y & 0xffffu) - rx + 1u;
         uint32_t q = (uint32_t)((float)m * __builtin_amdgcn_rcpf((float)width));
         int32_t rem = (int32_t)(m - q * width);
         if (rem < 0) {
@@ -615,7 +636,7 @@ __device__ __forceinline__ void emit_walk(WalkLds& L, const uint32_t* sorted_vis
           q += 1u;
           rem -= (int32_t)width;
         }
-        const uint32_t ty = r.y + q, tx = r.x + (uint32_t)rem;
+        const uint32_t ty = ry + q, tx = rx + (uint32_t)rem;
         const int2 vw = s_view[s_v[w][own]];
         const uint32_t key = (uint32_t)(vw.x + (int32_t)(ty * (uint32_t)vw.y + tx));
         emit(slot, key, s_vi[w][own]);
@@ -635,7 +656,7 @@ __device__ __forceinline__ void emit_walk(WalkLds& L, const uint32_t* sorted_vis
 // difference array, whose prefix sums are the counts.
 __global__ __launch_bounds__(B) void k_emit_count(const uint32_t* sorted_vis, const uint32_t* koff,
                                                   const uint32_t* firsts, const uint32_t* nvis_p,
-                                                  const uint32_t* total_keys, const ushort4* sorted_rect,
+                                                  const uint32_t* total_keys, const uint2* sorted_rect,
                                                   const ViewInfo* views, int32_t n_views, int64_t n_gauss,
                                                   int32_t tile_begin, uint32_t cap, int64_t nblocks, uint32_t dmask0,
                                                   uint32_t* hist) {
@@ -661,33 +682,41 @@ __global__ __launch_bounds__(B) void k_emit_count(const uint32_t* sorted_vis, co
     const uint32_t nvis = *nvis_p;
     const uint32_t ng = (uint32_t)n_gauss;
     const float inv_ng = 1.f / (float)ng;
-    for (uint32_t g = firsts[blockIdx.x] + (uint32_t)w * 64u; g < nvis; g += NW * 64u) {
-      const uint32_t k = g + (uint32_t)lane;
-      const bool valid = k < nvis;
-      uint32_t off = 0xffffffffu, end = 0, vi = 0;
-      ushort4 r = make_ushort4(0, 0, 0, 0);
-      if (valid) {
-        off = koff[k];
-        end = k + 1 < nvis ? koff[k + 1] : all_keys;
-        vi = sorted_vis[k];
-        r = sorted_rect[k];
-      }
-      if ((uint32_t)__builtin_amdgcn_readfirstlane((int)off) >= S1) break;   // the group starts past the chunk
-      const uint32_t lo = max(off, (uint32_t)S0), hi = min(end, S1);
+    // groups of 64 pairs as in the walk, the next group's loads issued
+    // before the group in hand is counted
+    uint32_t g = firsts[blockIdx.x] + (uint32_t)w * 64u;
+    PairIn nxt = load_pair(koff, sorted_vis, sorted_rect, g + (uint32_t)lane, nvis, all_keys);
+    for (; g < nvis; g += NW * 64u) {
+      const PairIn cur = nxt;
+      if ((uint32_t)__builtin_amdgcn_readfirstlane((int)cur.off) >= S1) break;   // the group starts past the chunk
+      const bool valid = g + (uint32_t)lane < nvis;
+      const uint32_t off = cur.off, vi = cur.vi;
+      const uint32_t lo = max(off, (uint32_t)S0), hi = min(cur.end, S1);
+      // everything taken from this group's loads, for every lane (lanes past
+      // the last pair or outside the chunk compute values they never use)
+      uint32_t v = (uint32_t)((float)vi * inv_ng);   // vi / n_gauss, corrected as in the walk
+      const uint64_t lv = (uint64_t)v * ng;
+      if (lv > vi) v -= 1u;
+      else if (lv + ng <= vi) v += 1u;
+      const int2 vw = s_view[v];
+      // the rectangle's words pass through an empty asm statement here, so
+      // that the compiler does not narrow the next group's rectangle load
+      // right where it is issued (which would make the wavefront wait for it)
+      uint32_t rw0 = cur.r.x, rw1 = cur.r.y;
+      asm volatile("" : "+v"(rw0), "+v"(rw1));
+      const uint32_t rx = rw0 & 0xffffu, ry = rw0 >> 16;
+      const uint32_t width = (rw1 & 0xffffu) - rx + 1u;
+      const uint32_t m0 = lo - off, m1 = hi - off;   // the pair's slots in the chunk, [m0, m1)
+      const uint32_t q0 = m0 / width, c0 = m0 - q0 * width;
+      const uint32_t q1 = (m1 - 1u) / width, c1 = (m1 - 1u) - q1 * width;
+      // so the next group's loads stay in flight while this one is counted
+      __builtin_amdgcn_sched_barrier(0);
+      nxt = load_pair(koff, sorted_vis, sorted_rect, g + NW * 64u + (uint32_t)lane, nvis, all_keys);
       if (valid && lo < hi) {
-        uint32_t v = (uint32_t)((float)vi * inv_ng);   // vi / n_gauss, corrected as in the walk
-        const uint64_t lv = (uint64_t)v * ng;
-        if (lv > vi) v -= 1u;
-        else if (lv + ng <= vi) v += 1u;
-        const int2 vw = s_view[v];
-        const uint32_t width = (uint32_t)r.z - r.x + 1u;
-        const uint32_t m0 = lo - off, m1 = hi - off;   // the pair's slots in the chunk, [m0, m1)
-        const uint32_t q0 = m0 / width, c0 = m0 - q0 * width;
-        const uint32_t q1 = (m1 - 1u) / width, c1 = (m1 - 1u) - q1 * width;
         uint32_t full = 0;
         for (uint32_t q = q0; q <= q1; ++q) {
           const uint32_t cs = q == q0 ? c0 : 0u, ce = q == q1 ? c1 : width - 1u;
-          const uint32_t a = (uint32_t)(vw.x + (int32_t)(((uint32_t)r.y + q) * (uint32_t)vw.y + r.x + cs));
+          const uint32_t a = (uint32_t)(vw.x + (int32_t)((ry + q) * (uint32_t)vw.y + rx + cs));
           const uint32_t len = ce - cs + 1u;
           full += len >> bits0;
           const uint32_t rem = len & dmask0;
@@ -724,7 +753,7 @@ __global__ __launch_bounds__(B) void k_emit_count(const uint32_t* sorted_vis, co
 // emitting and sorting in separate kernels.
 __global__ __launch_bounds__(B) void k_emit_scatter(const uint32_t* sorted_vis, const uint32_t* koff,
                                                     const uint32_t* firsts, const uint32_t* nvis_p,
-                                                    const uint32_t* total_keys, const ushort4* sorted_rect,
+                                                    const uint32_t* total_keys, const uint2* sorted_rect,
                                                     const ViewInfo* views, int32_t n_views, int64_t n_gauss,
                                                     int32_t tile_begin, uint32_t cap, int64_t nblocks, uint32_t dmask0,
                                                     const uint32_t* hist_scanned, uint32_t* kout, uint32_t* vout) {
@@ -1032,16 +1061,15 @@ hipError_t launch_tile_lists(const Plan& pl, int v0, int nv, void* ws, hipStream
   if (bits == 0) bits = 1;
   const int first_bits = bits - 8 * ((bits - 1) / 8);
   uint32_t* hist = seg<uint32_t>(ws, pl.ws.hist);
-  const ushort4* srect4 = reinterpret_cast<const ushort4*>(sorted_rect);
   const uint32_t dmask0 = (1u << first_bits) - 1u;
   hipLaunchKernelGGL(k_emit_count, dim3((unsigned)key_chunks), dim3(B), 0, st, sorted_vis, koff, firsts, &ctr->nvis,
-                     &ctr->keys, srect4, pl.d_views, pl.n_views, N, tile_begin, cap, key_chunks, dmask0, hist);
+                     &ctr->keys, sorted_rect, pl.d_views, pl.n_views, N, tile_begin, cap, key_chunks, dmask0, hist);
   e = scan_src(ScanSrc{hist, nullptr, 0}, hist, 256 * key_chunks, nullptr, partial, pl.ws.partial_len, nullptr, st);
   if (e != hipSuccess) return e;
   // 5. stable sort by tile (relative to the first tile of the call): its
   // first pass fused with the emission, into the second buffers
   hipLaunchKernelGGL(k_emit_scatter, dim3((unsigned)key_chunks), dim3(B), 0, st, sorted_vis, koff, firsts, &ctr->nvis,
-                     &ctr->keys, srect4, pl.d_views, pl.n_views, N, tile_begin, cap, key_chunks, dmask0, hist, keys_b,
+                     &ctr->keys, sorted_rect, pl.d_views, pl.n_views, N, tile_begin, cap, key_chunks, dmask0, hist, keys_b,
                      vals_b);
   e = radix_sort(pl, ws, keys_a, vals_a, keys_b, vals_b, nullptr, nullptr, pl.cap, &ctr->keys, bits, &in_b, st, nullptr,
                  true, first_bits);
