@@ -89,6 +89,28 @@ def test_tile_lists_with_pairs_spanning_sort_chunks_bit_exact(oracle):
     assert np.array_equal(ranges, ranges_o)
 
 
+@pytest.mark.parametrize("sizes", [((192, 160),), ((192, 160), (64, 48))])
+def test_tile_lists_with_narrow_first_digit_bit_exact(oracle, sizes):
+    # 480 (9 bits) or 528 (10 bits) tiles at 8x8: the tile sort's first pass
+    # takes 1 or 2 bits, so the digit counts of the emission see tile rows
+    # that wrap the digit range many times, and large Gaussians make pairs
+    # of hundreds of keys that straddle sort chunks
+    w = small(seed=137, n=1500, sizes=sizes)
+    w.scene.log_scale[:, :40] = -0.5
+    r = renderer_for(w, tile=(8, 8), cap=1 << 20)
+    P = DeviceParams.from_scene(w.scene)
+    r.forward(P)
+    c = r.counters()
+    cnt = seg_np(r, "count", np.uint32)
+    assert cnt.max() >= 100 and c.keys > 2 * 4096
+    vals_o, ranges_o = oracle.tile_lists(w.scene, w.cams, 8, 8)
+    assert c.overflow == 0 and c.keys == len(vals_o)
+    vals = seg_np(r, "sorted_values", np.uint32)[:c.keys]
+    assert np.array_equal(vals, vals_o)
+    ranges = seg_np(r, "ranges", np.uint32).reshape(-1, 2)
+    assert np.array_equal(ranges, ranges_o)
+
+
 @pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.3, 0.5, 0.1)])
 def test_composite_matches_oracle(oracle, bg):
     w = small(seed=103)
