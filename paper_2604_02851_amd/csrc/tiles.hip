@@ -827,23 +827,37 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys, const uint
   const uint32_t n = min(*count_p, cap);
   const uint32_t nq = (n + 3u) / 4u;
   const bool aligned = (reinterpret_cast<uintptr_t>(keys) & 15u) == 0;
-  for (uint32_t qd = blockIdx.x * blockDim.x + threadIdx.x; qd < nq; qd += gridDim.x * blockDim.x) {
+  const uint32_t lane = threadIdx.x & 63u;
+  // whole wavefronts go round the loop together (lanes past the last quad
+  // hold kNone), so that each quad's outer neighbours, the last key of the
+  // quad before and the first of the quad after, come from the lanes beside
+  // it
+  for (uint32_t qb = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); qb < nq; qb += gridDim.x * blockDim.x) {
+    const uint32_t qd = qb + lane;
+    const bool here = qd < nq;
     const uint32_t k0 = qd * 4u;
     uint32_t t[6];
-    if (aligned && k0 + 4u <= n) {
+    if (here && aligned && k0 + 4u <= n) {
       typedef uint32_t U4 __attribute__((ext_vector_type(4)));
       const U4 x = __builtin_nontemporal_load(reinterpret_cast<const U4*>(keys + k0));
       t[1] = x.x, t[2] = x.y, t[3] = x.z, t[4] = x.w;
     } else {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) t[1 + c] = k0 + c < n ? keys[k0 + c] : kNone;
+      for (int c = 0; c < 4; ++c) t[1 + c] = here && k0 + c < n ? keys[k0 + c] : kNone;
     }
-    t[0] = k0 > 0u ? keys[k0 - 1u] : kNone;
-    t[5] = k0 + 4u < n ? keys[k0 + 4u] : kNone;
+    // lane 0's key before its quad and lane 63's key after it, in flight
+    // together with the quads
+    uint32_t before = kNone, after = kNone;
+    if (lane == 0u && here && k0 > 0u) before = keys[k0 - 1u];
+    if (lane == 63u && here && k0 + 4u < n) after = keys[k0 + 4u];
+    t[0] = (uint32_t)__shfl_up((int)t[4], 1, 64);
+    t[5] = (uint32_t)__shfl_down((int)t[1], 1, 64);
+    if (lane == 0u) t[0] = before;
+    if (lane == 63u) t[5] = after;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const uint32_t k = k0 + c;
-      if (k < n) {
+      if (here && k < n) {
         if (t[c] != t[c + 1]) ranges[tile_begin + t[c + 1]].x = k;
         if (t[c + 2] != t[c + 1]) ranges[tile_begin + t[c + 1]].y = k + 1u;
       }
